@@ -1,0 +1,190 @@
+"""FP64 CPU oracle for the SRB sampling planner -- TEST INFRASTRUCTURE ONLY.
+
+This package is the correctness reference that the GPU library is checked
+against. Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline
+leg of ``bench.py`` may import it; the product path (the
+``paper_2603_20525_amd`` package and its C library) never does, and it shares
+no code with it. The arithmetic lives in ``srb_oracle.c`` (plain C, double
+precision); this module only builds it and marshals arguments with ctypes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "srb_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile ``srb_oracle.c`` into ``liboracle.so`` (gcc -O2, no fast-math,
+    OpenMP over candidates)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-fopenmp", "-fPIC", "-shared",
+               "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Vehicle(C.Structure):
+    _fields_ = [(n, C.c_double) for n in (
+        "M", "Jxx", "Jyy", "Jzz", "Lf", "Lr", "e", "hR", "kf", "kr", "bf", "br",
+        "C", "mu", "delta_max", "delta_rate_max", "g")]
+
+
+class Cost(C.Structure):
+    _fields_ = [(n, C.c_double) for n in (
+        "w_t", "w_c", "w_g", "goal_x", "goal_y", "goal_r", "sigma", "eps_esm",
+        "eps_dist")]
+
+
+class Integ(C.Structure):
+    _fields_ = [("dt", C.c_double), ("substeps", C.c_int),
+                ("accel_max", C.c_double), ("vx_min", C.c_double)]
+
+
+class Diag(C.Structure):
+    _fields_ = [
+        ("P", C.c_double * 3 * 4), ("vi", C.c_double * 3 * 4),
+        ("terr", C.c_double * 4 * 4),
+        ("chi", C.c_double * 4), ("chidot", C.c_double * 4),
+        ("Fk", C.c_double * 4), ("Fb", C.c_double * 4), ("Fz", C.c_double * 4),
+        ("Fy", C.c_double * 4), ("alpha", C.c_double * 4),
+        ("f", C.c_double * 3 * 4),
+        ("Fy_sum", C.c_double), ("Fz_sum", C.c_double), ("Mx", C.c_double),
+        ("My", C.c_double), ("Mz", C.c_double), ("c_sum", C.c_double),
+        ("U_esm", C.c_double), ("L", C.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = np.ctypeslib.as_array(v).copy() if hasattr(v, "_length_") else float(v)
+        return out
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = C.CDLL(_LIB)
+        dp, fp, ip, vp = (C.POINTER(C.c_double), C.POINTER(C.c_float),
+                          C.POINTER(C.c_int), C.c_void_p)
+        L.oracle_create.restype = vp
+        L.oracle_create.argtypes = [C.POINTER(Vehicle), C.POINTER(Cost), C.POINTER(Integ)]
+        L.oracle_destroy.argtypes = [vp]
+        L.oracle_set_terrain.argtypes = [vp, fp, C.c_int, C.c_int, C.c_double,
+                                         C.c_double, C.c_double, fp]
+        L.oracle_sample_terrain.argtypes = [vp, C.c_double, C.c_double, dp]
+        L.oracle_rhs.argtypes = [vp, dp, C.c_double, C.c_double, dp, C.POINTER(Diag)]
+        L.oracle_esm.restype = C.c_double
+        L.oracle_esm.argtypes = [vp, C.c_double, C.c_double]
+        L.oracle_soft.restype = C.c_double
+        L.oracle_soft.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.oracle_rollout.argtypes = [vp, fp, fp, C.c_int, C.c_int, dp, dp, ip]
+        L.oracle_select.argtypes = [vp, C.c_int, C.c_double, fp, fp, C.c_int,
+                                    C.c_int, ip, dp, dp]
+        _lib = L
+    return _lib
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+def soft(sigma: float, eps: float, pi: float) -> float:
+    return lib().oracle_soft(sigma, eps, pi)
+
+
+class Oracle:
+    """One oracle context: parameters plus (after ``set_terrain``) a terrain."""
+
+    def __init__(self, vehicle: dict, cost: dict, integ: dict):
+        self._veh = Vehicle(**{k: float(vehicle[k]) for k, _ in Vehicle._fields_})
+        self._cost = Cost(**{k: float(cost.get(k, 0.0)) for k, _ in Cost._fields_})
+        self._integ = Integ(dt=float(integ["dt"]), substeps=int(integ["substeps"]),
+                            accel_max=float(integ["accel_max"]),
+                            vx_min=float(integ["vx_min"]))
+        self._h = lib().oracle_create(C.byref(self._veh), C.byref(self._cost),
+                                      C.byref(self._integ))
+        if not self._h:
+            raise ValueError("oracle_create rejected the parameters")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.oracle_destroy(h)
+            self._h = None
+
+    def set_terrain(self, height, x0, y0, res, costmap=None):
+        h = _f32(height)
+        H, W = h.shape
+        c = None if costmap is None else _f32(costmap)
+        self._keep = (h, c)
+        rc = lib().oracle_set_terrain(self._h, _ptr(h, C.c_float), W, H, x0, y0, res,
+                                      None if c is None else _ptr(c, C.c_float))
+        if rc != 0:
+            raise ValueError("oracle_set_terrain rejected the terrain")
+
+    def sample(self, x, y):
+        out = np.zeros(4)
+        lib().oracle_sample_terrain(self._h, float(x), float(y), _ptr(out, C.c_double))
+        return out
+
+    def rhs(self, xi, delta_dot, vx_dot):
+        xi = np.ascontiguousarray(xi, dtype=np.float64)
+        out = np.zeros(13)
+        d = Diag()
+        rc = lib().oracle_rhs(self._h, _ptr(xi, C.c_double), float(delta_dot),
+                              float(vx_dot), _ptr(out, C.c_double), C.byref(d))
+        if rc != 0:
+            raise RuntimeError("oracle_rhs failed (no terrain?)")
+        return out, d.as_dict()
+
+    def esm(self, phi, theta):
+        return lib().oracle_esm(self._h, float(phi), float(theta))
+
+    def rollout(self, state0, controls):
+        """controls: [N][2][K] float32. Returns (cost[K], final_state[13][K], exit_step[K])."""
+        s0 = _f32(state0)
+        u = _f32(controls)
+        N, two, K = u.shape
+        assert two == 2 and s0.shape == (13,)
+        cost = np.zeros(K)
+        fs = np.zeros((13, K))
+        ex = np.zeros(K, dtype=np.int32)
+        rc = lib().oracle_rollout(self._h, _ptr(s0, C.c_float), _ptr(u, C.c_float), K, N,
+                                  _ptr(cost, C.c_double), _ptr(fs, C.c_double),
+                                  _ptr(ex, C.c_int))
+        if rc != 0:
+            raise RuntimeError(f"oracle_rollout failed ({rc})")
+        return cost, fs, ex
+
+    def select(self, controls, cost, mode=0, lam=0.0):
+        u = _f32(controls)
+        N, _, K = u.shape
+        J = _f32(cost)
+        bk = C.c_int(0)
+        bc = C.c_double(0)
+        plan = np.zeros((N, 2))
+        rc = lib().oracle_select(self._h, int(mode), float(lam), _ptr(u, C.c_float),
+                                 _ptr(J, C.c_float), K, N, C.byref(bk), C.byref(bc),
+                                 _ptr(plan, C.c_double))
+        if rc != 0:
+            raise ValueError("oracle_select rejected the arguments")
+        return bk.value, bc.value, plan

@@ -1,0 +1,120 @@
+/*
+ * FP64 CPU oracle for the single-rigid-body (SRB) sampling planner.
+ *
+ * TEST INFRASTRUCTURE ONLY. This library is the correctness reference that the
+ * GPU path is checked against. Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it; the product path never does.
+ * It shares no source, header, table or helper with the GPU library.
+ *
+ * What it computes (paper: "Proposed MPC Formulation" and "Real-Time
+ * Implementation"): for K given candidate control sequences, the forward-Euler
+ * rollout of the SRB model over a gridded heightmap, the running cost with the
+ * energy-stability-margin (ESM) soft constraint and the costmap term, the
+ * terminal distance cost, and the selection over candidates (empirical argmin,
+ * or the MPPI-style weighted average).
+ *
+ * All internal arithmetic is double precision. Inputs that the GPU path also
+ * receives (heights, costmap, controls, initial state) are taken as float
+ * arrays and promoted, so both sides start from identical bits.
+ */
+#ifndef SRB_ORACLE_H
+#define SRB_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Vehicle parameters (paper, appendix "Vehicle Model Parameters", tables
+ * of model and tire parameters; notation table). hR is h+R. */
+typedef struct {
+    double M, Jxx, Jyy, Jzz;
+    double Lf, Lr, e, hR;
+    double kf, kr, bf, br;
+    double C, mu;
+    double delta_max, delta_rate_max;
+    double g;
+} oracle_vehicle;
+
+/* Cost parameters (paper, "OCP Formulation": running/terminal cost, soft
+ * constraints, goal radius). eps_esm <= 0 selects the default: 10 % of the
+ * ESM on level ground. */
+typedef struct {
+    double w_t, w_c, w_g;
+    double goal_x, goal_y, goal_r;
+    double sigma, eps_esm, eps_dist;
+} oracle_cost;
+
+/* Integration: dt is the zero-order-hold period of one control, substeps is
+ * the number of Euler steps per control (h = dt/substeps), accel_max maps the
+ * normalised throttle channel to the prescribed longitudinal acceleration,
+ * vx_min is the floor kept on the CoM longitudinal speed. */
+typedef struct {
+    double dt;
+    int substeps;
+    double accel_max, vx_min;
+} oracle_integ;
+
+/* Per-wheel diagnostic of one right-hand-side evaluation (wheel order
+ * fl, fr, rl, rr). f is the force on the chassis at the wheel, in the body
+ * frame: (F_x, F_y cos(delta_i), F_z). vi is the contact-point velocity in
+ * the body frame. */
+typedef struct {
+    double P[4][3];
+    double vi[4][3];
+    double terr[4][4];  /* h, f_x, f_y, c at the wheel */
+    double chi[4], chidot[4];
+    double Fk[4], Fb[4], Fz[4], Fy[4], alpha[4];
+    double f[4][3];
+    double Fy_sum, Fz_sum, Mx, My, Mz, c_sum;
+    double U_esm, L;    /* ESM and running cost at this state/control */
+} oracle_diag;
+
+typedef struct oracle_ctx oracle_ctx;
+
+/* Returns NULL on invalid parameters. */
+oracle_ctx *oracle_create(const oracle_vehicle *veh, const oracle_cost *cost,
+                          const oracle_integ *integ);
+void oracle_destroy(oracle_ctx *o);
+
+/* Heights [H][W] (node (i,j) at (x0+i*res, y0+j*res), stored row j),
+ * optional costmap [H][W] in cost units per second (NULL = zeros).
+ * Returns 0, or -1 on invalid arguments. */
+int oracle_set_terrain(oracle_ctx *o, const float *height, int W, int H,
+                       double x0, double y0, double res, const float *costmap);
+
+/* Bilinear sample of (h, f_x, f_y, c) at (x, y); clamp-to-edge. */
+int oracle_sample_terrain(const oracle_ctx *o, double x, double y, double out[4]);
+
+/* State derivative for state xi[13] and applied control (delta_dot, vx_dot),
+ * with optional diagnostics. Returns 0, or -1 if no terrain is set. */
+int oracle_rhs(const oracle_ctx *o, const double xi[13], double delta_dot,
+               double vx_dot, double xidot[13], oracle_diag *diag);
+
+/* ESM at roll phi and pitch theta. */
+double oracle_esm(const oracle_ctx *o, double phi, double theta);
+
+/* Normalised quadratic soft-constraint cost rate for violation measure pi. */
+double oracle_soft(double sigma, double eps, double pi);
+
+/* Rollout of K candidates. controls is [N][2][K] float (channel 0 steering
+ * rate in rad/s, channel 1 normalised throttle). cost[K] and, if non-NULL,
+ * final_state[13][K] are written in double. exit_step[K] (optional) receives
+ * the Euler-node index at which the goal test fired, or -1.
+ * Returns 0, -1 on invalid arguments, -4 if no terrain is set. */
+int oracle_rollout(const oracle_ctx *o, const float state0[13],
+                   const float *controls, int K, int N,
+                   double *cost, double *final_state, int *exit_step);
+
+/* Selection over candidates. mode 0 = argmin, 1 = softmin with temperature
+ * lambda. cost is [K] float (the values being selected over). plan is
+ * [N][2] double: the applied (clamped) controls of the selected candidate, or
+ * their weighted average. best_k = -1 if no candidate is finite.
+ * Returns 0 or -1 on invalid arguments. */
+int oracle_select(const oracle_ctx *o, int mode, double lambda,
+                  const float *controls, const float *cost, int K, int N,
+                  int *best_k, double *best_cost, double *plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

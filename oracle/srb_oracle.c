@@ -1,0 +1,493 @@
+/*
+ * FP64 CPU oracle for the single-rigid-body (SRB) sampling planner.
+ *
+ * TEST INFRASTRUCTURE ONLY: the reference the GPU path is checked against.
+ * Only tests, the smoke check and the benchmark's CPU-baseline leg may load
+ * it. It shares no code with the GPU library.
+ *
+ * Written plainly and sequentially from the paper (arXiv 2603.20525):
+ *   - SRB model: section "Single Rigid Body Vehicle Dynamics Model"
+ *     (state vector, eq. models:6dof:A, rotation matrix
+ *     eq. models:6dof:rotation-matrix, Euler rates eq. models:6dof:euler-rates,
+ *     contact point eq. models:6dof:P, extension eq. models:6dof:chi, suspension
+ *     eq. models:6dof:Fs, slip angle, force and moment sums, rear constraint
+ *     force F_x).
+ *   - Tire: eq. models:tire (sigmoid lateral force).
+ *   - Static loads: eqs. models:3dof:Kzzf, models:3dof:Kzzr.
+ *   - ESM: eqs. esm and models:6dof:esm, with R-bar and phi-bar.
+ *   - Cost: eq. framework:cost, baseline running cost
+ *     eq. formulation:baseline_running_cost, terminal cost, L_soft, pi_ESM.
+ *   - Goal: eq. formulation:goal; horizon and ZOH: section "OCP Formulation".
+ *   - Optimiser: section "Real-Time Implementation" (empirical argmin; MPPI
+ *     weighted average as the lambda > 0 variant; forward Euler).
+ *
+ * Readings where the paper is silent or ambiguous (listed in the design notes):
+ *   - terrain normal taken as (-f_x, -f_y, 1), the upward normal of z=f(x,y);
+ *   - ESM sign: negative once |phi| + phi_bar exceeds pi/2 (CoM past the
+ *     wheel line);
+ *   - eps_ESM default: 10 % of the level-ground ESM;
+ *   - costmap holds the summed distance soft-cost rate; the four wheel
+ *     lookups are added to the running cost;
+ *   - cost quadrature: left Riemann sum at the Euler nodes;
+ *   - goal test at each Euler node before the step, inclusive;
+ *   - steering angle clamped to +-delta_max after each step, CoM speed floored
+ *     at vx_min;
+ *   - node slopes by central differences (one-sided on the border), bilinear
+ *     interpolation of height, slopes and cost, clamp-to-edge queries;
+ *   - slip angle literal atan(v_y/v_x); 0/0 gives alpha = -delta_i;
+ *   - non-finite cost or final state makes the candidate cost +inf; argmin
+ *     ties go to the lowest index.
+ */
+#define _DEFAULT_SOURCE
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+struct oracle_ctx {
+    oracle_vehicle v;
+    oracle_cost c;
+    oracle_integ in;
+    /* terrain, double precision, row j = y index */
+    int W, H;
+    double x0, y0, res;
+    double *th, *tfx, *tfy, *tc;
+    int has_terrain;
+};
+
+static double clampd(double x, double lo, double hi)
+{
+    if (x < lo) return lo;
+    if (x > hi) return hi;
+    return x;
+}
+
+/* ---------------------------------------------------------------- ESM ---- */
+
+/* Eqs. esm and models:6dof:esm: Delta h = R_bar (1 - sin(|phi| + phi_bar)) cos(theta),
+ * R_bar = sqrt((h+R)^2 + (e/2)^2), phi_bar = atan(2(h+R)/e).
+ * U = +M g Delta h while the CoM is inside the footprint, -M g Delta h once it
+ * is outside (|phi| + phi_bar > pi/2 under the rollover-only simplification). */
+double oracle_esm(const oracle_ctx *o, double phi, double theta)
+{
+    const oracle_vehicle *v = &o->v;
+    double Rbar = sqrt(v->hR * v->hR + (v->e / 2.0) * (v->e / 2.0));
+    double phibar = atan(2.0 * v->hR / v->e);
+    double a = fabs(phi) + phibar;
+    double dh = Rbar * (1.0 - sin(a)) * cos(theta);
+    double U = v->M * v->g * dh;
+    if (a > 2.0 * atan(1.0)) U = -U; /* pi/2 */
+    return U;
+}
+
+/* L_soft term for one constraint: sigma * max(0, 1 + pi/eps)^2. */
+double oracle_soft(double sigma, double eps, double pi)
+{
+    double m = fmax(0.0, 1.0 + pi / eps);
+    return sigma * m * m;
+}
+
+/* ------------------------------------------------------------ context ---- */
+
+oracle_ctx *oracle_create(const oracle_vehicle *veh, const oracle_cost *cost,
+                          const oracle_integ *integ)
+{
+    if (!veh || !cost || !integ) return NULL;
+    if (!(veh->M > 0) || !(veh->Jxx > 0) || !(veh->Jyy > 0) || !(veh->Jzz > 0))
+        return NULL;
+    if (!(veh->Lf + veh->Lr > 0) || !(veh->e > 0) || !(veh->hR > 0)) return NULL;
+    if (!(integ->dt > 0) || integ->substeps < 1) return NULL;
+    oracle_ctx *o = (oracle_ctx *)calloc(1, sizeof(oracle_ctx));
+    if (!o) return NULL;
+    o->v = *veh;
+    o->c = *cost;
+    o->in = *integ;
+    if (!(o->c.eps_esm > 0)) {
+        /* 10 % of the ESM on level ground (the soft constraint starts adding
+         * cost at a 10 % safety factor). */
+        o->c.eps_esm = 0.1 * oracle_esm(o, 0.0, 0.0);
+    }
+    return o;
+}
+
+void oracle_destroy(oracle_ctx *o)
+{
+    if (!o) return;
+    free(o->th);
+    free(o->tfx);
+    free(o->tfy);
+    free(o->tc);
+    free(o);
+}
+
+/* ------------------------------------------------------------ terrain ---- */
+
+int oracle_set_terrain(oracle_ctx *o, const float *height, int W, int H,
+                       double x0, double y0, double res, const float *costmap)
+{
+    if (!o || !height || W < 2 || H < 2 || !(res > 0)) return -1;
+    size_t n = (size_t)W * (size_t)H;
+    for (size_t q = 0; q < n; ++q)
+        if (!isfinite((double)height[q]) || (costmap && !isfinite((double)costmap[q])))
+            return -1;
+    free(o->th);
+    free(o->tfx);
+    free(o->tfy);
+    free(o->tc);
+    o->th = (double *)malloc(n * sizeof(double));
+    o->tfx = (double *)malloc(n * sizeof(double));
+    o->tfy = (double *)malloc(n * sizeof(double));
+    o->tc = (double *)malloc(n * sizeof(double));
+    if (!o->th || !o->tfx || !o->tfy || !o->tc) return -1;
+    o->W = W;
+    o->H = H;
+    o->x0 = x0;
+    o->y0 = y0;
+    o->res = res;
+    for (int j = 0; j < H; ++j) {
+        for (int i = 0; i < W; ++i) {
+            size_t q = (size_t)j * W + i;
+            o->th[q] = (double)height[q];
+            o->tc[q] = costmap ? (double)costmap[q] : 0.0;
+        }
+    }
+    /* Numerical first derivatives of the height function (the models only
+     * need f, f_x, f_y; the paper asks for numerical derivatives of a
+     * heightmap): central differences inside, one-sided on the border. */
+    for (int j = 0; j < H; ++j) {
+        for (int i = 0; i < W; ++i) {
+            size_t q = (size_t)j * W + i;
+            double fx, fy;
+            if (i == 0)
+                fx = (o->th[q + 1] - o->th[q]) / res;
+            else if (i == W - 1)
+                fx = (o->th[q] - o->th[q - 1]) / res;
+            else
+                fx = (o->th[q + 1] - o->th[q - 1]) / (2.0 * res);
+            if (j == 0)
+                fy = (o->th[q + W] - o->th[q]) / res;
+            else if (j == H - 1)
+                fy = (o->th[q] - o->th[q - W]) / res;
+            else
+                fy = (o->th[q + W] - o->th[q - W]) / (2.0 * res);
+            o->tfx[q] = fx;
+            o->tfy[q] = fy;
+        }
+    }
+    o->has_terrain = 1;
+    return 0;
+}
+
+/* Bilinear interpolation of the four node fields at (x, y), clamp-to-edge.
+ * A non-finite query returns NaN in every channel. */
+int oracle_sample_terrain(const oracle_ctx *o, double x, double y, double out[4])
+{
+    if (!o || !o->has_terrain) return -1;
+    if (!isfinite(x) || !isfinite(y)) {
+        out[0] = out[1] = out[2] = out[3] = NAN;
+        return 0;
+    }
+    double u = clampd((x - o->x0) / o->res, 0.0, (double)(o->W - 1));
+    double w = clampd((y - o->y0) / o->res, 0.0, (double)(o->H - 1));
+    int i = (int)floor(u);
+    int j = (int)floor(w);
+    if (i > o->W - 2) i = o->W - 2;
+    if (j > o->H - 2) j = o->H - 2;
+    double tx = u - i, ty = w - j;
+    size_t q00 = (size_t)j * o->W + i, q10 = q00 + 1;
+    size_t q01 = q00 + o->W, q11 = q01 + 1;
+    const double *F[4] = {o->th, o->tfx, o->tfy, o->tc};
+    for (int ch = 0; ch < 4; ++ch) {
+        const double *g = F[ch];
+        out[ch] = (1.0 - tx) * (1.0 - ty) * g[q00] + tx * (1.0 - ty) * g[q10] +
+                  (1.0 - tx) * ty * g[q01] + tx * ty * g[q11];
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------- SRB model ---- */
+
+int oracle_rhs(const oracle_ctx *o, const double xi[13], double delta_dot,
+               double vx_dot, double xidot[13], oracle_diag *diag)
+{
+    if (!o || !o->has_terrain) return -1;
+    const oracle_vehicle *V = &o->v;
+
+    /* state vector eq. models:6dof:state */
+    double x = xi[0], y = xi[1], z = xi[2];
+    double psi = xi[3], th = xi[4], ph = xi[5];
+    double vb[3] = {xi[6], xi[7], xi[8]};
+    double w[3] = {xi[9], xi[10], xi[11]};
+    double delta = xi[12];
+
+    /* 3-2-1 rotation matrix W <- B, eq. models:6dof:rotation-matrix */
+    double cps = cos(psi), sps = sin(psi);
+    double cth = cos(th), sth = sin(th);
+    double cph = cos(ph), sph = sin(ph);
+    double R[3][3] = {
+        {cps * cth, cps * sph * sth - cph * sps, sph * sps + cph * cps * sth},
+        {cth * sps, cph * cps + sph * sps * sth, cph * sps * sth - cps * sph},
+        {-sth, cth * sph, cph * cth},
+    };
+
+    /* world-frame CoM velocity */
+    double vw[3];
+    for (int r = 0; r < 3; ++r) vw[r] = R[r][0] * vb[0] + R[r][1] * vb[1] + R[r][2] * vb[2];
+
+    /* Euler-angle rates, eq. models:6dof:euler-rates */
+    double psid = (sph / cth) * w[1] + (cph / cth) * w[2];
+    double thd = cph * w[1] - sph * w[2];
+    double phd = w[0] + (sph * sth / cth) * w[1] + (cph * sth / cth) * w[2];
+
+    /* gravity resolved in the body frame: R^T (0, 0, -g) */
+    double gB[3];
+    for (int cidx = 0; cidx < 3; ++cidx) gB[cidx] = R[2][cidx] * (-V->g);
+
+    /* static loads, eqs. models:3dof:Kzzf / models:3dof:Kzzr */
+    double L = V->Lf + V->Lr;
+    double Kzz_f = V->M * V->Lr / L;
+    double Kzz_r = V->M * V->Lf / L;
+
+    /* wheels fl, fr, rl, rr; body-frame lever arms rho^i */
+    double rho[4][3] = {
+        {V->Lf, V->e / 2.0, -V->hR},
+        {V->Lf, -V->e / 2.0, -V->hR},
+        {-V->Lr, V->e / 2.0, -V->hR},
+        {-V->Lr, -V->e / 2.0, -V->hR},
+    };
+
+    double Fy_sum = 0.0, Fz_sum = 0.0, Msum[3] = {0.0, 0.0, 0.0}, c_sum = 0.0;
+    for (int i = 0; i < 4; ++i) {
+        int front = (i < 2);
+        /* contact point and its velocity, eq. models:6dof:P */
+        double P[3], vi[3];
+        for (int r = 0; r < 3; ++r)
+            P[r] = (r == 0 ? x : (r == 1 ? y : z)) +
+                   R[r][0] * rho[i][0] + R[r][1] * rho[i][1] + R[r][2] * rho[i][2];
+        /* v^i = v + omega x rho^i (body frame) */
+        vi[0] = vb[0] + (w[1] * rho[i][2] - w[2] * rho[i][1]);
+        vi[1] = vb[1] + (w[2] * rho[i][0] - w[0] * rho[i][2]);
+        vi[2] = vb[2] + (w[0] * rho[i][1] - w[1] * rho[i][0]);
+
+        /* terrain height and slope at the nominal contact patch */
+        double T[4];
+        oracle_sample_terrain(o, P[0], P[1], T);
+
+        /* normal to the terrain, world frame (upward normal of z = f(x,y)),
+         * resolved in the body frame */
+        double nW[3] = {-T[1], -T[2], 1.0};
+        double nB[3];
+        for (int cidx = 0; cidx < 3; ++cidx)
+            nB[cidx] = R[0][cidx] * nW[0] + R[1][cidx] * nW[1] + R[2][cidx] * nW[2];
+
+        /* extension and rate, eq. models:6dof:chi; omega x b_z = (w_y, -w_x, 0) */
+        double chi = (P[2] - T[0]) / nB[2];
+        double rel[3] = {vi[0] - chi * w[1], vi[1] + chi * w[0], vi[2]};
+        double chidot = (nB[0] * rel[0] + nB[1] * rel[1] + nB[2] * rel[2]) / nB[2];
+
+        /* suspension with liftoff, eq. models:6dof:Fs */
+        double Kzz = front ? Kzz_f : Kzz_r;
+        double k = front ? V->kf : V->kr;
+        double b = front ? V->bf : V->br;
+        double Fs = (V->g / 2.0) * Kzz;
+        double Fk = fmax(Fs - k * chi, 0.0);
+        double Fb = (Fk > 0.0) ? fmax(-b * chidot, -Fk) : 0.0;
+        double Fz = Fk + Fb;
+
+        /* slip angle and sigmoid tire, eq. models:tire */
+        double delta_i = front ? delta : 0.0;
+        double alpha;
+        if (vi[0] == 0.0 && vi[1] == 0.0)
+            alpha = -delta_i;
+        else
+            alpha = atan(vi[1] / vi[0]) - delta_i;
+        double Ca = V->C * alpha;
+        double Fy = Fz * (-Ca * V->mu) / sqrt(V->mu * V->mu + Ca * Ca);
+
+        /* longitudinal constraint force (rear wheels only) */
+        double Fx = front ? 0.0
+                          : (V->M / 2.0) * (vx_dot - gB[0] + w[1] * vb[2] - w[2] * vb[1]);
+
+        /* force on the chassis at wheel i (body frame) */
+        double f[3] = {Fx, Fy * cos(delta_i), Fz};
+        /* summed forces and moments */
+        Fy_sum += f[1];
+        Fz_sum += f[2];
+        Msum[0] += rho[i][1] * f[2] - rho[i][2] * f[1];
+        Msum[1] += rho[i][2] * f[0] - rho[i][0] * f[2];
+        Msum[2] += rho[i][0] * f[1] - rho[i][1] * f[0];
+        c_sum += T[3];
+
+        if (diag) {
+            for (int r = 0; r < 3; ++r) {
+                diag->P[i][r] = P[r];
+                diag->vi[i][r] = vi[r];
+                diag->f[i][r] = f[r];
+            }
+            for (int ch = 0; ch < 4; ++ch) diag->terr[i][ch] = T[ch];
+            diag->chi[i] = chi;
+            diag->chidot[i] = chidot;
+            diag->Fk[i] = Fk;
+            diag->Fb[i] = Fb;
+            diag->Fz[i] = Fz;
+            diag->Fy[i] = Fy;
+            diag->alpha[i] = alpha;
+        }
+    }
+
+    /* eq. models:6dof:A plus B zeta */
+    xidot[0] = vw[0];
+    xidot[1] = vw[1];
+    xidot[2] = vw[2];
+    xidot[3] = psid;
+    xidot[4] = thd;
+    xidot[5] = phd;
+    xidot[6] = vx_dot;
+    xidot[7] = Fy_sum / V->M + gB[1] + w[0] * vb[2] - w[2] * vb[0];
+    xidot[8] = Fz_sum / V->M + gB[2] - w[0] * vb[1] + w[1] * vb[0];
+    xidot[9] = (Msum[0] + (V->Jyy - V->Jzz) * w[1] * w[2]) / V->Jxx;
+    xidot[10] = (Msum[1] - (V->Jxx - V->Jzz) * w[0] * w[2]) / V->Jyy;
+    xidot[11] = (Msum[2] + (V->Jxx - V->Jyy) * w[0] * w[1]) / V->Jzz;
+    xidot[12] = delta_dot;
+
+    /* ESM constraint and running cost: L = w_t + w_c delta_dot^2 + L_soft,
+     * with pi_ESM = -U_ESM and the costmap (distance) term at the wheels */
+    double U = oracle_esm(o, ph, th);
+    double Lrun = o->c.w_t + o->c.w_c * delta_dot * delta_dot +
+                  oracle_soft(o->c.sigma, o->c.eps_esm, -U) + c_sum;
+
+    if (diag) {
+        diag->Fy_sum = Fy_sum;
+        diag->Fz_sum = Fz_sum;
+        diag->Mx = Msum[0];
+        diag->My = Msum[1];
+        diag->Mz = Msum[2];
+        diag->c_sum = c_sum;
+        diag->U_esm = U;
+        diag->L = Lrun;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------ rollout ---- */
+
+static double goal_distance(const oracle_ctx *o, double x, double y)
+{
+    double dx = x - o->c.goal_x, dy = y - o->c.goal_y;
+    return sqrt(dx * dx + dy * dy);
+}
+
+/* One candidate: J = sum over Euler nodes of h L + Phi at the final (or
+ * goal-exit) state. */
+static void rollout_one(const oracle_ctx *o, const float state0[13],
+                        const float *controls, int K, int N, int k,
+                        double *J_out, double xi_out[13], int *exit_out)
+{
+    const int S = o->in.substeps;
+    const double h = o->in.dt / S;
+    double xi[13], xd[13];
+    for (int s = 0; s < 13; ++s) xi[s] = (double)state0[s];
+    double J = 0.0;
+    int done = 0, exit_step = -1;
+
+    for (int n = 0; n < N && !done; ++n) {
+        /* zero-order hold: control n applies for the whole interval; the
+         * sampled controls are restricted to the admissible set */
+        double u0 = (double)controls[((size_t)n * 2 + 0) * K + k];
+        double u1 = (double)controls[((size_t)n * 2 + 1) * K + k];
+        double delta_dot = clampd(u0, -o->v.delta_rate_max, o->v.delta_rate_max);
+        double vx_dot = o->in.accel_max * clampd(u1, -1.0, 1.0);
+        for (int s = 0; s < S; ++s) {
+            /* goal reached: horizon ends here (t_f) */
+            if (goal_distance(o, xi[0], xi[1]) <= o->c.goal_r) {
+                done = 1;
+                exit_step = n * S + s;
+                break;
+            }
+            oracle_diag d;
+            oracle_rhs(o, xi, delta_dot, vx_dot, xd, &d);
+            J += h * d.L;
+            for (int q = 0; q < 13; ++q) xi[q] = xi[q] + h * xd[q];
+            xi[12] = clampd(xi[12], -o->v.delta_max, o->v.delta_max);
+            if (xi[6] < o->in.vx_min) xi[6] = o->in.vx_min;
+        }
+    }
+    J += o->c.w_g * goal_distance(o, xi[0], xi[1]);
+
+    int finite = isfinite(J);
+    for (int q = 0; q < 13; ++q) finite = finite && isfinite(xi[q]);
+    if (!finite) J = INFINITY;
+    *J_out = J;
+    if (xi_out)
+        for (int q = 0; q < 13; ++q) xi_out[q] = xi[q];
+    if (exit_out) *exit_out = exit_step;
+}
+
+int oracle_rollout(const oracle_ctx *o, const float state0[13],
+                   const float *controls, int K, int N,
+                   double *cost, double *final_state, int *exit_step)
+{
+    if (!o || !state0 || !controls || !cost || K < 1 || N < 1) return -1;
+    if (!o->has_terrain) return -4;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int k = 0; k < K; ++k) {
+        double xi[13];
+        int ex;
+        rollout_one(o, state0, controls, K, N, k, &cost[k], xi, &ex);
+        if (final_state)
+            for (int q = 0; q < 13; ++q) final_state[(size_t)q * K + k] = xi[q];
+        if (exit_step) exit_step[k] = ex;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------- select ---- */
+
+int oracle_select(const oracle_ctx *o, int mode, double lambda,
+                  const float *controls, const float *cost, int K, int N,
+                  int *best_k, double *best_cost, double *plan)
+{
+    if (!o || !controls || !cost || !best_k || !best_cost || !plan) return -1;
+    if (K < 1 || N < 1 || (mode != 0 && mode != 1)) return -1;
+    if (mode == 1 && !(lambda > 0)) return -1;
+
+    /* empirical argmin: lowest index among the minimal finite costs */
+    int kb = -1;
+    double Jb = INFINITY;
+    for (int k = 0; k < K; ++k) {
+        double J = (double)cost[k];
+        if (!isfinite(J)) continue;
+        if (kb < 0 || J < Jb) {
+            kb = k;
+            Jb = J;
+        }
+    }
+    *best_k = kb;
+    *best_cost = Jb;
+    if (kb < 0) {
+        for (int q = 0; q < 2 * N; ++q) plan[q] = 0.0;
+        return 0;
+    }
+
+    for (int n = 0; n < N; ++n) {
+        for (int ch = 0; ch < 2; ++ch) {
+            double lim = (ch == 0) ? o->v.delta_rate_max : 1.0;
+            if (mode == 0) {
+                plan[n * 2 + ch] = clampd((double)controls[((size_t)n * 2 + ch) * K + kb], -lim, lim);
+            } else {
+                /* MPPI-style average: weights exp(-(J_k - J_min)/lambda) */
+                double num = 0.0, den = 0.0;
+                for (int k = 0; k < K; ++k) {
+                    double J = (double)cost[k];
+                    if (!isfinite(J)) continue;
+                    double wk = exp(-(J - Jb) / lambda);
+                    num += wk * clampd((double)controls[((size_t)n * 2 + ch) * K + k], -lim, lim);
+                    den += wk;
+                }
+                plan[n * 2 + ch] = num / den;
+            }
+        }
+    }
+    return 0;
+}

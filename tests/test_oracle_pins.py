@@ -1,0 +1,623 @@
+"""Pins for the FP64 oracle (CPU only).
+
+Each test checks the oracle against something other than its own formulas:
+closed forms that follow from the paper's equations, mechanical invariants
+(work-energy), textbook constructions (elementary rotations, plane geometry),
+the paper's other model (the extended single-track model, for the flat-ground
+reduction), physical sign conventions, and brute force on tiny inputs.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_20525_amd import inputs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# CoM height with an exact binary representation, so that float32 initial
+# states put the wheels exactly on the ground
+HR_EXACT = 0.625
+
+
+def _veh(**kw):
+    v = dict(inputs.WORKLOAD_VEHICLE)
+    v["hR"] = HR_EXACT
+    v.update(kw)
+    return v
+
+
+def _cost(**kw):
+    c = dict(inputs.BASE_COST)
+    c.update(kw)
+    return c
+
+
+def _integ(**kw):
+    i = dict(inputs.BASE_INTEG)
+    i.update(kw)
+    return i
+
+
+def _grid(f, n=81, res=0.25, x0=-10.0, y0=-10.0):
+    xs = x0 + res * np.arange(n)
+    ys = y0 + res * np.arange(n)
+    X, Y = np.meshgrid(xs, ys)
+    return f(X, Y).astype(np.float32), x0, y0, res
+
+
+def _oracle(veh=None, cost=None, integ=None, terrain=None, costmap=None):
+    o = oracle.Oracle(veh or _veh(), cost or _cost(goal_x=1e4, goal_y=0.0),
+                      integ or _integ())
+    h, x0, y0, res = terrain if terrain is not None else _grid(lambda X, Y: 0.0 * X)
+    o.set_terrain(h, x0, y0, res, costmap)
+    return o
+
+
+def Rz(a):
+    c, s = math.cos(a), math.sin(a)
+    return np.array([[c, -s, 0], [s, c, 0], [0, 0, 1.0]])
+
+
+def Ry(a):
+    c, s = math.cos(a), math.sin(a)
+    return np.array([[c, 0, s], [0, 1.0, 0], [-s, 0, c]])
+
+
+def Rx(a):
+    c, s = math.cos(a), math.sin(a)
+    return np.array([[1.0, 0, 0], [0, c, -s], [0, s, c]])
+
+
+def R321(psi, th, ph):
+    """Yaw about w_z, then pitch about the new y, then roll about b_x."""
+    return Rz(psi) @ Ry(th) @ Rx(ph)
+
+
+def rho_all(v):
+    return np.array([[v["Lf"], v["e"] / 2, -v["hR"]], [v["Lf"], -v["e"] / 2, -v["hR"]],
+                     [-v["Lr"], v["e"] / 2, -v["hR"]], [-v["Lr"], -v["e"] / 2, -v["hR"]]])
+
+
+def state(x=0.0, y=0.0, z=None, psi=0.0, th=0.0, ph=0.0, v=(5.0, 0, 0), w=(0, 0, 0),
+          delta=0.0, hR=None):
+    hR = HR_EXACT if hR is None else hR
+    z = hR if z is None else z
+    return np.array([x, y, z, psi, th, ph, *v, *w, delta], dtype=np.float64)
+
+
+# ----------------------------------------------------------- golden values
+
+def test_golden_paper_parameters_match_presets():
+    g = json.load(open(os.path.join(HERE, "golden", "paper_params.json")))
+    pv = inputs.PAPER_VEHICLE
+    for k in ("M", "Jxx", "Jyy", "Jzz", "Lf", "Lr", "e", "kf", "kr", "bf", "br",
+              "delta_max", "delta_rate_max"):
+        assert pv[k] == pytest.approx(g["vehicle"][k])
+    assert pv["hR"] == pytest.approx(g["vehicle"]["h"] + g["vehicle"]["R"])
+    assert (pv["C"], pv["mu"]) == (g["tire_sim"]["C"], g["tire_sim"]["mu"])
+    for k in ("w_t", "w_c", "w_g", "sigma", "eps_dist", "goal_r"):
+        assert inputs.BASE_COST[k] == pytest.approx(g["cost"][k])
+    rt = g["realtime"]
+    # resident-sample arithmetic printed with the real-time study
+    assert (rt["regs_per_core"] // rt["regs_srb"]) * rt["cores_rtx5000"] == rt["N_resident"]
+    assert rt["k"] * rt["N_resident"] == rt["N_samples"]
+    assert g["horizon"]["n_t"] * g["horizon"]["dt"] == pytest.approx(4.0)
+    assert g["horizon"]["dt"] / g["horizon"]["euler_step"] == pytest.approx(50.0)
+
+
+# ------------------------------------------------------ rotation & kinematics
+
+@pytest.mark.parametrize("ang", [(0.3, -0.2, 0.1), (-2.0, 0.6, -0.9), (1.0, 0.0, 0.5)])
+def test_rotation_and_contact_points_match_elementary_rotations(ang):
+    v = _veh()
+    o = _oracle(v)
+    xi = state(x=1.0, y=-2.0, z=3.0, psi=ang[0], th=ang[1], ph=ang[2], v=(4.0, -0.5, 0.3))
+    xd, d = o.rhs(xi, 0.0, 0.0)
+    R = R321(*ang)
+    P_expect = xi[:3][None, :] + (R @ rho_all(v).T).T
+    np.testing.assert_allclose(d["P"], P_expect, atol=1e-12)
+    np.testing.assert_allclose(xd[:3], R @ xi[6:9], atol=1e-12)
+
+
+@pytest.mark.parametrize("ang,w", [((0.3, -0.2, 0.1), (0.4, -0.7, 0.2)),
+                                   ((2.0, 0.9, -1.1), (-1.0, 0.3, 0.8))])
+def test_euler_rates_reproduce_body_angular_velocity(ang, w):
+    o = _oracle()
+    xi = state(psi=ang[0], th=ang[1], ph=ang[2], w=w, z=5.0)
+    xd, _ = o.rhs(xi, 0.0, 0.0)
+    rates = xd[3:6]
+    eps = 1e-6
+    a = np.array(ang)
+    Rdot = (R321(*(a + eps * rates)) - R321(*(a - eps * rates))) / (2 * eps)
+    # R^T Rdot = [omega]_x for a body-frame angular velocity
+    Wx = R321(*a).T @ Rdot
+    np.testing.assert_allclose([Wx[2, 1], Wx[0, 2], Wx[1, 0]], w, atol=1e-8)
+    np.testing.assert_allclose(Wx + Wx.T, 0.0, atol=1e-8)
+
+
+def test_wheel_velocity_is_rigid_body_velocity_of_contact_point():
+    v = _veh()
+    o = _oracle(v)
+    xi = state(psi=0.4, th=0.1, ph=-0.2, v=(6.0, 0.4, -0.2), w=(0.3, -0.5, 0.9), z=4.0)
+    xd, d = o.rhs(xi, 0.0, 0.0)
+    # world velocity of the contact point by finite differences of P(t)
+    eps = 1e-6
+    xp = xi.copy()
+    xp[:6] += eps * xd[:6]
+    xm = xi.copy()
+    xm[:6] -= eps * xd[:6]
+    _, dp = o.rhs(xp, 0.0, 0.0)
+    _, dm = o.rhs(xm, 0.0, 0.0)
+    Pdot = (np.array(dp["P"]) - np.array(dm["P"])) / (2 * eps)
+    R = R321(*xi[3:6])
+    np.testing.assert_allclose((R @ np.array(d["vi"]).T).T, Pdot, atol=1e-7)
+
+
+# ------------------------------------------------------- P1 static equilibrium
+
+def test_p1_static_equilibrium_on_flat_ground():
+    c0 = float(np.float32(0.37))   # the terrain is handed over in float32
+    v = _veh()
+    o = _oracle(v, terrain=_grid(lambda X, Y: c0 + 0.0 * X))
+    xi = state(z=c0 + v["hR"], v=(7.0, 0, 0))
+    xd, d = o.rhs(xi, 0.0, 0.0)
+    expect = np.zeros(13)
+    expect[0] = 7.0
+    np.testing.assert_allclose(xd, expect, atol=1e-9)
+    np.testing.assert_allclose(d["chi"], 0.0, atol=1e-12)
+    assert d["Fz_sum"] == pytest.approx(v["M"] * v["g"], rel=1e-12)
+    L = v["Lf"] + v["Lr"]
+    np.testing.assert_allclose(d["Fz"], [v["g"] / 2 * v["M"] * v["Lr"] / L] * 2 +
+                               [v["g"] / 2 * v["M"] * v["Lf"] / L] * 2, rtol=1e-12)
+
+
+# --------------------------------------------------- P2 flat straight line
+
+def test_p2_flat_straight_line_rollout():
+    v = _veh()
+    N, dt, v0 = 40, 0.02, 6.0
+    gx, gy = 100.0, 3.0
+    o = _oracle(v, cost=_cost(goal_x=gx, goal_y=gy))
+    s0 = state(z=v["hR"], v=(v0, 0, 0)).astype(np.float32)
+    u = np.zeros((N, 2, 1), np.float32)
+    J, fs, ex = o.rollout(s0, u)
+    T = N * dt
+    assert fs[0, 0] == pytest.approx(v0 * T, rel=1e-12)
+    np.testing.assert_allclose(fs[1:6, 0], s0[1:6], atol=1e-12)
+    np.testing.assert_allclose(fs[7:, 0], 0.0, atol=1e-12)
+    Jexp = 5.0 * T + 15.0 * math.hypot(gx - v0 * T, gy)
+    assert J[0] == pytest.approx(Jexp, rel=1e-12)
+    assert ex[0] == -1
+
+
+def test_constant_costmap_adds_four_wheel_lookups_per_second():
+    v = _veh()
+    N, dt, v0, c0 = 25, 0.02, 6.0, 7.0
+    h, x0, y0, res = _grid(lambda X, Y: 0.0 * X)
+    cm = np.full_like(h, c0)
+    o = _oracle(v, cost=_cost(goal_x=100.0, goal_y=0.0), terrain=(h, x0, y0, res), costmap=cm)
+    s0 = state(z=v["hR"], v=(v0, 0, 0)).astype(np.float32)
+    J, fs, _ = o.rollout(s0, np.zeros((N, 2, 1), np.float32))
+    T = N * dt
+    assert J[0] == pytest.approx((5.0 + 4 * c0) * T + 15.0 * (100.0 - v0 * T), rel=1e-12)
+
+
+# ------------------------------------------- P3 flat-ground reduction to EST
+
+@pytest.mark.parametrize("vy,delta", [(0.8, 0.2), (-1.5, -0.4), (0.3, 0.0)])
+def test_p3_flat_ground_reduces_to_extended_single_track(vy, delta):
+    v = _veh()
+    vx = 8.0
+    o = _oracle(v)
+    xi = state(z=v["hR"], v=(vx, vy, 0.0), delta=delta)
+    xd, d = o.rhs(xi, 0.0, 0.0)
+    # extended single-track model (paper, section on the EST model): virtual
+    # front/rear tires, normal loads from the static load coefficients with
+    # no longitudinal acceleration, same sigmoid tire
+    g, M = v["g"], v["M"]
+    L = v["Lf"] + v["Lr"]
+    Kf, Kr = M * v["Lr"] / L, M * v["Lf"] / L
+    Fzf, Fzr = Kf * g, Kr * g   # -K_zz g_Bz on level ground
+    af = math.atan((vy + 0.0 * v["Lf"]) / vx) - delta
+    ar = math.atan((vy - 0.0 * v["Lr"]) / vx)
+
+    def tire(a, Fz):
+        Ca = v["C"] * a
+        return -Ca * v["mu"] / math.sqrt(v["mu"] ** 2 + Ca ** 2) * Fz
+
+    Fyf, Fyr = tire(af, Fzf), tire(ar, Fzr)
+    wz_dot_est = (Fyf * v["Lf"] * math.cos(delta) - Fyr * v["Lr"]) / v["Jzz"]
+    assert xd[11] == pytest.approx(wz_dot_est, rel=1e-10, abs=1e-12)
+    # lateral row: same with the front force projected by cos(delta)
+    vy_dot = (Fyf * math.cos(delta) + Fyr) / M
+    assert xd[7] == pytest.approx(vy_dot, rel=1e-10, abs=1e-12)
+
+
+def test_tire_signs_and_limits():
+    v = _veh()
+    o = _oracle(v)
+    # sideslip to the left is opposed
+    xd, _ = o.rhs(state(z=v["hR"], v=(8.0, 1.0, 0.0)), 0.0, 0.0)
+    assert xd[7] < 0
+    # steering left turns left
+    xd, _ = o.rhs(state(z=v["hR"], v=(8.0, 0.0, 0.0), delta=0.2), 0.0, 0.0)
+    assert xd[11] > 0 and xd[7] > 0
+    # linear region: F_y/F_z ~ -C alpha; saturation at mu
+    _, d = o.rhs(state(z=v["hR"], v=(8.0, 8.0 * math.tan(1e-5), 0.0)), 0.0, 0.0)
+    for i in range(4):
+        assert d["Fy"][i] / d["Fz"][i] / d["alpha"][i] == pytest.approx(-v["C"], rel=1e-6)
+    # near pure sideslip the ratio approaches (but never exceeds) mu
+    _, d = o.rhs(state(z=v["hR"], v=(1.0, 1e4, 0.0)), 0.0, 0.0)
+    for i in range(4):
+        r = d["Fy"][i] / d["Fz"][i]
+        assert -v["mu"] < r < -0.99 * v["mu"]
+
+
+# --------------------------------------------------- P4 heave energy, b = 0
+
+def test_p4_euler_heave_energy_grows_by_exact_factor():
+    v = _veh(Lf=1.2, Lr=1.2, kf=5.0e4, kr=5.0e4, bf=0.0, br=0.0)
+    N, dt, e0, v0 = 12, 0.02, 0.01, 5.0
+    o = _oracle(v)
+    s0 = state(z=v["hR"] + e0, v=(v0, 0, 0)).astype(np.float32)
+    J, fs, _ = o.rollout(s0, np.zeros((N, 2, 1), np.float32))
+    w2 = 2.0 * (v["kf"] + v["kr"]) / v["M"]
+    e_0 = float(s0[2]) - v["hR"]
+    A = np.array([[1.0, dt], [-dt * w2, 1.0]])
+    eN, vN = np.linalg.matrix_power(A, N) @ np.array([e_0, 0.0])
+    assert fs[2, 0] - v["hR"] == pytest.approx(eN, rel=1e-9, abs=1e-13)
+    assert fs[8, 0] == pytest.approx(vN, rel=1e-9, abs=1e-13)
+    E0 = 0.5 * w2 * e_0 ** 2
+    EN = 0.5 * fs[8, 0] ** 2 + 0.5 * w2 * (fs[2, 0] - v["hR"]) ** 2
+    assert EN / E0 == pytest.approx((1 + w2 * dt * dt) ** N, rel=1e-9)
+    np.testing.assert_allclose(fs[[4, 5, 9, 10, 11], 0], 0.0, atol=1e-13)
+
+
+# ------------------------------------------- P5 work-energy identity (3-D)
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_p5_work_energy_identity_on_rough_terrain(seed):
+    rng = np.random.default_rng(seed)
+    v = _veh()
+    T = inputs.bumps_terrain(11, n=96, res=0.2)
+    o = _oracle(v, terrain=(T.height, T.x0, T.y0, T.res))
+    for _ in range(5):
+        xi = state(x=rng.uniform(5, 14), y=rng.uniform(5, 14),
+                   psi=rng.uniform(-3, 3), th=rng.uniform(-0.3, 0.3), ph=rng.uniform(-0.3, 0.3),
+                   v=(rng.uniform(2, 10), rng.uniform(-2, 2), rng.uniform(-1, 1)),
+                   w=rng.uniform(-1, 1, size=3), delta=rng.uniform(-0.5, 0.5))
+        xi[2] = float(o.sample(xi[0], xi[1])[0]) + v["hR"] + rng.uniform(-0.05, 0.02)
+        zeta2 = rng.uniform(-2, 2)
+        xd, d = o.rhs(xi, rng.uniform(-1, 1), zeta2)
+        vb, w = xi[6:9], xi[9:12]
+        J = np.array([v["Jxx"], v["Jyy"], v["Jzz"]])
+        Edot = v["M"] * vb @ xd[6:9] + np.sum(J * w * xd[9:12]) + v["M"] * v["g"] * xd[2]
+        power = sum(np.dot(d["f"][i], d["vi"][i]) for i in range(4))
+        scale = v["M"] * v["g"] * 10.0
+        assert Edot == pytest.approx(power, abs=1e-9 * scale)
+
+
+# ---------------------------------------------------- P6 inclined plane
+
+# slopes and grid chosen so the float32 heights are exact
+@pytest.mark.parametrize("a,b,psi", [(0.25, -0.125, 0.3), (-0.375, 0.25, 2.1)])
+def test_p6_inclined_plane_normal_sign(a, b, psi):
+    v = _veh()
+    terr = _grid(lambda X, Y: a * X + b * Y + 1.0)
+    o = _oracle(v, terrain=terr)
+    s = math.sqrt(1 + a * a + b * b)
+    n = np.array([-a, -b, 1.0]) / s
+    c, si = math.cos(psi), math.sin(psi)
+    n1 = np.array([c * n[0] + si * n[1], -si * n[0] + c * n[1], n[2]])
+    ph = -math.asin(n1[1])
+    th = math.atan2(n1[0], n1[2])
+    R = R321(psi, th, ph)
+    np.testing.assert_allclose(R[:, 2], n, atol=1e-12)
+    p0 = np.array([0.5, -0.3, a * 0.5 + b * -0.3 + 1.0])
+    p = p0 + v["hR"] * n
+    xi = state(x=p[0], y=p[1], z=p[2], psi=psi, th=th, ph=ph, v=(5.0, 0.7, 0.0), w=(0, 0, 0.4))
+    xd, d = o.rhs(xi, 0.0, 0.0)
+    np.testing.assert_allclose(d["chi"], 0.0, atol=1e-12)
+    np.testing.assert_allclose(d["chidot"], 0.0, atol=1e-11)
+    dz = 0.03
+    xi2 = xi.copy()
+    xi2[2] += dz
+    _, d2 = o.rhs(xi2, 0.0, 0.0)
+    np.testing.assert_allclose(d2["chi"], dz / s, rtol=1e-10)
+
+
+# ---------------------------------------------------- P7 liftoff
+
+def test_p7_free_fall_after_liftoff_and_no_esm_cost():
+    v = _veh()
+    N, dt, vz0 = 10, 0.02, 0.5
+    z0 = v["hR"] + 1.0
+    o = _oracle(v, cost=_cost(goal_x=200.0, goal_y=0.0))
+    s0 = state(z=z0, v=(5.0, 0.0, vz0)).astype(np.float32)
+    _, d = o.rhs(s0.astype(np.float64), 0.0, 0.0)
+    np.testing.assert_allclose(d["Fz"], 0.0)
+    np.testing.assert_allclose(d["Fb"], 0.0)
+    J, fs, _ = o.rollout(s0, np.zeros((N, 2, 1), np.float32))
+    n = N
+    z_exact = float(s0[2]) + n * dt * float(s0[8]) - v["g"] * dt * dt * n * (n - 1) / 2
+    assert fs[2, 0] == pytest.approx(z_exact, rel=1e-12)
+    assert fs[8, 0] == pytest.approx(float(s0[8]) - v["g"] * n * dt, rel=1e-12)
+    T = N * dt
+    assert J[0] == pytest.approx(5.0 * T + 15.0 * (200.0 - 5.0 * T), rel=1e-12)
+
+
+def test_normal_force_never_attractive():
+    v = _veh()
+    T = inputs.bumps_terrain(3, n=96, res=0.2)
+    o = _oracle(v, terrain=(T.height, T.x0, T.y0, T.res))
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        xi = state(x=rng.uniform(3, 16), y=rng.uniform(3, 16), psi=rng.uniform(-3, 3),
+                   th=rng.uniform(-0.4, 0.4), ph=rng.uniform(-0.4, 0.4),
+                   v=(rng.uniform(1, 10), rng.uniform(-2, 2), rng.uniform(-3, 3)),
+                   w=rng.uniform(-2, 2, size=3))
+        xi[2] = float(o.sample(xi[0], xi[1])[0]) + v["hR"] + rng.uniform(-0.1, 0.1)
+        _, d = o.rhs(xi, 0.0, 0.0)
+        assert min(d["Fz"]) >= 0.0
+        for i in range(4):
+            if d["Fk"][i] == 0.0:
+                assert d["Fb"][i] == 0.0
+
+
+# ---------------------------------------------------- P8 ESM
+
+@pytest.mark.parametrize("veh", [inputs.WORKLOAD_VEHICLE, inputs.PAPER_VEHICLE])
+def test_p8_esm_matches_tipping_geometry(veh):
+    o = _oracle(dict(veh))
+    M, g, e, hR = veh["M"], veh["g"], veh["e"], veh["hR"]
+
+    def com_height_over_wheel_line(phi):
+        # CoM-to-contact-line vector (e/2, hR) in the roll plane, rotated by |phi|
+        # towards that wheel line
+        a = abs(phi)
+        return (e / 2) * math.sin(a) + hR * math.cos(a)
+
+    grid = np.linspace(0, math.pi / 2, 200001)
+    h_top = max(com_height_over_wheel_line(p) for p in grid[::100])
+    h_top = max(h_top, float(np.max((e / 2) * np.sin(grid) + hR * np.cos(grid))))
+    phi_tip = math.atan2(e / 2, hR)   # CoM straight over the wheel line
+    for phi in [0.0, 0.1, -0.3, 0.5, phi_tip - 0.01, phi_tip + 0.01, 1.2, -1.4]:
+        dh = h_top - com_height_over_wheel_line(phi)
+        inside = abs(phi) <= phi_tip
+        U_geom = (M * g * dh) if inside else (-M * g * dh)
+        assert o.esm(phi, 0.0) == pytest.approx(U_geom, rel=1e-7, abs=1e-6)
+        assert o.esm(phi, 0.4) == pytest.approx(U_geom * math.cos(0.4), rel=1e-7, abs=1e-6)
+        assert o.esm(-phi, 0.0) == o.esm(phi, 0.0)
+    assert o.esm(phi_tip, 0.0) == pytest.approx(0.0, abs=1e-9)
+    phis = np.linspace(0, 1.5, 301)
+    U = np.array([o.esm(p, 0.0) for p in phis])
+    assert np.all(np.diff(U) < 0)
+    assert U[-1] < 0
+
+
+def test_p8_esm_soft_cost_starts_at_ten_percent_margin():
+    v = _veh()
+    o = _oracle(v)
+    U0 = o.esm(0.0, 0.0)
+    # find roll where U = 0.1 U0: below it the ESM term is active
+    lo, hi = 0.0, 1.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if o.esm(mid, 0.0) > 0.1 * U0:
+            lo = mid
+        else:
+            hi = mid
+    phi10 = lo
+    for phi, active in ((phi10 - 1e-3, False), (phi10 + 1e-3, True)):
+        xi = state(ph=phi, z=5.0)
+        _, d = o.rhs(xi, 0.0, 0.0)
+        soft = d["L"] - 5.0 - d["c_sum"]
+        assert (soft > 0) == active
+
+
+# ---------------------------------------------------- P9 soft constraint
+
+def test_p9_soft_constraint_shape():
+    sig, eps = 1.0e6, 0.25
+    assert oracle.soft(sig, eps, -1.0) == 0.0
+    assert oracle.soft(sig, eps, -eps) == 0.0
+    assert oracle.soft(sig, eps, 0.0) == pytest.approx(sig)
+    assert oracle.soft(sig, eps, eps) == pytest.approx(4 * sig)
+    assert oracle.soft(sig, eps, -0.5 * eps) == pytest.approx(0.25 * sig)
+
+
+# ---------------------------------------------------- P10 terrain sampler
+
+def test_p10_plane_is_reproduced_exactly():
+    a, b, c = 0.3, -0.15, 2.0
+    o = _oracle(terrain=_grid(lambda X, Y: a * X + b * Y + c))
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        x, y = rng.uniform(-10, 10, size=2)
+        t = o.sample(x, y)
+        assert t[0] == pytest.approx(a * x + b * y + c, abs=1e-5)
+        assert t[1] == pytest.approx(a, abs=1e-5)
+        assert t[2] == pytest.approx(b, abs=1e-5)
+        assert t[3] == 0.0
+
+
+def test_p10_central_differences_exact_for_quadratic_at_nodes_and_clamp():
+    h, x0, y0, res = _grid(lambda X, Y: 0.01 * X * X - 0.02 * Y * Y, n=41, res=0.5)
+    o = _oracle(terrain=(h, x0, y0, res))
+    hd = h.astype(np.float64)
+    for (i, j) in [(5, 7), (20, 20), (39, 1)]:
+        x, y = x0 + i * res, y0 + j * res
+        t = o.sample(x, y)
+        assert t[0] == hd[j, i]
+        assert t[1] == pytest.approx((hd[j, i + 1] - hd[j, i - 1]) / (2 * res), abs=1e-12)
+        assert t[1] == pytest.approx(0.02 * x, abs=1e-4)
+        assert t[2] == pytest.approx(-0.04 * y, abs=1e-4)
+    # clamp-to-edge outside the grid
+    t_out = o.sample(x0 - 5.0, y0 + 3.0)
+    t_edge = o.sample(x0, y0 + 3.0)
+    np.testing.assert_array_equal(t_out, t_edge)
+    t_out = o.sample(x0 + 100.0, y0 + 100.0)
+    corner = o.sample(x0 + 40 * res, y0 + 40 * res)
+    np.testing.assert_array_equal(t_out, corner)
+
+
+def test_bilinear_midpoint_is_mean_of_corners():
+    rng = np.random.default_rng(2)
+    h = rng.standard_normal((10, 12)).astype(np.float32)
+    o = _oracle(terrain=(h, 0.0, 0.0, 1.0))
+    t = o.sample(3.5, 4.5)
+    assert t[0] == pytest.approx(float(np.mean(h[4:6, 3:5].astype(np.float64))), abs=1e-12)
+
+
+# ---------------------------------------------------- P11 brute force
+
+def _three_segment_candidates():
+    vals = (-1.0, 0.0, 1.0)
+    cands = [(a, b, c) for a in vals for b in vals for c in vals]
+    u = np.zeros((3, 2, len(cands)), np.float32)
+    for k, seq in enumerate(cands):
+        u[:, 0, k] = seq
+    return u
+
+
+def test_p11_brute_force_argmin_over_27_sequences():
+    T = inputs.bumps_terrain(1000)
+    v = _veh()
+    o = oracle.Oracle(v, _cost(goal_x=17.0, goal_y=14.0), _integ(dt=0.1, substeps=10))
+    o.set_terrain(T.height, T.x0, T.y0, T.res)
+    s0 = inputs.settled_state(T, 5.0, 12.8, 0.0, 8.0, v["hR"])
+    u = _three_segment_candidates()
+    J, _, _ = o.rollout(s0, u)
+    for k in range(u.shape[2]):
+        Jk, _, _ = o.rollout(s0, u[:, :, k:k + 1].copy())
+        assert Jk[0] == J[k]
+    Jf = J.astype(np.float32)
+    kb, jb, plan = o.select(u, Jf, mode=0)
+    enum = min(range(len(Jf)), key=lambda k: (Jf[k], k))
+    assert kb == enum and jb == float(Jf[enum])
+    np.testing.assert_array_equal(plan, u[:, :, enum])
+    # softmin limits
+    kb0, _, plan0 = o.select(u, Jf, mode=1, lam=1e-9)
+    np.testing.assert_allclose(plan0, plan, atol=1e-12)
+    _, _, plan_inf = o.select(u, Jf, mode=1, lam=1e12)
+    np.testing.assert_allclose(plan_inf, u.mean(axis=2), atol=1e-9)
+
+
+def test_p11_softmin_two_candidates_and_ties():
+    o = _oracle()
+    u = np.zeros((2, 2, 2), np.float32)
+    u[:, 0, 0] = [0.5, -0.5]
+    u[:, 0, 1] = [-0.25, 0.75]
+    u[:, 1, 1] = [0.4, 0.4]
+    J = np.array([10.0, 11.0], np.float32)
+    lam = 2.0
+    w1 = math.exp(-1.0 / lam)
+    _, _, plan = o.select(u, J, mode=1, lam=lam)
+    ud = u.astype(np.float64)
+    np.testing.assert_allclose(plan[:, 0], (ud[:, 0, 0] + w1 * ud[:, 0, 1]) / (1 + w1), rtol=1e-12)
+    np.testing.assert_allclose(plan[:, 1], (w1 * ud[:, 1, 1]) / (1 + w1), rtol=1e-12)
+    # clamped controls are what the plan reports
+    u2 = np.full((1, 2, 3), 5.0, np.float32)
+    _, _, p2 = o.select(u2, np.array([3.0, 1.0, 1.0], np.float32), mode=0)
+    np.testing.assert_array_equal(p2, [[1.0, 1.0]])
+    kb, _, _ = o.select(u2, np.array([3.0, 1.0, 1.0], np.float32), mode=0)
+    assert kb == 1
+    kb, jb, p3 = o.select(u2, np.array([np.inf, np.nan, np.inf], np.float32), mode=0)
+    assert kb == -1 and math.isinf(jb)
+    np.testing.assert_array_equal(p3, 0.0)
+
+
+# ---------------------------------------------------- P12 Euler consistency
+
+def test_p12_euler_first_order_convergence():
+    T = inputs.bumps_terrain(1000)
+    v = _veh()
+    s0 = inputs.settled_state(T, 5.0, 12.8, 0.0, 5.0, v["hR"])
+    N = 20
+    u = np.zeros((N, 2, 1), np.float32)
+    u[:, 0, 0] = 0.3 * np.sin(np.arange(N) * 0.3)
+    finals = []
+    for S in (4, 8, 16, 32):
+        o = oracle.Oracle(v, _cost(goal_x=100.0, goal_y=0.0), _integ(dt=0.05, substeps=S))
+        o.set_terrain(T.height, T.x0, T.y0, T.res)
+        _, fs, _ = o.rollout(s0, u)
+        finals.append(fs[:, 0])
+    d = [np.linalg.norm(finals[i] - finals[i + 1]) for i in range(3)]
+    for i in range(2):
+        assert 1.6 < d[i] / d[i + 1] < 2.5
+
+
+# ---------------------------------------------------- goal, clamps, non-finite
+
+def test_goal_exit_on_straight_line():
+    v = _veh()
+    o = _oracle(v, cost=_cost(goal_x=20.0, goal_y=0.0, goal_r=2.5))
+    s0 = state(z=v["hR"], v=(10.0, 0, 0)).astype(np.float32)
+    J, fs, ex = o.rollout(s0, np.zeros((150, 2, 1), np.float32))
+    n_star = math.ceil(17.5 / 0.2)
+    assert ex[0] == n_star
+    assert fs[0, 0] == pytest.approx(n_star * 0.2, rel=1e-12)
+    assert J[0] == pytest.approx(5.0 * n_star * 0.02 + 15.0 * (20.0 - n_star * 0.2), rel=1e-10)
+
+
+def test_steering_angle_and_speed_clamps():
+    v = _veh()
+    N = 50
+    o = _oracle(v, cost=_cost(goal_x=500.0, goal_y=0.0))
+    s0 = state(z=v["hR"], v=(2.0, 0, 0)).astype(np.float32)
+    u = np.zeros((N, 2, 1), np.float32)
+    u[:, 0, 0] = 5.0     # beyond the 1 rad/s steering-rate limit
+    u[:, 1, 0] = -3.0    # beyond full braking
+    J, fs, _ = o.rollout(s0, u)
+    assert fs[12, 0] == v["delta_max"]
+    assert fs[6, 0] == 1.0
+    Phi = 15.0 * math.hypot(500.0 - fs[0, 0], fs[1, 0])
+    assert J[0] - Phi == pytest.approx(N * 0.02 * (5.0 + 8.0 * 1.0), rel=1e-9)
+
+
+def test_non_finite_state_gives_infinite_cost():
+    o = _oracle()
+    s0 = state().astype(np.float32)
+    s0[7] = np.nan
+    J, _, _ = o.rollout(s0, np.zeros((5, 2, 2), np.float32))
+    assert np.all(np.isinf(J))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_extension_rate_is_time_derivative_of_extension_on_plane(seed):
+    """On planar terrain the extension chi (distance along b_z from the
+    contact point to the plane) has an exact time derivative; chi_dot must
+    equal it for any motion, including rotation with the wheel off the plane."""
+    rng = np.random.default_rng(seed)
+    a, b = 0.25, -0.375
+    o = _oracle(terrain=_grid(lambda X, Y: a * X + b * Y))
+    xi = state(x=0.3, y=-0.4, z=1.1, psi=rng.uniform(-3, 3), th=rng.uniform(-0.3, 0.3),
+               ph=rng.uniform(-0.3, 0.3), v=rng.uniform(-3, 3, size=3), w=rng.uniform(-1, 1, size=3))
+    xd, d = o.rhs(xi, 0.0, 0.0)
+    assert max(abs(c) for c in d["chi"]) > 0.05
+    eps = 1e-6
+    xp, xm = xi.copy(), xi.copy()
+    xp[:6] += eps * xd[:6]
+    xm[:6] -= eps * xd[:6]
+    _, dp = o.rhs(xp, 0.0, 0.0)
+    _, dm = o.rhs(xm, 0.0, 0.0)
+    chi_dot_fd = (np.array(dp["chi"]) - np.array(dm["chi"])) / (2 * eps)
+    np.testing.assert_allclose(d["chidot"], chi_dot_fd, atol=1e-7)
+
+
+def test_steering_rate_cost_is_quadratic():
+    v = _veh()
+    N = 30
+    o = _oracle(v, cost=_cost(goal_x=500.0, goal_y=0.0))
+    s0 = state(z=v["hR"], v=(2.0, 0, 0)).astype(np.float32)
+    for rate in (0.5, -0.25):
+        u = np.zeros((N, 2, 1), np.float32)
+        u[:, 0, 0] = rate
+        J, fs, _ = o.rollout(s0, u)
+        Phi = 15.0 * math.hypot(500.0 - fs[0, 0], fs[1, 0])
+        assert J[0] - Phi == pytest.approx(N * 0.02 * (5.0 + 8.0 * rate * rate), rel=1e-9)
