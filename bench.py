@@ -1,0 +1,191 @@
+#!/usr/bin/env python3
+"""Planner benchmark on one MI355X.
+
+One step = one plan of the sampling MPC planner: the HIP rollout of K
+candidate control sequences through the single-rigid-body model over the
+heightmap (stage cost and ESM constraint at every Euler step), followed by
+the argmin selection and the 8-byte readback of (k*, J*) -- what one MPC
+iteration needs before it can act. The default workload is a single plan of
+K=4096 candidates x N=100 steps (dt 0.02 s) over a 512x512 fractal-noise
+terrain with two berms, initial speed 15 m/s (synthetic, seeded).
+
+Prints one JSON line: rollout-steps/s (K*N*substeps per plan / wall time per
+plan), p50/p99 plan latency, the rollout kernel's ALU roofline fraction
+(HIP events on the planner's stream) and the FP64 oracle timed on the host
+cores on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "candidate rollout-steps/sec and p50/p99 plan latency (serving vs plain)"
+
+# FP32 operations per rollout-step of the step definition, one lane per
+# candidate, transcendentals counted as one (the per-block count is tabulated
+# in the design notes); used for the algorithmic side of the ALU roofline.
+OPS_PER_STEP = 532
+# MI355X vector ALU issue: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz, one
+# non-packed FP32 operation per lane per clock.
+ALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
+
+
+def workload(name):
+    from paper_2603_20525_amd import inputs
+    if name == "c2":
+        return inputs.c2(), "single plan: K=4096 candidates, N=100 steps at dt=0.02 s, " \
+                            "512x512 fBm+berms terrain at 0.1 m, v0=15 m/s"
+    if name == "c5":
+        return inputs.c5(), "stress: K=65536, N=200 at dt=0.01 s, 2048x2048 side-slope/berm/rut " \
+                            "terrain at 0.05 m, v0=20 m/s"
+    if name == "paper":
+        return inputs.paper_shape(), "paper solver shape: K=204288 uniform samples, 16 ZOH x 0.25 s, " \
+                                     "50 Euler substeps (5 ms), paper vehicle, 512x512 terrain"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def percentile(xs, q):
+    s = sorted(xs)
+    if not s:
+        return None
+    i = min(len(s) - 1, max(0, int(round(q / 100.0 * (len(s) - 1)))))
+    return s[i]
+
+
+def cpu_baseline(w, seconds):
+    """FP64 oracle on the host cores: full rollouts of the same workload
+    (or a candidate subset for very large K), repeated for about `seconds`."""
+    import numpy as np
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)))
+    o = oracle.Oracle(w.vehicle, w.cost, w.integ)
+    T = w.terrain
+    o.set_terrain(T.height, T.x0, T.y0, T.res)
+    K = w.K
+    u = w.controls
+    sample = f"full workload (K={K}, N={w.N})"
+    if K > 8192:
+        idx = np.arange(0, K, K // 4096)[:4096]
+        u = np.ascontiguousarray(u[:, :, idx])
+        sample = f"{len(idx)}-candidate subset of K={K}, N={w.N}"
+    steps_per_run = u.shape[2] * u.shape[0] * w.integ["substeps"]
+    runs, t0 = 0, time.perf_counter()
+    while True:
+        o.rollout(w.state0, u)
+        runs += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or runs >= 1000:
+            break
+    return {"value": steps_per_run * runs / el, "unit": "rollout-steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{sample} repeated {runs}x in {el:.1f} s (FP64 C, OpenMP over candidates)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c5", "paper"])
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="seconds of oracle work for cpu_baseline (0 = skip)")
+    ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(candidate sharding over GPUs is described in the design notes, not built)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2603_20525_amd import plan as P
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    w, desc = workload(args.workload)
+    T = w.terrain
+    K, N, S = w.K, w.N, w.integ["substeps"]
+    print(f"[bench] workload {args.workload}: {desc}", file=sys.stderr, flush=True)
+
+    pl = P.Planner(w.vehicle, w.cost, w.integ, K, N, T.W, T.H)
+    pl.set_terrain(torch.from_numpy(T.height).cuda(), T.x0, T.y0, T.res)
+    pl.set_launch(args.lanes, args.block)
+    u = torch.from_numpy(w.controls).cuda()
+    J = torch.empty(K, device="cuda")
+    plan = torch.empty(N, 2, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def one_plan():
+        pl.rollout(w.state0, u, J)
+        return pl.select(u, J, plan)
+
+    for _ in range(args.warmup):
+        one_plan()
+    torch.cuda.synchronize()
+    print(f"[bench] warmup {args.warmup} done; launch {pl.get_launch()}", file=sys.stderr,
+          flush=True)
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ta = time.perf_counter()
+        ev[i][0].record(stream)
+        pl.rollout(w.state0, u, J)
+        ev[i][1].record(stream)
+        k_best, j_best = pl.select(u, J, plan)
+        lat.append(time.perf_counter() - ta)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kern_ms = [a.elapsed_time(b) for a, b in ev]
+    print(f"[bench] timed {args.steps} plans in {elapsed:.3f} s", file=sys.stderr, flush=True)
+
+    steps_per_plan = K * N * S
+    value = steps_per_plan * args.steps / elapsed
+    k_avg_s = sum(kern_ms) / len(kern_ms) / 1e3
+    achieved = OPS_PER_STEP * steps_per_plan / k_avg_s / 1e9
+    lanes, block = pl.get_launch()
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "rollout-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "K": K, "N": N, "substeps": S, "dt": w.integ["dt"],
+                   "terrain": f"{T.W}x{T.H} at {T.res} m", "launch": {"lanes": lanes, "block": block}},
+        "plan_latency_ms": {"p50": percentile(lat, 50) * 1e3, "p99": percentile(lat, 99) * 1e3,
+                            "path": "plain (one rollout + argmin + readback per plan)"},
+        "rollout_kernel_ms": {"avg": k_avg_s * 1e3, "min": min(kern_ms), "max": max(kern_ms)},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_GOPS, "unit": "Gop/s",
+                     "frac": achieved / ALU_PEAK_GOPS, "traffic": None,
+                     "ops_per_rollout_step": OPS_PER_STEP},
+        "best": {"k": k_best, "J": j_best},
+    }
+    if args.cpu_seconds > 0:
+        print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    else:
+        out["cpu_baseline"] = None
+    pl.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

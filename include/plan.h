@@ -1,0 +1,208 @@
+/*
+ * plan.h -- C ABI of libplan: the data-parallel hot path of the off-road
+ * sampling MPC planner of "High-Speed, All-Terrain Autonomy: Ensuring Safety
+ * at the Limits of Mobility" (arXiv 2603.20525), for AMD Instinct MI355X
+ * (gfx950).
+ *
+ * One optimal-control problem (section "OCP Formulation", the problem solved
+ * at each MPC iteration) is: given the most recent state estimate xi_0, a
+ * heightmap f, a costmap of obstacle/path-boundary cost, a goal and the model
+ * parameters, evaluate the cost J (eq. framework:cost) of each of K sampled
+ * control sequences by forward-simulating the single-rigid-body (SRB) vehicle
+ * model (section "Single Rigid Body Vehicle Dynamics Model", eq.
+ * models:6dof:A), then return the sequence of minimal cost -- the "empirical
+ * argmin" of section "Real-Time Implementation" -- or, optionally, the
+ * MPPI-style weighted average of the sequences described beside it.
+ *
+ * Conventions shared by every call
+ *   - Status: every call returns plan_status_t; 0 (PLAN_OK) on success and a
+ *     negative code on failure. No call throws, aborts or exits. After a
+ *     failure plan_last_error() returns a one-line description.
+ *   - Device pointers (suffix _dev) are plain device addresses on the
+ *     context's device, owned by the caller, FP32, contiguous, 4-byte aligned.
+ *     Host pointers are ordinary process memory.
+ *   - Asynchrony: plan_set_terrain, plan_rollout and plan_select enqueue work
+ *     on the context's HIP stream and return without waiting, except where a
+ *     call states that it synchronises.
+ *   - Threads: a context is not thread-safe; independent contexts may be used
+ *     concurrently from different threads on different streams.
+ *   - Units: SI (m, s, kg, rad); costs in the paper's cost units.
+ */
+#ifndef PLAN_H
+#define PLAN_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct plan_ctx plan_ctx; /* opaque, owned by the library */
+
+typedef enum {
+    PLAN_OK = 0,
+    PLAN_EINVAL = -1,     /* invalid argument (NULL, size out of range, non-finite) */
+    PLAN_ENOMEM = -2,     /* device or host allocation failed */
+    PLAN_EDEVICE = -3,    /* a HIP runtime call or kernel launch failed */
+    PLAN_ENOTERRAIN = -4  /* rollout before any successful plan_set_terrain */
+} plan_status_t;
+
+/* Vehicle parameters (appendix "Vehicle Model Parameters": model parameter
+ * table and tire tables; notation table). hR = h + R, the CoM height above the
+ * contact patches at rest. C, mu: sigmoid tire (eq. models:tire). delta_max:
+ * steering angle limit; delta_rate_max: steering rate limit (the admissible
+ * control set of section "OCP Formulation"). g: gravity (positive). */
+typedef struct {
+    float M, Jxx, Jyy, Jzz;
+    float Lf, Lr, e, hR;
+    float kf, kr, bf, br;
+    float C, mu;
+    float delta_max, delta_rate_max;
+    float g;
+} plan_vehicle_t;
+
+/* Cost parameters (section "OCP Formulation"): running cost
+ * L = w_t + w_c delta_dot^2 + L_soft, terminal cost w_g * distance to the goal
+ * (goal_x, goal_y), goal radius goal_r ending the horizon early
+ * (eq. formulation:goal). sigma and eps_esm normalise the ESM soft constraint
+ * (L_soft term sigma * max(0, 1 - U_ESM / eps_esm)^2); eps_esm <= 0 selects
+ * 10 % of the ESM on level ground. eps_dist is the distance normaliser used
+ * when building a costmap; the rollout itself reads costmap cost rates. */
+typedef struct {
+    float w_t, w_c, w_g;
+    float goal_x, goal_y, goal_r;
+    float sigma, eps_esm, eps_dist;
+} plan_cost_t;
+
+/* Integration (sections "OCP Formulation" and "Real-Time Implementation"):
+ * dt = zero-order-hold period of one control; substeps = forward-Euler steps
+ * per control (Euler step h = dt / substeps); accel_max maps the throttle
+ * channel in [-1, 1] to the prescribed longitudinal acceleration vx_dot;
+ * vx_min is the floor kept on the CoM longitudinal speed (the model assumes it
+ * positive). */
+typedef struct {
+    float dt;
+    int substeps;
+    float accel_max;
+    float vx_min;
+} plan_integ_t;
+
+enum { PLAN_ARGMIN = 0, PLAN_SOFTMIN = 1 };
+
+/* Create a context on the current HIP device. max_K, max_N, max_W, max_H bound
+ * the sizes later calls may use; the library allocates its workspace for them
+ * once here (terrain texels 16*max_W*max_H bytes plus selection scratch).
+ * hip_stream is a hipStream_t, or NULL for the default stream.
+ * Errors: PLAN_EINVAL for NULL pointers, non-positive sizes or invalid
+ * parameters (M, J, Lf+Lr, e, hR, dt <= 0, substeps < 1, non-finite values);
+ * PLAN_ENOMEM; PLAN_EDEVICE. *out is set only on success. */
+plan_status_t plan_create(plan_ctx **out, const plan_vehicle_t *veh,
+                          const plan_cost_t *cost, const plan_integ_t *integ,
+                          int max_K, int max_N, int max_W, int max_H,
+                          void *hip_stream);
+
+/* Replace the stream later calls enqueue on (a hipStream_t, NULL = default). */
+plan_status_t plan_set_stream(plan_ctx *ctx, void *hip_stream);
+
+/* Replace the cost parameters (e.g. a new goal for the next MPC iteration). */
+plan_status_t plan_set_cost(plan_ctx *ctx, const plan_cost_t *cost);
+
+/* Upload a terrain (the heightmap f of assumption A1; slopes f_x, f_y by
+ * numerical first derivatives as the models require; costmap per section
+ * "Real-Time Implementation", pre-computed distance cost interpolated at run
+ * time). height_dev is [H][W] FP32, node (i, j) at (x0 + i*res, y0 + j*res),
+ * row j contiguous. costmap_dev is [H][W] FP32 cost units per second at each
+ * node, or NULL for zero. The library copies both into its own texel grid, so
+ * the caller may reuse the buffers once the stream has passed this call.
+ * Synchronises the stream (once per terrain, off the per-plan path) to check
+ * the data. Errors: PLAN_EINVAL for NULL height, W or H < 2 or above the
+ * create-time maxima, res <= 0, or any non-finite height or cost (the previous
+ * terrain is then no longer valid); PLAN_EDEVICE. */
+plan_status_t plan_set_terrain(plan_ctx *ctx, const float *height_dev, int W, int H,
+                               float x0, float y0, float res,
+                               const float *costmap_dev);
+
+/* Roll out K candidates for N zero-order-hold intervals of `substeps` Euler
+ * steps each and write their costs (eq. framework:cost, horizon ended early
+ * at the goal per eq. formulation:goal).
+ *   state0:          host, 13 floats in the order of eq. models:6dof:state:
+ *                    x, y, z, psi, theta, phi, vx, vy, vz, wx, wy, wz, delta
+ *                    (3-2-1 Euler angles, body-frame velocities).
+ *   controls_dev:    [N][2][K]: channel 0 steering rate (rad/s), channel 1
+ *                    throttle in [-1, 1]; both are clamped to the admissible
+ *                    set before use.
+ *   cost_dev:        [K] output; +inf for a candidate whose cost or final
+ *                    state is not finite.
+ *   final_state_dev: [13][K] output (state at the horizon end or goal exit),
+ *                    or NULL.
+ * Errors: PLAN_EINVAL (NULL ctx/state0/controls/cost, K not in [1, max_K], N
+ * not in [1, max_N], non-finite state0); PLAN_ENOTERRAIN; PLAN_EDEVICE. */
+plan_status_t plan_rollout(plan_ctx *ctx, const float state0[13],
+                           const float *controls_dev, int K, int N,
+                           float *cost_dev, float *final_state_dev);
+
+/* Resumable form of plan_rollout, for callers that advance candidates a few
+ * control intervals at a time (a serving loop interleaving requests, or a
+ * backward pass recomputing from checkpoints). state_dev [13][K] and
+ * cost_dev [K] hold each candidate's state (order of plan_rollout's state0)
+ * and running cost; this call advances them in place through control
+ * intervals n0 .. n1-1 of controls_dev [N][2][K]. finalize != 0 adds the
+ * terminal cost and applies the +inf rule, as at the end of plan_rollout. A
+ * candidate that reached the goal stays frozen (its next goal test fires
+ * again). plan_init_state followed by chunks covering [0, N) with finalize on
+ * the last gives bit-identical costs and states to one plan_rollout.
+ * Errors: PLAN_EINVAL (NULL pointers, K or N out of range, not
+ * 0 <= n0 <= n1 <= N); PLAN_ENOTERRAIN; PLAN_EDEVICE. */
+plan_status_t plan_rollout_chunk(plan_ctx *ctx, float *state_dev, float *cost_dev,
+                                 const float *controls_dev, int K, int N, int n0, int n1,
+                                 int finalize);
+
+/* Fill state_dev [13][K] with state0 (host, 13 floats) for every candidate
+ * and cost_dev [K] with zero, on the context's stream.
+ * Errors: PLAN_EINVAL (NULL pointers, K out of range, non-finite state0). */
+plan_status_t plan_init_state(plan_ctx *ctx, const float state0[13], float *state_dev,
+                              float *cost_dev, int K);
+
+/* Select over the K candidates of a rollout (section "Real-Time
+ * Implementation"). mode PLAN_ARGMIN: the lowest index k* of minimal finite
+ * cost; plan_dev [N][2] receives candidate k*'s clamped controls. mode
+ * PLAN_SOFTMIN: MPPI-style average, weights exp(-(J_k - J_min) / lambda) over
+ * finite costs (lambda > 0); plan_dev receives the weighted mean of the
+ * clamped controls, and best_k / best_cost still report the argmin.
+ * If no cost is finite, best_k = -1, best_cost = +inf, plan_dev is zeroed and
+ * the status is still PLAN_OK.
+ * best_k and best_cost are host pointers; if either is non-NULL the call
+ * synchronises the stream to fill them. Pass both NULL to stay asynchronous.
+ * Errors: PLAN_EINVAL (NULL ctx/controls/cost/plan, K or N out of range, bad
+ * mode, lambda <= 0 for SOFTMIN); PLAN_EDEVICE. */
+plan_status_t plan_select(plan_ctx *ctx, int mode, float lambda,
+                          const float *controls_dev, const float *cost_dev,
+                          int K, int N, int *best_k, float *best_cost,
+                          float *plan_dev);
+
+/* Launch shape of the rollout kernel: lanes per candidate (1, 2 or 4; the
+ * four wheels are split over the lanes) and workgroup size (64 or 256).
+ * 0 restores the automatic choice. Results are identical for every shape up
+ * to FP32 rounding of the wheel sums' evaluation order, which is fixed. */
+plan_status_t plan_set_launch(plan_ctx *ctx, int lanes, int block);
+
+/* Launch shape chosen for the most recent rollout. */
+plan_status_t plan_get_launch(const plan_ctx *ctx, int *lanes, int *block);
+
+/* Kernel timing: when enabled, HIP events bracket each rollout kernel on the
+ * context's stream; plan_last_rollout_ms waits for the end event and returns
+ * the kernel's elapsed time in milliseconds. */
+plan_status_t plan_enable_timing(plan_ctx *ctx, int on);
+plan_status_t plan_last_rollout_ms(plan_ctx *ctx, float *ms);
+
+/* Release everything the context owns. NULL is ignored. Waits for the
+ * context's stream first. */
+void plan_destroy(plan_ctx *ctx);
+
+/* Description of the most recent failure on ctx ("" if none). With ctx NULL,
+ * the description of the most recent failed plan_create in this process. The
+ * string stays valid until the next call on ctx. */
+const char *plan_last_error(const plan_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PLAN_H */

@@ -95,6 +95,10 @@ def lib():
         L.oracle_rollout.argtypes = [vp, fp, fp, C.c_int, C.c_int, dp, dp, ip]
         L.oracle_select.argtypes = [vp, C.c_int, C.c_double, fp, fp, C.c_int,
                                     C.c_int, ip, dp, dp]
+        L.oracle_rollout_span.argtypes = [vp, fp, fp, fp, C.c_int, C.c_int, C.c_int,
+                                          C.c_int, C.c_int, dp, dp, dp, dp, dp]
+        L.oracle_set_round32.argtypes = [vp, C.c_int]
+        L.oracle_set_round32.restype = None
         _lib = L
     return _lib
 
@@ -174,6 +178,34 @@ class Oracle:
         if rc != 0:
             raise RuntimeError(f"oracle_rollout failed ({rc})")
         return cost, fs, ex
+
+    def rollout_span(self, state_in, cost_in, controls, n0, n1, finalize, margins=False):
+        """Continue from per-candidate float32 states [13][K] and running costs
+        [K] over control intervals [n0, n1). Returns (state_out [13][K],
+        cost_out [K]) in double, plus (touchdown margin [K], slip margin [K],
+        largest |roll| or |pitch| [K]) when margins is set."""
+        si = _f32(state_in)
+        ci = _f32(cost_in)
+        u = _f32(controls)
+        N, _, K = u.shape
+        assert si.shape == (13, K) and ci.shape == (K,)
+        so = np.zeros((13, K))
+        co = np.zeros(K)
+        td = np.zeros(K)
+        sl = np.zeros(K)
+        tl = np.zeros(K)
+        rc = lib().oracle_rollout_span(self._h, _ptr(si, C.c_float), _ptr(ci, C.c_float),
+                                       _ptr(u, C.c_float), K, N, int(n0), int(n1),
+                                       int(bool(finalize)), _ptr(so, C.c_double),
+                                       _ptr(co, C.c_double), _ptr(td, C.c_double),
+                                       _ptr(sl, C.c_double), _ptr(tl, C.c_double))
+        if rc != 0:
+            raise RuntimeError(f"oracle_rollout_span failed ({rc})")
+        return (so, co, td, sl, tl) if margins else (so, co)
+
+    def set_round32(self, on: bool):
+        """Conditioning probe: round state and running cost to float after each step."""
+        lib().oracle_set_round32(self._h, int(bool(on)))
 
     def select(self, controls, cost, mode=0, lam=0.0):
         u = _f32(controls)

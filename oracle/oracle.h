@@ -105,6 +105,29 @@ int oracle_rollout(const oracle_ctx *o, const float state0[13],
                    const float *controls, int K, int N,
                    double *cost, double *final_state, int *exit_step);
 
+/* Continue K candidates from per-candidate states over control intervals
+ * [n0, n1) of the [N][2][K] control array. state_in is [13][K] float and
+ * cost_in [K] float (running cost so far); state_out [13][K] and cost_out [K]
+ * are double. With finalize, the terminal cost and the non-finite rule are
+ * applied at the end (as after the last interval of oracle_rollout).
+ * td_margin and slip_margin (optional, [K]) receive each candidate's smallest
+ * distance over the span to the model's discontinuities: the damper's
+ * touchdown switch (|F_s - k chi| / F_s on a compressing wheel) and the slip
+ * angle's sign flip (|v_x| of a wheel, m/s); tilt_max (optional, [K]) the
+ * largest |roll| or |pitch| (rad) met over the span.
+ * Returns 0, -1 on invalid arguments, -4 if no terrain is set. */
+int oracle_rollout_span(const oracle_ctx *o, const float *state_in, const float *cost_in,
+                        const float *controls, int K, int N, int n0, int n1, int finalize,
+                        double *state_out, double *cost_out, double *td_margin,
+                        double *slip_margin, double *tilt_max);
+
+/* Conditioning probe (off by default): when on, rollouts round the state and
+ * the running cost to float after every Euler step, while computing in
+ * double. Comparing with the plain double run shows how far float storage
+ * alone moves each trajectory, i.e. which candidates are well conditioned
+ * enough for an element-wise float-vs-double comparison. */
+void oracle_set_round32(oracle_ctx *o, int on);
+
 /* Selection over candidates. mode 0 = argmin, 1 = softmin with temperature
  * lambda. cost is [K] float (the values being selected over). plan is
  * [N][2] double: the applied (clamped) controls of the selected candidate, or

@@ -54,6 +54,7 @@ struct oracle_ctx {
     double x0, y0, res;
     double *th, *tfx, *tfy, *tc;
     int has_terrain;
+    int round32; /* conditioning probe, see oracle_set_round32 */
 };
 
 static double clampd(double x, double lo, double hi)
@@ -378,20 +379,53 @@ static double goal_distance(const oracle_ctx *o, double x, double y)
     return sqrt(dx * dx + dy * dy);
 }
 
-/* One candidate: J = sum over Euler nodes of h L + Phi at the final (or
- * goal-exit) state. */
-static void rollout_one(const oracle_ctx *o, const float state0[13],
-                        const float *controls, int K, int N, int k,
-                        double *J_out, double xi_out[13], int *exit_out)
+/* One candidate over control intervals [n0, n1): J accumulates h L at each
+ * Euler node (left Riemann sum); the horizon ends early at the goal. With
+ * finalize, Phi is added at the final (or goal-exit) state and a non-finite
+ * cost or state makes J = +inf. With round32, the state and J are rounded to
+ * float after every Euler step (a conditioning probe: how far float storage
+ * alone moves the double-precision trajectory). */
+/* Distance of one right-hand-side evaluation to the model's two
+ * discontinuities (diagnostic for float-vs-double comparisons):
+ *   - touchdown: the damper force is max(-b chi_dot, -F_k) while F_k > 0 and 0
+ *     at F_k = 0, so a compressing wheel (chi_dot < 0) gains b|chi_dot| at the
+ *     step where F_s - k chi crosses zero; margin |F_s - k chi| / F_s;
+ *   - slip: atan(v_y / v_x) jumps by pi where a wheel's v_x changes sign;
+ *     margin |v_x| in m/s;
+ * and the largest roll or pitch magnitude (the paper scores a trial as a
+ * rollover once either exceeds 72 degrees). */
+static void discontinuity_margins(const oracle_ctx *o, const oracle_diag *d,
+                                  const double xi[13], double *td, double *sl, double *tilt)
+{
+    double t = fmax(fabs(xi[4]), fabs(xi[5]));
+    if (!(t <= *tilt)) *tilt = t;
+    const oracle_vehicle *V = &o->v;
+    double L = V->Lf + V->Lr;
+    for (int i = 0; i < 4; ++i) {
+        int front = (i < 2);
+        double Fs = (V->g / 2.0) * V->M * (front ? V->Lr : V->Lf) / L;
+        double k = front ? V->kf : V->kr;
+        if (d->chidot[i] < 0.0) {
+            double m = fabs(Fs - k * d->chi[i]) / Fs;
+            if (!(m >= *td)) *td = m;
+        }
+        double vxm = fabs(d->vi[i][0]);
+        if (!(vxm >= *sl)) *sl = vxm;
+    }
+}
+
+static void span_one(const oracle_ctx *o, double xi[13], double *J_io,
+                     const float *controls, int K, int k, int n0, int n1,
+                     int finalize, int round32, int *exit_out, double *td, double *sl,
+                     double *tilt)
 {
     const int S = o->in.substeps;
     const double h = o->in.dt / S;
-    double xi[13], xd[13];
-    for (int s = 0; s < 13; ++s) xi[s] = (double)state0[s];
-    double J = 0.0;
+    double xd[13];
+    double J = *J_io;
     int done = 0, exit_step = -1;
 
-    for (int n = 0; n < N && !done; ++n) {
+    for (int n = n0; n < n1 && !done; ++n) {
         /* zero-order hold: control n applies for the whole interval; the
          * sampled controls are restricted to the admissible set */
         double u0 = (double)controls[((size_t)n * 2 + 0) * K + k];
@@ -407,20 +441,24 @@ static void rollout_one(const oracle_ctx *o, const float state0[13],
             }
             oracle_diag d;
             oracle_rhs(o, xi, delta_dot, vx_dot, xd, &d);
+            if (td && sl && tilt) discontinuity_margins(o, &d, xi, td, sl, tilt);
             J += h * d.L;
             for (int q = 0; q < 13; ++q) xi[q] = xi[q] + h * xd[q];
             xi[12] = clampd(xi[12], -o->v.delta_max, o->v.delta_max);
             if (xi[6] < o->in.vx_min) xi[6] = o->in.vx_min;
+            if (round32) {
+                for (int q = 0; q < 13; ++q) xi[q] = (double)(float)xi[q];
+                J = (double)(float)J;
+            }
         }
     }
-    J += o->c.w_g * goal_distance(o, xi[0], xi[1]);
-
-    int finite = isfinite(J);
-    for (int q = 0; q < 13; ++q) finite = finite && isfinite(xi[q]);
-    if (!finite) J = INFINITY;
-    *J_out = J;
-    if (xi_out)
-        for (int q = 0; q < 13; ++q) xi_out[q] = xi[q];
+    if (finalize) {
+        J += o->c.w_g * goal_distance(o, xi[0], xi[1]);
+        int finite = isfinite(J);
+        for (int q = 0; q < 13; ++q) finite = finite && isfinite(xi[q]);
+        if (!finite) J = INFINITY;
+    }
+    *J_io = J;
     if (exit_out) *exit_out = exit_step;
 }
 
@@ -432,14 +470,45 @@ int oracle_rollout(const oracle_ctx *o, const float state0[13],
     if (!o->has_terrain) return -4;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int k = 0; k < K; ++k) {
-        double xi[13];
+        double xi[13], J = 0.0;
         int ex;
-        rollout_one(o, state0, controls, K, N, k, &cost[k], xi, &ex);
+        for (int q = 0; q < 13; ++q) xi[q] = (double)state0[q];
+        span_one(o, xi, &J, controls, K, k, 0, N, 1, o->round32, &ex, NULL, NULL, NULL);
+        cost[k] = J;
         if (final_state)
             for (int q = 0; q < 13; ++q) final_state[(size_t)q * K + k] = xi[q];
         if (exit_step) exit_step[k] = ex;
     }
     return 0;
+}
+
+int oracle_rollout_span(const oracle_ctx *o, const float *state_in, const float *cost_in,
+                        const float *controls, int K, int N, int n0, int n1, int finalize,
+                        double *state_out, double *cost_out, double *td_margin,
+                        double *slip_margin, double *tilt_max)
+{
+    if (!o || !state_in || !cost_in || !controls || !state_out || !cost_out) return -1;
+    if (K < 1 || N < 1 || n0 < 0 || n1 < n0 || n1 > N) return -1;
+    if (!o->has_terrain) return -4;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int k = 0; k < K; ++k) {
+        double xi[13], J = (double)cost_in[k];
+        double td = INFINITY, sl = INFINITY, tilt = 0.0;
+        for (int q = 0; q < 13; ++q) xi[q] = (double)state_in[(size_t)q * K + k];
+        span_one(o, xi, &J, controls, K, k, n0, n1, finalize, o->round32, NULL, &td, &sl,
+                 &tilt);
+        if (td_margin) td_margin[k] = td;
+        if (slip_margin) slip_margin[k] = sl;
+        if (tilt_max) tilt_max[k] = tilt;
+        cost_out[k] = J;
+        for (int q = 0; q < 13; ++q) state_out[(size_t)q * K + k] = xi[q];
+    }
+    return 0;
+}
+
+void oracle_set_round32(oracle_ctx *o, int on)
+{
+    if (o) o->round32 = on != 0;
 }
 
 /* ------------------------------------------------------------- select ---- */

@@ -1,0 +1,49 @@
+"""Build libplan.so (HIP, gfx950) in-tree with hipcc."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libplan.so")
+SOURCES = ["rollout.hip", "select.hip", "plan_api.hip"]
+
+HIPCC_FLAGS = [
+    "--offload-arch=gfx950",
+    "-O3",
+    "-std=c++17",
+    "-fPIC",
+    # packed FP32 ops stay off: the scalar float code is compiled to plain VALU
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no implicit contraction: every fused multiply-add is written as fmaf, so
+    # all kernel variants evaluate identical arithmetic
+    "-ffp-contract=off",
+    "-Wall",
+]
+
+
+def build(verbose: bool = False, extra=None) -> str:
+    """Compile every HIP source and link the shared library; returns its path."""
+    objs = []
+    bdir = os.path.join(HERE, "_build")
+    os.makedirs(bdir, exist_ok=True)
+    for src in SOURCES:
+        obj = os.path.join(bdir, src.replace(".hip", ".o"))
+        cmd = ["hipcc", *HIPCC_FLAGS, *(extra or []), "-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        objs.append(obj)
+    tmp = LIB + ".tmp"
+    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose="-v" in sys.argv)

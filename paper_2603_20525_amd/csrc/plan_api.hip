@@ -1,0 +1,423 @@
+// Host side of the libplan C ABI (include/plan.h): argument validation,
+// workspace ownership, derived constants, kernel launches on the caller's
+// stream. No exception or abort crosses the ABI.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "../../include/plan.h"
+#include "plan_internal.h"
+
+using plan::RolloutArgs;
+using plan::SelectOut;
+
+struct plan_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    plan_vehicle_t veh{};
+    plan_cost_t cost{};
+    plan_integ_t integ{};
+    int max_K = 0, max_N = 0, max_W = 0, max_H = 0;
+    // terrain texels
+    float4 *tex = nullptr;
+    int W = 0, H = 0;
+    float x0 = 0, y0 = 0, res = 0;
+    bool has_terrain = false;
+    int *bad_dev = nullptr;
+    int *bad_host = nullptr;  // pinned
+    // selection workspace
+    unsigned long long *part_keys = nullptr;
+    unsigned int *counters = nullptr;  // [0] argmin ticket, [1] softmin ticket
+    float *wpart = nullptr;
+    SelectOut *sel_dev = nullptr;
+    SelectOut *sel_host = nullptr;  // pinned
+    // launch shape
+    int lanes_opt = 0, block_opt = 0;
+    int last_lanes = 0, last_block = 0;
+    // timing
+    bool timing = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool ev_recorded = false;
+    std::string err;
+};
+
+static thread_local std::string g_create_err;
+
+static plan_status_t fail(plan_ctx *c, plan_status_t st, const char *fmt, const char *a = "") {
+    char buf[512];
+    snprintf(buf, sizeof buf, fmt, a);
+    if (c)
+        c->err = buf;
+    else
+        g_create_err = buf;
+    return st;
+}
+
+static plan_status_t hip_fail(plan_ctx *c, const char *what, hipError_t e) {
+    char buf[512];
+    snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+    if (c)
+        c->err = buf;
+    else
+        g_create_err = buf;
+    return PLAN_EDEVICE;
+}
+
+#define HIP_TRY(ctx, call)                                         \
+    do {                                                           \
+        hipError_t e__ = (call);                                   \
+        if (e__ != hipSuccess) return hip_fail((ctx), #call, e__); \
+    } while (0)
+
+static bool finite_all(const float *p, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!isfinite(p[i])) return false;
+    return true;
+}
+
+static bool valid_vehicle(const plan_vehicle_t &v) {
+    if (!finite_all(&v.M, sizeof(plan_vehicle_t) / sizeof(float))) return false;
+    return v.M > 0 && v.Jxx > 0 && v.Jyy > 0 && v.Jzz > 0 && v.Lf + v.Lr > 0 && v.e > 0 &&
+           v.hR > 0 && v.mu > 0 && v.g > 0 && v.delta_max >= 0 && v.delta_rate_max >= 0;
+}
+
+static bool valid_cost(const plan_cost_t &c) {
+    return finite_all(&c.w_t, sizeof(plan_cost_t) / sizeof(float)) && c.goal_r >= 0;
+}
+
+static bool valid_integ(const plan_integ_t &i) {
+    return isfinite(i.dt) && i.dt > 0 && i.substeps >= 1 && isfinite(i.accel_max) &&
+           isfinite(i.vx_min);
+}
+
+// ESM on level ground, M g (R_bar - (h+R)), in double.
+static double esm_level(const plan_vehicle_t &v) {
+    const double hR = v.hR, he = 0.5 * (double)v.e;
+    return (double)v.M * v.g * (sqrt(hR * hR + he * he) - hR);
+}
+
+static void release(plan_ctx *c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(c->tex);
+    (void)hipFree(c->bad_dev);
+    (void)hipFree(c->part_keys);
+    (void)hipFree(c->counters);
+    (void)hipFree(c->wpart);
+    (void)hipFree(c->sel_dev);
+    if (c->sel_host) (void)hipHostFree(c->sel_host);
+    if (c->bad_host) (void)hipHostFree(c->bad_host);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+}
+
+extern "C" {
+
+plan_status_t plan_create(plan_ctx **out, const plan_vehicle_t *veh, const plan_cost_t *cost,
+                          const plan_integ_t *integ, int max_K, int max_N, int max_W, int max_H,
+                          void *hip_stream) {
+    if (!out || !veh || !cost || !integ) return fail(nullptr, PLAN_EINVAL, "NULL argument");
+    if (!valid_vehicle(*veh)) return fail(nullptr, PLAN_EINVAL, "invalid vehicle parameters");
+    if (!valid_cost(*cost)) return fail(nullptr, PLAN_EINVAL, "invalid cost parameters");
+    if (!valid_integ(*integ)) return fail(nullptr, PLAN_EINVAL, "invalid integration parameters");
+    if (max_K < 1 || max_N < 1 || max_W < 2 || max_H < 2)
+        return fail(nullptr, PLAN_EINVAL, "max sizes must be K,N >= 1 and W,H >= 2");
+    if ((long long)max_W * max_H > (1ll << 28))
+        return fail(nullptr, PLAN_EINVAL, "terrain grid too large");
+    if ((long long)max_K * 4 > 0x7fffffffll) return fail(nullptr, PLAN_EINVAL, "max_K too large");
+
+    plan_ctx *c = new (std::nothrow) plan_ctx;
+    if (!c) return fail(nullptr, PLAN_ENOMEM, "host allocation failed");
+    c->veh = *veh;
+    c->cost = *cost;
+    c->integ = *integ;
+    c->max_K = max_K;
+    c->max_N = max_N;
+    c->max_W = max_W;
+    c->max_H = max_H;
+    c->stream = (hipStream_t)hip_stream;
+    hipError_t e;
+#define CREATE_TRY(call)                                    \
+    do {                                                    \
+        e = (call);                                         \
+        if (e != hipSuccess) {                              \
+            hip_fail(nullptr, #call, e);                    \
+            release(c);                                     \
+            delete c;                                       \
+            return e == hipErrorOutOfMemory ? PLAN_ENOMEM : PLAN_EDEVICE; \
+        }                                                   \
+    } while (0)
+    CREATE_TRY(hipGetDevice(&c->device));
+    CREATE_TRY(hipMalloc(&c->tex, sizeof(float4) * (size_t)max_W * max_H));
+    CREATE_TRY(hipMalloc(&c->bad_dev, sizeof(int)));
+    CREATE_TRY(hipHostMalloc(&c->bad_host, sizeof(int), hipHostMallocDefault));
+    const int nb = plan::select_blocks(max_K);
+    CREATE_TRY(hipMalloc(&c->part_keys, sizeof(unsigned long long) * nb));
+    CREATE_TRY(hipMalloc(&c->counters, sizeof(unsigned int) * 4));
+    CREATE_TRY(hipMemset(c->counters, 0, sizeof(unsigned int) * 4));
+    const size_t wsz = (size_t)plan::softmin_chunks(max_K) * (2 * (size_t)max_N + 1);
+    CREATE_TRY(hipMalloc(&c->wpart, sizeof(float) * wsz));
+    CREATE_TRY(hipMalloc(&c->sel_dev, sizeof(SelectOut)));
+    CREATE_TRY(hipHostMalloc(&c->sel_host, sizeof(SelectOut), hipHostMallocDefault));
+    CREATE_TRY(hipEventCreate(&c->ev0));
+    CREATE_TRY(hipEventCreate(&c->ev1));
+    CREATE_TRY(hipDeviceSynchronize());
+#undef CREATE_TRY
+    *out = c;
+    return PLAN_OK;
+}
+
+plan_status_t plan_set_stream(plan_ctx *c, void *hip_stream) {
+    if (!c) return PLAN_EINVAL;
+    c->stream = (hipStream_t)hip_stream;
+    return PLAN_OK;
+}
+
+plan_status_t plan_set_cost(plan_ctx *c, const plan_cost_t *cost) {
+    if (!c) return PLAN_EINVAL;
+    if (!cost || !valid_cost(*cost)) return fail(c, PLAN_EINVAL, "invalid cost parameters");
+    c->cost = *cost;
+    return PLAN_OK;
+}
+
+plan_status_t plan_set_terrain(plan_ctx *c, const float *height_dev, int W, int H, float x0,
+                               float y0, float res, const float *costmap_dev) {
+    if (!c) return PLAN_EINVAL;
+    if (!height_dev) return fail(c, PLAN_EINVAL, "height is NULL");
+    if (W < 2 || H < 2 || W > c->max_W || H > c->max_H)
+        return fail(c, PLAN_EINVAL, "terrain size outside [2, max] in W or H");
+    if (!(res > 0) || !isfinite(res) || !isfinite(x0) || !isfinite(y0))
+        return fail(c, PLAN_EINVAL, "terrain origin/resolution invalid");
+    HIP_TRY(c, hipSetDevice(c->device));
+    c->has_terrain = false;
+    HIP_TRY(c, hipMemsetAsync(c->bad_dev, 0, sizeof(int), c->stream));
+    HIP_TRY(c, plan::launch_pack_terrain(height_dev, costmap_dev, W, H, 1.0f / res, c->tex,
+                                         c->bad_dev, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->bad_host, c->bad_dev, sizeof(int), hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (*c->bad_host) return fail(c, PLAN_EINVAL, "terrain holds non-finite values");
+    c->W = W;
+    c->H = H;
+    c->x0 = x0;
+    c->y0 = y0;
+    c->res = res;
+    c->has_terrain = true;
+    return PLAN_OK;
+}
+
+static void auto_launch(int K, int *lanes, int *block) {
+    // Spread small candidate sets over more lanes (wheel-parallel); large
+    // sets use one lane per candidate to avoid redundant chassis work.
+    if (K <= 16384) {
+        *lanes = 4;
+    } else if (K <= 65536) {
+        *lanes = 2;
+    } else {
+        *lanes = 1;
+    }
+    const long long waves = ((long long)K * *lanes + 63) / 64;
+    *block = (waves < 4096) ? 64 : 256;
+}
+
+// Derived constants of one launch (double on the host, rounded once).
+static void fill_args(const plan_ctx *c, RolloutArgs &a) {
+    const plan_vehicle_t &v = c->veh;
+    const plan_cost_t &co = c->cost;
+    const plan_integ_t &in = c->integ;
+    memset(&a, 0, sizeof a);
+    const double L = (double)v.Lf + v.Lr;
+    a.invM = (float)(1.0 / v.M);
+    a.invJxx = (float)(1.0 / v.Jxx);
+    a.invJyy = (float)(1.0 / v.Jyy);
+    a.invJzz = (float)(1.0 / v.Jzz);
+    a.dJyz = (float)((double)v.Jyy - v.Jzz);
+    a.dJxz = (float)((double)v.Jxx - v.Jzz);
+    a.dJxy = (float)((double)v.Jxx - v.Jyy);
+    a.Lf = v.Lf;
+    a.Lr = v.Lr;
+    a.half_e = 0.5f * v.e;
+    a.hR = v.hR;
+    a.kf = v.kf;
+    a.kr = v.kr;
+    a.bf = v.bf;
+    a.br = v.br;
+    a.Fsf = (float)(0.5 * v.g * v.M * v.Lr / L);
+    a.Fsr = (float)(0.5 * v.g * v.M * v.Lf / L);
+    a.Mhalf = 0.5f * v.M;
+    a.C = v.C;
+    a.mu = v.mu;
+    a.mu2 = v.mu * v.mu;
+    a.delta_max = v.delta_max;
+    a.drate_max = v.delta_rate_max;
+    a.g = v.g;
+    const double he = 0.5 * (double)v.e;
+    a.MgRbar = (float)((double)v.M * v.g * sqrt((double)v.hR * v.hR + he * he));
+    a.phibar = (float)atan(2.0 * v.hR / v.e);
+    a.w_t = co.w_t;
+    a.w_c = co.w_c;
+    a.w_g = co.w_g;
+    a.goal_x = co.goal_x;
+    a.goal_y = co.goal_y;
+    a.goal_r2 = (float)((double)co.goal_r * co.goal_r);
+    a.sigma = co.sigma;
+    const double eps = (co.eps_esm > 0) ? (double)co.eps_esm : 0.1 * esm_level(v);
+    a.inv_eps_esm = (float)(1.0 / eps);
+    a.h = (float)((double)in.dt / in.substeps);
+    a.S = in.substeps;
+    a.accel_max = in.accel_max;
+    a.vx_min = in.vx_min;
+    a.tex = c->tex;
+    a.W = c->W;
+    a.H = c->H;
+    a.x0 = c->x0;
+    a.y0 = c->y0;
+    a.inv_res = (float)(1.0 / c->res);
+    a.umax = (float)(c->W - 1);
+    a.vmax = (float)(c->H - 1);
+}
+
+static plan_status_t launch(plan_ctx *c, RolloutArgs &a, bool chunk) {
+    int lanes, block;
+    auto_launch(a.K, &lanes, &block);
+    if (c->lanes_opt) lanes = c->lanes_opt;
+    if (c->block_opt) block = c->block_opt;
+    c->last_lanes = lanes;
+    c->last_block = block;
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (c->timing) HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
+    HIP_TRY(c, plan::launch_rollout(a, lanes, block, chunk, c->stream));
+    if (c->timing) {
+        HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
+        c->ev_recorded = true;
+    }
+    return PLAN_OK;
+}
+
+plan_status_t plan_rollout(plan_ctx *c, const float state0[13], const float *controls_dev, int K,
+                           int N, float *cost_dev, float *final_state_dev) {
+    if (!c) return PLAN_EINVAL;
+    if (!state0 || !controls_dev || !cost_dev) return fail(c, PLAN_EINVAL, "NULL argument");
+    if (K < 1 || K > c->max_K) return fail(c, PLAN_EINVAL, "K outside [1, max_K]");
+    if (N < 1 || N > c->max_N) return fail(c, PLAN_EINVAL, "N outside [1, max_N]");
+    if (!finite_all(state0, 13)) return fail(c, PLAN_EINVAL, "state0 not finite");
+    if (!c->has_terrain) return fail(c, PLAN_ENOTERRAIN, "no terrain set");
+    RolloutArgs a;
+    fill_args(c, a);
+    for (int q = 0; q < 13; ++q) a.s0[q] = state0[q];
+    a.controls = controls_dev;
+    a.K = K;
+    a.N = N;
+    a.n0 = 0;
+    a.n1 = N;
+    a.finalize = 1;
+    a.cost = cost_dev;
+    a.final_state = final_state_dev;
+    return launch(c, a, false);
+}
+
+plan_status_t plan_init_state(plan_ctx *c, const float state0[13], float *state_dev,
+                              float *cost_dev, int K) {
+    if (!c) return PLAN_EINVAL;
+    if (!state0 || !state_dev || !cost_dev) return fail(c, PLAN_EINVAL, "NULL argument");
+    if (K < 1 || K > c->max_K) return fail(c, PLAN_EINVAL, "K outside [1, max_K]");
+    if (!finite_all(state0, 13)) return fail(c, PLAN_EINVAL, "state0 not finite");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, plan::launch_init_state(state0, state_dev, cost_dev, K, c->stream));
+    return PLAN_OK;
+}
+
+plan_status_t plan_rollout_chunk(plan_ctx *c, float *state_dev, float *cost_dev,
+                                 const float *controls_dev, int K, int N, int n0, int n1,
+                                 int finalize) {
+    if (!c) return PLAN_EINVAL;
+    if (!state_dev || !cost_dev || !controls_dev) return fail(c, PLAN_EINVAL, "NULL argument");
+    if (K < 1 || K > c->max_K) return fail(c, PLAN_EINVAL, "K outside [1, max_K]");
+    if (N < 1 || N > c->max_N) return fail(c, PLAN_EINVAL, "N outside [1, max_N]");
+    if (n0 < 0 || n1 < n0 || n1 > N) return fail(c, PLAN_EINVAL, "need 0 <= n0 <= n1 <= N");
+    if (!c->has_terrain) return fail(c, PLAN_ENOTERRAIN, "no terrain set");
+    RolloutArgs a;
+    fill_args(c, a);
+    a.controls = controls_dev;
+    a.K = K;
+    a.N = N;
+    a.n0 = n0;
+    a.n1 = n1;
+    a.finalize = finalize != 0;
+    a.cost = cost_dev;
+    a.state = state_dev;
+    return launch(c, a, true);
+}
+
+plan_status_t plan_select(plan_ctx *c, int mode, float lambda, const float *controls_dev,
+                          const float *cost_dev, int K, int N, int *best_k, float *best_cost,
+                          float *plan_dev) {
+    if (!c) return PLAN_EINVAL;
+    if (!controls_dev || !cost_dev || !plan_dev) return fail(c, PLAN_EINVAL, "NULL argument");
+    if (K < 1 || K > c->max_K) return fail(c, PLAN_EINVAL, "K outside [1, max_K]");
+    if (N < 1 || N > c->max_N) return fail(c, PLAN_EINVAL, "N outside [1, max_N]");
+    if (mode != PLAN_ARGMIN && mode != PLAN_SOFTMIN) return fail(c, PLAN_EINVAL, "bad mode");
+    if (mode == PLAN_SOFTMIN && !(lambda > 0 && isfinite(lambda)))
+        return fail(c, PLAN_EINVAL, "softmin needs a finite lambda > 0");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, plan::launch_select(mode, lambda, controls_dev, cost_dev, K, N,
+                                   c->veh.delta_rate_max, plan_dev, c->part_keys, c->counters,
+                                   c->wpart, c->sel_dev, c->stream));
+    if (best_k || best_cost) {
+        HIP_TRY(c, hipMemcpyAsync(c->sel_host, c->sel_dev, sizeof(SelectOut),
+                                  hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        if (best_k) *best_k = c->sel_host->best_k;
+        if (best_cost) *best_cost = c->sel_host->best_cost;
+    }
+    return PLAN_OK;
+}
+
+plan_status_t plan_set_launch(plan_ctx *c, int lanes, int block) {
+    if (!c) return PLAN_EINVAL;
+    if (!(lanes == 0 || lanes == 1 || lanes == 2 || lanes == 4))
+        return fail(c, PLAN_EINVAL, "lanes must be 0, 1, 2 or 4");
+    if (!(block == 0 || block == 64 || block == 256))
+        return fail(c, PLAN_EINVAL, "block must be 0, 64 or 256");
+    c->lanes_opt = lanes;
+    c->block_opt = block;
+    return PLAN_OK;
+}
+
+plan_status_t plan_get_launch(const plan_ctx *c, int *lanes, int *block) {
+    if (!c || !lanes || !block) return PLAN_EINVAL;
+    *lanes = c->last_lanes;
+    *block = c->last_block;
+    return PLAN_OK;
+}
+
+plan_status_t plan_enable_timing(plan_ctx *c, int on) {
+    if (!c) return PLAN_EINVAL;
+    c->timing = on != 0;
+    c->ev_recorded = false;
+    return PLAN_OK;
+}
+
+plan_status_t plan_last_rollout_ms(plan_ctx *c, float *ms) {
+    if (!c || !ms) return PLAN_EINVAL;
+    if (!c->ev_recorded) return fail(c, PLAN_EINVAL, "no timed rollout recorded");
+    HIP_TRY(c, hipEventSynchronize(c->ev1));
+    HIP_TRY(c, hipEventElapsedTime(ms, c->ev0, c->ev1));
+    return PLAN_OK;
+}
+
+void plan_destroy(plan_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    release(c);
+    delete c;
+}
+
+const char *plan_last_error(const plan_ctx *c) {
+    return c ? c->err.c_str() : g_create_err.c_str();
+}
+
+}  // extern "C"

@@ -176,9 +176,11 @@ def fbm_berm_terrain(seed: int, n: int = 512, res: float = 0.1, berms=True,
 
 
 def side_slope_terrain(seed: int, n: int = 2048, res: float = 0.05,
-                       track: float = 1.5) -> Terrain:
+                       track: float = 1.5, berm_sigma: float = 1.0) -> Terrain:
     """Alternating 15 degree cross slopes (sign flips every 10 m along x with a
-    tanh blend), 0.5 m berms about every 15 m, two 0.3 m ruts one track apart."""
+    tanh blend), 0.5 m berms about every 15 m (Gaussian profile, sigma 1 m:
+    steepest flank about 17 degrees, so a 20 m/s vehicle is launched but not
+    thrown), two 0.3 m ruts one track apart."""
     rng = np.random.default_rng(seed)
     X, Y = np.meshgrid(res * np.arange(n), res * np.arange(n))
     yc = n * res / 2.0
@@ -191,7 +193,7 @@ def side_slope_terrain(seed: int, n: int = 2048, res: float = 0.05,
     x = 5.0
     while x < n * res - 5.0:
         x += rng.uniform(12.0, 18.0)
-        h += gaussian_ridge(X, Y, x, yc, rng.uniform(-30, 30), 0.5, 0.4)
+        h += gaussian_ridge(X, Y, x, yc, rng.uniform(-30, 30), 0.5, berm_sigma)
     for yr in (yc - track / 2.0, yc + track / 2.0):
         h -= 0.3 * np.exp(-((Y - yr) ** 2) / (2.0 * 0.3 * 0.3))
     return Terrain(h.astype(np.float32), 0.0, 0.0, res)

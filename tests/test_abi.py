@@ -1,0 +1,85 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/plan.h declares, and rejects invalid arguments before touching the
+device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2603_20525_amd import inputs
+from paper_2603_20525_amd import plan as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "plan.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(plan_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(P.LIB_PATH):
+        from paper_2603_20525_amd import build
+        build.build()
+    return P.lib()
+
+
+def test_header_declares_the_binding_surface():
+    assert _declared() == sorted(P.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+    # nothing of the oracle is linked into the product library
+    out = os.popen(f"nm -D --defined-only {P.LIB_PATH}").read()
+    assert "oracle_" not in out
+    for name in _declared():
+        assert re.search(rf"\bT {name}\b", out), name
+
+
+def test_create_rejects_invalid_arguments_without_a_device(lib):
+    v = P._struct(P.Vehicle, inputs.WORKLOAD_VEHICLE)
+    c = P._struct(P.Cost, inputs.BASE_COST)
+    i = P._struct(P.Integ, inputs.BASE_INTEG)
+    h = C.c_void_p()
+    assert lib.plan_create(None, C.byref(v), C.byref(c), C.byref(i), 8, 8, 8, 8, None) == P.PLAN_EINVAL
+    assert lib.plan_create(C.byref(h), None, C.byref(c), C.byref(i), 8, 8, 8, 8, None) == P.PLAN_EINVAL
+    assert "NULL" in P.plan_last_error(None)
+    bad = P._struct(P.Vehicle, dict(inputs.WORKLOAD_VEHICLE, M=-1.0))
+    assert lib.plan_create(C.byref(h), C.byref(bad), C.byref(c), C.byref(i), 8, 8, 8, 8, None) == P.PLAN_EINVAL
+    assert "vehicle" in P.plan_last_error(None)
+    nan = P._struct(P.Vehicle, dict(inputs.WORKLOAD_VEHICLE, Jzz=float("nan")))
+    assert lib.plan_create(C.byref(h), C.byref(nan), C.byref(c), C.byref(i), 8, 8, 8, 8, None) == P.PLAN_EINVAL
+    bi = P._struct(P.Integ, dict(inputs.BASE_INTEG, substeps=0))
+    assert lib.plan_create(C.byref(h), C.byref(v), C.byref(c), C.byref(bi), 8, 8, 8, 8, None) == P.PLAN_EINVAL
+    bi = P._struct(P.Integ, dict(inputs.BASE_INTEG, dt=0.0))
+    assert lib.plan_create(C.byref(h), C.byref(v), C.byref(c), C.byref(bi), 8, 8, 8, 8, None) == P.PLAN_EINVAL
+    for sizes in ((0, 8, 8, 8), (8, 0, 8, 8), (8, 8, 1, 8), (8, 8, 8, 1)):
+        assert lib.plan_create(C.byref(h), C.byref(v), C.byref(c), C.byref(i), *sizes, None) == P.PLAN_EINVAL
+    assert not h.value
+
+
+def test_calls_on_null_context_are_rejected(lib):
+    s0 = (C.c_float * 13)()
+    assert lib.plan_rollout(None, s0, None, 1, 1, None, None) == P.PLAN_EINVAL
+    assert lib.plan_select(None, 0, 0.0, None, None, 1, 1, None, None, None) == P.PLAN_EINVAL
+    assert lib.plan_set_terrain(None, None, 2, 2, 0.0, 0.0, 1.0, None) == P.PLAN_EINVAL
+    assert lib.plan_set_launch(None, 4, 64) == P.PLAN_EINVAL
+    assert lib.plan_set_stream(None, None) == P.PLAN_EINVAL
+    assert lib.plan_set_cost(None, None) == P.PLAN_EINVAL
+    assert lib.plan_enable_timing(None, 1) == P.PLAN_EINVAL
+    lib.plan_destroy(None)
+
+
+def test_package_has_no_oracle_or_cpu_fallback():
+    pkg = os.path.join(ROOT, "paper_2603_20525_amd")
+    for dp, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dp, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f
+                assert "liboracle" not in txt, f
