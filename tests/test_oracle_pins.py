@@ -621,3 +621,42 @@ def test_steering_rate_cost_is_quadratic():
         J, fs, _ = o.rollout(s0, u)
         Phi = 15.0 * math.hypot(500.0 - fs[0, 0], fs[1, 0])
         assert J[0] - Phi == pytest.approx(N * 0.02 * (5.0 + 8.0 * rate * rate), rel=1e-9)
+
+
+def test_span_rollout_matches_full_rollout():
+    """The resumable span form runs the same steps: from broadcast state0
+    over [0, N) it equals the plain rollout bit for bit, and with float32
+    state storage the chunked and unchunked runs agree bit for bit."""
+    w = inputs.c1(K=32, N=30)
+    o = oracle.Oracle(w.vehicle, w.cost, w.integ)
+    o.set_terrain(w.terrain.height, w.terrain.x0, w.terrain.y0, w.terrain.res)
+    J, F, _ = o.rollout(w.state0, w.controls)
+    s = np.repeat(w.state0[:, None], w.K, axis=1)
+    F2, J2 = o.rollout_span(s, np.zeros(w.K, np.float32), w.controls, 0, w.N, True)
+    np.testing.assert_array_equal(J2, J)
+    np.testing.assert_array_equal(F2, F)
+    o.set_round32(True)
+    J32, F32, _ = o.rollout(w.state0, w.controls)
+    sc, cc = s.copy(), np.zeros(w.K, np.float32)
+    for n0, n1 in ((0, 11), (11, 12), (12, 30)):
+        so, co = o.rollout_span(sc, cc, w.controls, n0, n1, n1 == w.N)
+        sc, cc = so.astype(np.float32), co.astype(np.float32)
+    o.set_round32(False)
+    np.testing.assert_array_equal(so, F32)
+    np.testing.assert_array_equal(co, J32)
+
+
+def test_discontinuity_margins_flag_touchdown_and_rollover():
+    v = _veh()
+    o = _oracle(v)
+    K = 1
+    # a wheel-set landing: start just above the liftoff height, falling
+    Fs_r = v["g"] / 2 * v["M"] * v["Lf"] / (v["Lf"] + v["Lr"])
+    z_lift = v["hR"] + Fs_r / v["kr"]
+    s = state(z=z_lift + 0.002, v=(5.0, 0.0, -1.0)).astype(np.float32)[:, None]
+    u = np.zeros((3, 2, K), np.float32)
+    _, _, td, sl, tilt = o.rollout_span(s, np.zeros(K, np.float32), u, 0, 3, False, margins=True)
+    assert td[0] < 0.05 and sl[0] > 1.0 and tilt[0] < 0.01
+    s2 = state(z=5.0, ph=1.4).astype(np.float32)[:, None]
+    _, _, td, sl, tilt = o.rollout_span(s2, np.zeros(K, np.float32), u, 0, 1, False, margins=True)
+    assert tilt[0] == pytest.approx(1.4, rel=1e-6) and np.isinf(td[0])
