@@ -97,6 +97,7 @@ def lib():
                                     C.c_int, ip, dp, dp]
         L.oracle_rollout_span.argtypes = [vp, fp, fp, fp, C.c_int, C.c_int, C.c_int,
                                           C.c_int, C.c_int, dp, dp, dp, dp, dp]
+        L.oracle_rollout_d.argtypes = [vp, dp, dp, C.c_int, C.c_int, dp, dp]
         L.oracle_set_round32.argtypes = [vp, C.c_int]
         L.oracle_set_round32.restype = None
         _lib = L
@@ -202,6 +203,36 @@ class Oracle:
         if rc != 0:
             raise RuntimeError(f"oracle_rollout_span failed ({rc})")
         return (so, co, td, sl, tl) if margins else (so, co)
+
+    def rollout_d(self, state0, controls):
+        """Double-precision inputs: state0 [13], controls [N][2][K]. Returns
+        (cost [K], final_state [13][K])."""
+        s0 = np.ascontiguousarray(state0, dtype=np.float64)
+        u = np.ascontiguousarray(controls, dtype=np.float64)
+        N, _, K = u.shape
+        cost = np.zeros(K)
+        fs = np.zeros((13, K))
+        rc = lib().oracle_rollout_d(self._h, _ptr(s0, C.c_double), _ptr(u, C.c_double), K, N,
+                                    _ptr(cost, C.c_double), _ptr(fs, C.c_double))
+        if rc != 0:
+            raise RuntimeError(f"oracle_rollout_d failed ({rc})")
+        return cost, fs
+
+    def fd_grad(self, state0, controls, k, entries, step=1e-6):
+        """FP64 central differences dJ_k/du[n][c] for (n, c) in entries, with
+        the one-sided differences (for detecting a kink in between)."""
+        u = np.ascontiguousarray(controls[:, :, k:k + 1], dtype=np.float64)
+        s0 = np.asarray(state0, dtype=np.float64)
+        cols = []
+        for n, c in entries:
+            up, dn = u.copy(), u.copy()
+            up[n, c, 0] += step
+            dn[n, c, 0] -= step
+            cols += [up, dn]
+        U = np.concatenate([u] + cols, axis=2)
+        J, _ = self.rollout_d(s0, U)
+        J0, Jp, Jm = J[0], J[1::2], J[2::2]
+        return (Jp - Jm) / (2 * step), (Jp - J0) / step, (J0 - Jm) / step
 
     def set_round32(self, on: bool):
         """Conditioning probe: round state and running cost to float after each step."""

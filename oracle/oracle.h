@@ -121,6 +121,12 @@ int oracle_rollout_span(const oracle_ctx *o, const float *state_in, const float 
                         double *state_out, double *cost_out, double *td_margin,
                         double *slip_margin, double *tilt_max);
 
+/* As oracle_rollout with a double initial state and double controls
+ * [N][2][K] (for finite-difference derivatives with steps below float
+ * resolution). */
+int oracle_rollout_d(const oracle_ctx *o, const double state0[13], const double *controls,
+                     int K, int N, double *cost, double *final_state);
+
 /* Conditioning probe (off by default): when on, rollouts round the state and
  * the running cost to float after every Euler step, while computing in
  * double. Comparing with the plain double run shows how far float storage

@@ -414,8 +414,16 @@ static void discontinuity_margins(const oracle_ctx *o, const oracle_diag *d,
     }
 }
 
+/* Control u[n][c] of candidate k, from the float array or, when given, the
+ * double one. */
+static double control_at(const float *cf, const double *cd, int K, int k, int n, int c)
+{
+    size_t q = ((size_t)n * 2 + c) * K + k;
+    return cd ? cd[q] : (double)cf[q];
+}
+
 static void span_one(const oracle_ctx *o, double xi[13], double *J_io,
-                     const float *controls, int K, int k, int n0, int n1,
+                     const float *controls, const double *controls_d, int K, int k, int n0, int n1,
                      int finalize, int round32, int *exit_out, double *td, double *sl,
                      double *tilt)
 {
@@ -428,8 +436,8 @@ static void span_one(const oracle_ctx *o, double xi[13], double *J_io,
     for (int n = n0; n < n1 && !done; ++n) {
         /* zero-order hold: control n applies for the whole interval; the
          * sampled controls are restricted to the admissible set */
-        double u0 = (double)controls[((size_t)n * 2 + 0) * K + k];
-        double u1 = (double)controls[((size_t)n * 2 + 1) * K + k];
+        double u0 = control_at(controls, controls_d, K, k, n, 0);
+        double u1 = control_at(controls, controls_d, K, k, n, 1);
         double delta_dot = clampd(u0, -o->v.delta_rate_max, o->v.delta_rate_max);
         double vx_dot = o->in.accel_max * clampd(u1, -1.0, 1.0);
         for (int s = 0; s < S; ++s) {
@@ -473,7 +481,7 @@ int oracle_rollout(const oracle_ctx *o, const float state0[13],
         double xi[13], J = 0.0;
         int ex;
         for (int q = 0; q < 13; ++q) xi[q] = (double)state0[q];
-        span_one(o, xi, &J, controls, K, k, 0, N, 1, o->round32, &ex, NULL, NULL, NULL);
+        span_one(o, xi, &J, controls, NULL, K, k, 0, N, 1, o->round32, &ex, NULL, NULL, NULL);
         cost[k] = J;
         if (final_state)
             for (int q = 0; q < 13; ++q) final_state[(size_t)q * K + k] = xi[q];
@@ -495,13 +503,30 @@ int oracle_rollout_span(const oracle_ctx *o, const float *state_in, const float 
         double xi[13], J = (double)cost_in[k];
         double td = INFINITY, sl = INFINITY, tilt = 0.0;
         for (int q = 0; q < 13; ++q) xi[q] = (double)state_in[(size_t)q * K + k];
-        span_one(o, xi, &J, controls, K, k, n0, n1, finalize, o->round32, NULL, &td, &sl,
+        span_one(o, xi, &J, controls, NULL, K, k, n0, n1, finalize, o->round32, NULL, &td, &sl,
                  &tilt);
         if (td_margin) td_margin[k] = td;
         if (slip_margin) slip_margin[k] = sl;
         if (tilt_max) tilt_max[k] = tilt;
         cost_out[k] = J;
         for (int q = 0; q < 13; ++q) state_out[(size_t)q * K + k] = xi[q];
+    }
+    return 0;
+}
+
+int oracle_rollout_d(const oracle_ctx *o, const double state0[13], const double *controls,
+                     int K, int N, double *cost, double *final_state)
+{
+    if (!o || !state0 || !controls || !cost || K < 1 || N < 1) return -1;
+    if (!o->has_terrain) return -4;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int k = 0; k < K; ++k) {
+        double xi[13], J = 0.0;
+        for (int q = 0; q < 13; ++q) xi[q] = state0[q];
+        span_one(o, xi, &J, NULL, controls, K, k, 0, N, 1, 0, NULL, NULL, NULL, NULL);
+        cost[k] = J;
+        if (final_state)
+            for (int q = 0; q < 13; ++q) final_state[(size_t)q * K + k] = xi[q];
     }
     return 0;
 }

@@ -660,3 +660,31 @@ def test_discontinuity_margins_flag_touchdown_and_rollover():
     s2 = state(z=5.0, ph=1.4).astype(np.float32)[:, None]
     _, _, td, sl, tilt = o.rollout_span(s2, np.zeros(K, np.float32), u, 0, 1, False, margins=True)
     assert tilt[0] == pytest.approx(1.4, rel=1e-6) and np.isinf(td[0])
+
+
+def test_double_control_rollout_matches_float_rollout():
+    w = inputs.c1(K=16, N=20)
+    o = oracle.Oracle(w.vehicle, w.cost, w.integ)
+    o.set_terrain(w.terrain.height, w.terrain.x0, w.terrain.y0, w.terrain.res)
+    J, F, _ = o.rollout(w.state0, w.controls)
+    Jd, Fd = o.rollout_d(w.state0.astype(np.float64), w.controls.astype(np.float64))
+    np.testing.assert_array_equal(Jd, J)
+    np.testing.assert_array_equal(Fd, F)
+
+
+def test_fd_gradient_of_steering_cost_on_flat_ground():
+    """On flat ground at low speed with no ESM or terrain cost, J depends on a
+    steering-rate entry through w_c h u^2 plus the path's terminal distance;
+    the terminal part vanishes for a goal straight ahead at first order, so
+    dJ/du[n][0] at u = 0 equals 0 and at u = a equals 2 w_c h a."""
+    v = _veh()
+    N = 10
+    o = _oracle(v, cost=_cost(goal_x=500.0, goal_y=0.0))
+    s0 = state(z=v["hR"], v=(2.0, 0, 0))
+    u = np.zeros((N, 2, 1))
+    u[3, 0, 0] = 0.25
+    g, gp, gm = o.fd_grad(s0, u, 0, [(3, 0), (5, 0)], step=1e-6)
+    # entry (5, 0): u = 0, symmetric: no first-order change of the quadratic
+    # cost; the path is bent by u[3] so the terminal term contributes ~1e-4
+    assert abs(g[1]) < 1e-2
+    assert g[0] == pytest.approx(2 * 8.0 * 0.02 * 0.25, abs=5e-3)
