@@ -100,6 +100,11 @@ def lib():
         L.oracle_rollout_d.argtypes = [vp, dp, dp, C.c_int, C.c_int, dp, dp]
         L.oracle_set_round32.argtypes = [vp, C.c_int]
         L.oracle_set_round32.restype = None
+        u64p = C.POINTER(C.c_uint64)
+        L.oracle_philox4x64.argtypes = [u64p, u64p, u64p]
+        L.oracle_philox4x64.restype = None
+        L.oracle_sample_controls.argtypes = [C.c_int, C.c_uint64, C.c_uint64, dp, C.c_int, fp,
+                                             C.c_int, C.c_int, dp]
         _lib = L
     return _lib
 
@@ -114,6 +119,32 @@ def _ptr(a, ct):
 
 def soft(sigma: float, eps: float, pi: float) -> float:
     return lib().oracle_soft(sigma, eps, pi)
+
+
+def philox4x64(counter, key):
+    """Philox4x64-10 block: four uint64 words for a 4-word counter, 2-word key."""
+    c = np.ascontiguousarray(counter, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    lib().oracle_philox4x64(_ptr(c, C.c_uint64), _ptr(k, C.c_uint64), _ptr(out, C.c_uint64))
+    return out
+
+
+SAMPLE_UNIFORM, SAMPLE_GAUSSIAN = 0, 1
+
+
+def sample_controls(kind, seed, stream, scale, K, N, nominal=None, keep_nominal=False):
+    """Candidate controls [N][2][K] (double) from the counter-based generator."""
+    sc = np.ascontiguousarray(scale, dtype=np.float64)
+    nom = None if nominal is None else _f32(nominal).reshape(N, 2)
+    out = np.zeros((N, 2, K))
+    rc = lib().oracle_sample_controls(int(kind), int(seed), int(stream), _ptr(sc, C.c_double),
+                                      int(bool(keep_nominal)),
+                                      None if nom is None else _ptr(nom, C.c_float),
+                                      int(K), int(N), _ptr(out, C.c_double))
+    if rc != 0:
+        raise ValueError("oracle_sample_controls rejected the arguments")
+    return out
 
 
 class Oracle:

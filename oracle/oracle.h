@@ -143,6 +143,21 @@ int oracle_select(const oracle_ctx *o, int mode, double lambda,
                   const float *controls, const float *cost, int K, int N,
                   int *best_k, double *best_cost, double *plan);
 
+/* Philox4x64-10 (Salmon et al., SC 2011): out = bijection of the 256-bit
+ * counter under the 128-bit key. */
+void oracle_philox4x64(const unsigned long long ctr[4], const unsigned long long key[2],
+                       unsigned long long out[4]);
+
+/* Candidate controls drawn from the counter-based generator: kind 0 uniform
+ * (nominal + scale * U(-1, 1) per channel), kind 1 Gaussian (nominal +
+ * scale * N(0, 1) by Box-Muller). Candidate k, interval n use word n mod 4
+ * of Philox4x64-10 at counter (k, n div 4, 0, 0), key (seed, stream).
+ * nominal is [N][2] float or NULL; keep_nominal makes candidate 0 the
+ * nominal. controls is [N][2][K] double. Returns 0 or -1. */
+int oracle_sample_controls(int kind, unsigned long long seed, unsigned long long stream,
+                           const double scale[2], int keep_nominal, const float *nominal,
+                           int K, int N, double *controls);
+
 #ifdef __cplusplus
 }
 #endif

@@ -42,6 +42,7 @@
 #include "oracle.h"
 
 #include <math.h>
+#include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -581,6 +582,94 @@ int oracle_select(const oracle_ctx *o, int mode, double lambda,
                 }
                 plan[n * 2 + ch] = num / den;
             }
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------ sampling ---- */
+/* The paper draws the candidate controls on the GPU with a counter-based
+ * generator ("Real-Time Implementation": the random samples are produced with
+ * cuRAND on the device; the published configuration draws the steering rate
+ * uniformly and holds the acceleration). The generator here is Philox4x64-10
+ * as defined by Salmon, Moraes, Dror and Shaw, "Parallel random numbers: as
+ * easy as 1, 2, 3" (SC 2011): ten rounds of two 64x64->128-bit products with
+ * the published multipliers, the halves crossed and xored with the key, the
+ * key advanced by the published Weyl increments between rounds. */
+void oracle_philox4x64(const unsigned long long ctr[4], const unsigned long long key[2],
+                       unsigned long long out[4])
+{
+    const uint64_t mul0 = 0xD2E7470EE14C6C93ull, mul1 = 0xCA5A826395121157ull;
+    const uint64_t weyl0 = 0x9E3779B97F4A7C15ull, weyl1 = 0xBB67AE8584CAA73Bull;
+    uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += weyl0;
+            k1 += weyl1;
+        }
+        unsigned __int128 p0 = (unsigned __int128)mul0 * c0;
+        unsigned __int128 p1 = (unsigned __int128)mul1 * c2;
+        uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+/* Controls [N][2][K] (double) for candidate k and interval n from the 64-bit
+ * word w = word (n mod 4) of Philox4x64-10 at counter (k, floor(n/4), 0, 0)
+ * and key (seed, stream). Two 24-bit integers are taken from w: a = bits
+ * 40..63 and b = bits 16..39.
+ *   kind 0 (uniform):  u_c = nominal_c + scale_c (2 x_c - 1), with
+ *                      x_0 = a 2^-24, x_1 = b 2^-24 (uniform on [0, 1));
+ *   kind 1 (Gaussian): Box-Muller (Box and Muller, 1958) on p = (a+1) 2^-24
+ *                      in (0, 1] and q = b 2^-24: r = sqrt(-2 ln p),
+ *                      u_0 = nominal_0 + scale_0 r cos(2 pi q),
+ *                      u_1 = nominal_1 + scale_1 r sin(2 pi q).
+ * nominal is [N][2] float or NULL (zeros). With keep_nominal, candidate 0 is
+ * the nominal itself. Returns 0, or -1 on invalid arguments. */
+int oracle_sample_controls(int kind, unsigned long long seed, unsigned long long stream,
+                           const double scale[2],
+                           int keep_nominal, const float *nominal, int K, int N,
+                           double *controls)
+{
+    if ((kind != 0 && kind != 1) || !scale || !controls || K < 1 || N < 1) return -1;
+    const double two_m24 = 1.0 / 16777216.0;
+    const double two_pi = 8.0 * atan(1.0);
+    const unsigned long long key[2] = {seed, stream};
+    for (int k = 0; k < K; ++k) {
+        for (int n = 0; n < N; ++n) {
+            double nom0 = nominal ? (double)nominal[2 * n] : 0.0;
+            double nom1 = nominal ? (double)nominal[2 * n + 1] : 0.0;
+            double u0 = nom0, u1 = nom1;
+            if (!(keep_nominal && k == 0)) {
+                const unsigned long long ctr[4] = {(unsigned long long)k,
+                                                   (unsigned long long)(n / 4), 0, 0};
+                unsigned long long words[4];
+                oracle_philox4x64(ctr, key, words);
+                uint64_t w = words[n % 4];
+                double a = (double)(w >> 40);
+                double b = (double)((w >> 16) & 0xFFFFFFull);
+                if (kind == 0) {
+                    u0 = nom0 + scale[0] * (2.0 * (a * two_m24) - 1.0);
+                    u1 = nom1 + scale[1] * (2.0 * (b * two_m24) - 1.0);
+                } else {
+                    double p = (a + 1.0) * two_m24;
+                    double q = b * two_m24;
+                    double r = sqrt(-2.0 * log(p));
+                    u0 = nom0 + scale[0] * r * cos(two_pi * q);
+                    u1 = nom1 + scale[1] * r * sin(two_pi * q);
+                }
+            }
+            controls[((size_t)n * 2 + 0) * K + k] = u0;
+            controls[((size_t)n * 2 + 1) * K + k] = u1;
         }
     }
     return 0;
