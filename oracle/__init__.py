@@ -41,7 +41,7 @@ class Vehicle(C.Structure):
 class Cost(C.Structure):
     _fields_ = [(n, C.c_double) for n in (
         "w_t", "w_c", "w_g", "goal_x", "goal_y", "goal_r", "sigma", "eps_esm",
-        "eps_dist")]
+        "eps_dist", "eps_ay")]
 
 
 class Integ(C.Structure):
@@ -60,6 +60,26 @@ class Diag(C.Structure):
         ("Fy_sum", C.c_double), ("Fz_sum", C.c_double), ("Mx", C.c_double),
         ("My", C.c_double), ("Mz", C.c_double), ("c_sum", C.c_double),
         ("U_esm", C.c_double), ("L", C.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = np.ctypeslib.as_array(v).copy() if hasattr(v, "_length_") else float(v)
+        return out
+
+
+class EstDiag(C.Structure):
+    _fields_ = [
+        ("phi", C.c_double), ("theta", C.c_double), ("z", C.c_double),
+        ("R", C.c_double * 3 * 3), ("gB", C.c_double * 3),
+        ("alpha_f", C.c_double), ("alpha_r", C.c_double),
+        ("Fz_f", C.c_double), ("Fz_r", C.c_double),
+        ("Fy_f", C.c_double), ("Fy_r", C.c_double),
+        ("Fz_wheel", C.c_double * 4), ("ax", C.c_double), ("ay", C.c_double),
+        ("pi_ay", C.c_double), ("a_bar_y", C.c_double),
+        ("P", C.c_double * 3 * 4), ("c_sum", C.c_double), ("L", C.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -100,6 +120,8 @@ def lib():
         L.oracle_rollout_d.argtypes = [vp, dp, dp, C.c_int, C.c_int, dp, dp]
         L.oracle_set_round32.argtypes = [vp, C.c_int]
         L.oracle_set_round32.restype = None
+        L.oracle_est_rhs.argtypes = [vp, dp, C.c_double, C.c_double, dp, C.POINTER(EstDiag)]
+        L.oracle_est_rollout.argtypes = [vp, fp, fp, C.c_int, C.c_int, dp, dp, ip]
         u64p = C.POINTER(C.c_uint64)
         L.oracle_philox4x64.argtypes = [u64p, u64p, u64p]
         L.oracle_philox4x64.restype = None
@@ -194,6 +216,34 @@ class Oracle:
 
     def esm(self, phi, theta):
         return lib().oracle_esm(self._h, float(phi), float(theta))
+
+    def est_rhs(self, xi, delta_dot, vx_dot):
+        """EST state derivative (7) and diagnostics."""
+        xi = np.ascontiguousarray(xi, dtype=np.float64)
+        out = np.zeros(7)
+        d = EstDiag()
+        rc = lib().oracle_est_rhs(self._h, _ptr(xi, C.c_double), float(delta_dot),
+                                  float(vx_dot), _ptr(out, C.c_double), C.byref(d))
+        if rc != 0:
+            raise RuntimeError("oracle_est_rhs failed (no terrain?)")
+        return out, d.as_dict()
+
+    def est_rollout(self, state0, controls):
+        """EST formulation: state0 [7] float32, controls [N][2][K] float32.
+        Returns (cost[K], final_state[7][K], exit_step[K])."""
+        s0 = _f32(state0)
+        u = _f32(controls)
+        N, two, K = u.shape
+        assert two == 2 and s0.shape == (7,)
+        cost = np.zeros(K)
+        fs = np.zeros((7, K))
+        ex = np.zeros(K, dtype=np.int32)
+        rc = lib().oracle_est_rollout(self._h, _ptr(s0, C.c_float), _ptr(u, C.c_float), K, N,
+                                      _ptr(cost, C.c_double), _ptr(fs, C.c_double),
+                                      _ptr(ex, C.c_int))
+        if rc != 0:
+            raise RuntimeError(f"oracle_est_rollout failed ({rc})")
+        return cost, fs, ex
 
     def rollout(self, state0, controls):
         """controls: [N][2][K] float32. Returns (cost[K], final_state[13][K], exit_step[K])."""

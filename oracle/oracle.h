@@ -42,6 +42,7 @@ typedef struct {
     double w_t, w_c, w_g;
     double goal_x, goal_y, goal_r;
     double sigma, eps_esm, eps_dist;
+    double eps_ay; /* lateral-acceleration normaliser; <= 0: 10 % of a_bar_y */
 } oracle_cost;
 
 /* Integration: dt is the zero-order-hold period of one control, substeps is
@@ -142,6 +143,40 @@ void oracle_set_round32(oracle_ctx *o, int on);
 int oracle_select(const oracle_ctx *o, int mode, double lambda,
                   const float *controls, const float *cost, int K, int N,
                   int *best_k, double *best_cost, double *plan);
+
+/* ---- extended single-track (EST) baseline formulation -------------------
+ * Paper: appendix "Extended Single-Track Vehicle Dynamics Model" (state
+ * eq. models:3dof:state, eqs. models:3dof:update / models:3dof:A, 1-2-3
+ * rotation, terrain normal at the CoM, slip angles, load transfer
+ * eqs. models:3dof:Fz_all / models:3dof:Fz_lon with the coefficients
+ * models:3dof:Kzzf..Kzy and accelerations models:3dof:abx / models:3dof:aby)
+ * and the lateral-acceleration soft constraint of "OCP Formulation"
+ * (pi_ay = |a_y - g_y| - a_bar_y, a_bar_y = M g / (2 K_zy)). State order:
+ * x, y, psi, v_y, omega_z, delta, v_x. */
+typedef struct {
+    double phi, theta;      /* roll and pitch from the normal under the CoM */
+    double z;               /* CoM height f + (h+R) cos(phi) cos(theta) */
+    double R[3][3];         /* 1-2-3 rotation W <- B */
+    double gB[3];
+    double alpha_f, alpha_r;
+    double Fz_f, Fz_r;      /* virtual-tire normal loads */
+    double Fy_f, Fy_r;
+    double Fz_wheel[4];     /* physical tires fl, fr, rl, rr */
+    double ax, ay;          /* CoM acceleration, body x and y */
+    double pi_ay, a_bar_y;
+    double P[4][3];         /* wheel contact points (costmap lookups) */
+    double c_sum, L;        /* costmap sum and running cost */
+} oracle_est_diag;
+
+/* EST state derivative (7) for state xi[7] and control (delta_dot, vx_dot).
+ * Returns 0, or -1 if no terrain is set. */
+int oracle_est_rhs(const oracle_ctx *o, const double xi[7], double delta_dot, double vx_dot,
+                   double xidot[7], oracle_est_diag *diag);
+
+/* EST formulation rollout: same controls layout, goal test, quadrature,
+ * clamps and +inf rule as oracle_rollout; final_state is [7][K]. */
+int oracle_est_rollout(const oracle_ctx *o, const float state0[7], const float *controls,
+                       int K, int N, double *cost, double *final_state, int *exit_step);
 
 /* Philox4x64-10 (Salmon et al., SC 2011): out = bijection of the 256-bit
  * counter under the 128-bit key. */

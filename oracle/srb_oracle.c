@@ -110,6 +110,11 @@ oracle_ctx *oracle_create(const oracle_vehicle *veh, const oracle_cost *cost,
          * cost at a 10 % safety factor). */
         o->c.eps_esm = 0.1 * oracle_esm(o, 0.0, 0.0);
     }
+    if (!(o->c.eps_ay > 0)) {
+        /* same 10 % safety factor on the lateral-acceleration boundary
+         * a_bar_y = M g / (2 K_zy) = g e / (2 (h+R)) */
+        o->c.eps_ay = 0.1 * o->v.g * o->v.e / (2.0 * o->v.hR);
+    }
     return o;
 }
 
@@ -583,6 +588,175 @@ int oracle_select(const oracle_ctx *o, int mode, double lambda,
                 plan[n * 2 + ch] = num / den;
             }
         }
+    }
+    return 0;
+}
+
+/* ----------------------------------------------------------- EST model ---- */
+
+int oracle_est_rhs(const oracle_ctx *o, const double xi[7], double delta_dot, double vx_dot,
+                   double xidot[7], oracle_est_diag *diag)
+{
+    if (!o || !o->has_terrain) return -1;
+    const oracle_vehicle *V = &o->v;
+
+    /* state vector eq. models:3dof:state */
+    double x = xi[0], y = xi[1], psi = xi[2];
+    double vy = xi[3], wz = xi[4], delta = xi[5], vx = xi[6];
+
+    /* roll and pitch: the chassis z axis is the terrain's unit upward normal
+     * under the CoM (the normal of z = f(x, y) is (-f_x, -f_y, 1)); under the
+     * 1-2-3 convention b_z = (sin th, -cos th sin ph, cos ph cos th) */
+    double T0[4];
+    oracle_sample_terrain(o, x, y, T0);
+    double nrm = sqrt(1.0 + T0[1] * T0[1] + T0[2] * T0[2]);
+    double n[3] = {-T0[1] / nrm, -T0[2] / nrm, 1.0 / nrm};
+    double th = asin(n[0]);
+    double ph = atan2(-n[1], n[2]);
+
+    /* 1-2-3 rotation W <- B, eq. app:models:3dof:rotation */
+    double cps = cos(psi), sps = sin(psi);
+    double cth = cos(th), sth = sin(th);
+    double cph = cos(ph), sph = sin(ph);
+    double R[3][3] = {
+        {cth * cps, -cth * sps, sth},
+        {cph * sps + cps * sph * sth, cph * cps - sph * sth * sps, -cth * sph},
+        {sph * sps - cph * cps * sth, cps * sph + cph * sth * sps, cph * cth},
+    };
+
+    /* planar body velocity (v_x, v_y, 0) and yaw-only angular velocity */
+    double vw0 = R[0][0] * vx + R[0][1] * vy;
+    double vw1 = R[1][0] * vx + R[1][1] * vy;
+
+    /* gravity in the body frame, R^T (0, 0, -g) */
+    double gB[3] = {-V->g * R[2][0], -V->g * R[2][1], -V->g * R[2][2]};
+
+    /* load-transfer coefficients, eqs. models:3dof:Kzzf .. models:3dof:Kzy */
+    double L = V->Lf + V->Lr;
+    double Kzz_f = V->M * V->Lr / L;
+    double Kzz_r = V->M * V->Lf / L;
+    double Kzx = V->M * V->hR / L;
+    double Kzy = V->M * V->hR / V->e;
+
+    /* longitudinal acceleration, eq. models:3dof:abx */
+    double ax = vx_dot - wz * vy;
+
+    /* virtual-tire normal loads, eq. models:3dof:Fz_lon */
+    double Fz_f = -Kzz_f * gB[2] - Kzx * ax;
+    double Fz_r = -Kzz_r * gB[2] + Kzx * ax;
+
+    /* slip angles of the virtual tires and sigmoid tire, eq. models:tire */
+    double alpha_f = atan((vy + wz * V->Lf) / vx) - delta;
+    double alpha_r = atan((vy - wz * V->Lr) / vx);
+    double Caf = V->C * alpha_f, Car = V->C * alpha_r;
+    double Fy_f = Fz_f * (-Caf * V->mu) / sqrt(V->mu * V->mu + Caf * Caf);
+    double Fy_r = Fz_r * (-Car * V->mu) / sqrt(V->mu * V->mu + Car * Car);
+
+    /* eq. models:3dof:A plus B zeta */
+    xidot[0] = vw0;
+    xidot[1] = vw1;
+    xidot[2] = wz;
+    xidot[3] = (Fy_f + Fy_r) / V->M + gB[1] - wz * vx;
+    xidot[4] = (Fy_f * V->Lf * cos(delta) - Fy_r * V->Lr) / V->Jzz;
+    xidot[5] = delta_dot;
+    xidot[6] = vx_dot;
+
+    /* lateral acceleration, eq. models:3dof:aby, and its soft constraint */
+    double ay = xidot[3] + wz * vx;
+    double a_bar_y = V->M * V->g / (2.0 * Kzy);
+    double pi_ay = fabs(ay - gB[1]) - a_bar_y;
+
+    /* wheel contact points for the costmap: CoM at height f + (h+R) b_z.w_z,
+     * wheels at the SRB lever arms rotated into the world frame */
+    double z = T0[0] + V->hR * R[2][2];
+    double rho[4][3] = {
+        {V->Lf, V->e / 2.0, -V->hR},
+        {V->Lf, -V->e / 2.0, -V->hR},
+        {-V->Lr, V->e / 2.0, -V->hR},
+        {-V->Lr, -V->e / 2.0, -V->hR},
+    };
+    double c_sum = 0.0, P[4][3];
+    for (int i = 0; i < 4; ++i) {
+        double p0[3] = {x, y, z};
+        for (int r = 0; r < 3; ++r)
+            P[i][r] = p0[r] + R[r][0] * rho[i][0] + R[r][1] * rho[i][1] + R[r][2] * rho[i][2];
+        double Ti[4];
+        oracle_sample_terrain(o, P[i][0], P[i][1], Ti);
+        c_sum += Ti[3];
+    }
+    double Lrun = o->c.w_t + o->c.w_c * delta_dot * delta_dot +
+                  oracle_soft(o->c.sigma, o->c.eps_ay, pi_ay) + c_sum;
+
+    if (diag) {
+        diag->phi = ph;
+        diag->theta = th;
+        diag->z = z;
+        for (int r = 0; r < 3; ++r)
+            for (int cc = 0; cc < 3; ++cc) diag->R[r][cc] = R[r][cc];
+        for (int r = 0; r < 3; ++r) diag->gB[r] = gB[r];
+        diag->alpha_f = alpha_f;
+        diag->alpha_r = alpha_r;
+        diag->Fz_f = Fz_f;
+        diag->Fz_r = Fz_r;
+        diag->Fy_f = Fy_f;
+        diag->Fy_r = Fy_r;
+        /* physical tires, eq. models:3dof:Fz_all */
+        double lat = Kzy * ay / (-V->M * gB[2]);
+        diag->Fz_wheel[0] = Fz_f * (0.5 - lat);
+        diag->Fz_wheel[1] = Fz_f * (0.5 + lat);
+        diag->Fz_wheel[2] = Fz_r * (0.5 - lat);
+        diag->Fz_wheel[3] = Fz_r * (0.5 + lat);
+        diag->ax = ax;
+        diag->ay = ay;
+        diag->pi_ay = pi_ay;
+        diag->a_bar_y = a_bar_y;
+        for (int i = 0; i < 4; ++i)
+            for (int r = 0; r < 3; ++r) diag->P[i][r] = P[i][r];
+        diag->c_sum = c_sum;
+        diag->L = Lrun;
+    }
+    return 0;
+}
+
+int oracle_est_rollout(const oracle_ctx *o, const float state0[7], const float *controls,
+                       int K, int N, double *cost, double *final_state, int *exit_step)
+{
+    if (!o || !state0 || !controls || !cost || K < 1 || N < 1) return -1;
+    if (!o->has_terrain) return -4;
+    const int S = o->in.substeps;
+    const double h = o->in.dt / S;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int k = 0; k < K; ++k) {
+        double xi[7], xd[7], J = 0.0;
+        int done = 0, ex = -1;
+        for (int q = 0; q < 7; ++q) xi[q] = (double)state0[q];
+        for (int n = 0; n < N && !done; ++n) {
+            double delta_dot = clampd((double)controls[((size_t)n * 2 + 0) * K + k],
+                                      -o->v.delta_rate_max, o->v.delta_rate_max);
+            double vx_dot = o->in.accel_max *
+                            clampd((double)controls[((size_t)n * 2 + 1) * K + k], -1.0, 1.0);
+            for (int s = 0; s < S; ++s) {
+                if (goal_distance(o, xi[0], xi[1]) <= o->c.goal_r) {
+                    done = 1;
+                    ex = n * S + s;
+                    break;
+                }
+                oracle_est_diag d;
+                oracle_est_rhs(o, xi, delta_dot, vx_dot, xd, &d);
+                J += h * d.L;
+                for (int q = 0; q < 7; ++q) xi[q] = xi[q] + h * xd[q];
+                xi[5] = clampd(xi[5], -o->v.delta_max, o->v.delta_max);
+                if (xi[6] < o->in.vx_min) xi[6] = o->in.vx_min;
+            }
+        }
+        J += o->c.w_g * goal_distance(o, xi[0], xi[1]);
+        int finite = isfinite(J);
+        for (int q = 0; q < 7; ++q) finite = finite && isfinite(xi[q]);
+        if (!finite) J = INFINITY;
+        cost[k] = J;
+        if (final_state)
+            for (int q = 0; q < 7; ++q) final_state[(size_t)q * K + k] = xi[q];
+        if (exit_step) exit_step[k] = ex;
     }
     return 0;
 }
