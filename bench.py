@@ -88,6 +88,89 @@ def cpu_baseline(w, seconds):
             "sample": f"{sample} repeated {runs}x in {el:.1f} s (FP64 C, OpenMP over candidates)"}
 
 
+def _summ(lat, t_first, t_last, steps, n):
+    span = max(t_last - t_first, 1e-9)
+    return {"p50_ms": percentile(lat, 50) * 1e3, "p99_ms": percentile(lat, 99) * 1e3,
+            "max_ms": max(lat) * 1e3, "req_per_s": n / span, "rollout_steps_per_s": steps / span}
+
+
+def serving_leg(scale=1.0, chunk=16, slots=64):
+    """Replay the 64-request serving trace (Poisson arrivals at 200 req/s,
+    K in {512..8192}, N in 40..160, own 256x256 terrain each) through the
+    plain path (one context: set_terrain + rollout + argmin + readback per
+    request, FIFO) and through the continuous-batching server. Arrival times
+    are multiplied by `scale` (0 = every request arrives at once). Inputs are
+    resident on the GPU before the clock starts. Latency = result visible on
+    the host minus arrival."""
+    import torch
+    from paper_2603_20525_amd import inputs
+    from paper_2603_20525_amd import plan as P
+    reqs = inputs.c3_trace()
+    dev = lambda a: torch.from_numpy(a).cuda()  # noqa: E731
+    R = [(r, dev(r.workload.terrain.height), dev(r.workload.controls),
+          torch.zeros(r.workload.N, 2, device="cuda")) for r in reqs]
+    maxK = max(r.workload.K for r in reqs)
+    maxN = max(r.workload.N for r in reqs)
+    steps = sum(r.workload.K * r.workload.N * r.workload.integ["substeps"] for r in reqs)
+    w0 = reqs[0].workload
+    J = torch.empty(maxK, device="cuda")
+    pl = P.Planner(w0.vehicle, w0.cost, w0.integ, maxK, maxN, 256, 256)
+    srv = P.Server(w0.vehicle, slots, maxK, maxN, 256, 256, 4 << 30, chunk)
+
+    def plain_one(r, h, u, plan):
+        w = r.workload
+        pl.set_cost(w.cost)
+        pl.set_terrain(h, w.terrain.x0, w.terrain.y0, w.terrain.res)
+        pl.rollout(w.state0, u, J[:w.K])
+        pl.select(u, J[:w.K], plan)
+
+    def submit(r, h, u, plan):
+        w = r.workload
+        return srv.submit(h, w.terrain.x0, w.terrain.y0, w.terrain.res, w.state0, u, w.cost,
+                          w.integ, plan)
+
+    for item in R[:4]:  # warm both paths (code objects, first-touch)
+        plain_one(*item)
+        submit(*item)
+    srv.drain()
+    torch.cuda.synchronize()
+    # plain path
+    lat, done = [], []
+    t0 = time.perf_counter() + 0.01
+    for r, h, u, plan in R:
+        w = r.workload
+        arr = t0 + r.arrival * scale
+        while time.perf_counter() < arr:
+            pass
+        plain_one(r, h, u, plan)
+        t = time.perf_counter()
+        lat.append(t - arr)
+        done.append(t)
+    plain = _summ(lat, t0, max(done), steps, len(R))
+    pl.close()
+    # continuous batching
+    ts0 = srv.now() + 0.01
+    ids, lat, done = {}, {}, []
+    i = 0
+    while len(lat) < len(R):
+        now = srv.now()
+        while i < len(R) and ts0 + R[i][0].arrival * scale <= now:
+            ids[i] = submit(*R[i])
+            i += 1
+        srv.step()
+        for j, rid in ids.items():
+            if j in lat:
+                continue
+            res = srv.result(rid)
+            if res["status"] != 0:
+                assert res["status"] == 1, res
+                lat[j] = res["t_done"] - (ts0 + R[j][0].arrival * scale)
+                done.append(res["t_done"])
+    serving = _summ(list(lat.values()), ts0, max(done), steps, len(R))
+    srv.close()
+    return {"plain": plain, "serving": serving}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +179,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c2", "c5", "paper"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="seconds of oracle work for cpu_baseline (0 = skip)")
+    ap.add_argument("--serving", type=int, default=1,
+                    help="also replay the serving trace (plain vs continuous batching)")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     args = ap.parse_args()
@@ -178,6 +263,14 @@ def main():
                      "ops_per_rollout_step": OPS_PER_STEP},
         "best": {"k": k_best, "J": j_best},
     }
+    if args.serving:
+        print("[bench] serving trace: plain vs continuous batching", file=sys.stderr, flush=True)
+        out["serving"] = {
+            "trace": "64 requests, Poisson arrivals at 200 req/s, K in {512,1024,2048,4096,8192}, "
+                     "N in 40..160, dt 0.02 s, own 256x256 terrain and start each",
+            "at_200_req_s": serving_leg(1.0),
+            "burst_all_at_once": serving_leg(0.0),
+        }
     if args.cpu_seconds > 0:
         print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

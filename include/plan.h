@@ -70,6 +70,8 @@ typedef struct {
     float w_t, w_c, w_g;
     float goal_x, goal_y, goal_r;
     float sigma, eps_esm, eps_dist;
+    float eps_ay; /* lateral-acceleration normaliser of plan_rollout_est;
+                   * <= 0 selects 10 % of a_bar_y = g e / (2 hR) */
 } plan_cost_t;
 
 /* Integration (sections "OCP Formulation" and "Real-Time Implementation"):
@@ -139,6 +141,25 @@ plan_status_t plan_rollout(plan_ctx *ctx, const float state0[13],
                            const float *controls_dev, int K, int N,
                            float *cost_dev, float *final_state_dev);
 
+/* plan_rollout for the extended single-track (EST) baseline formulation the
+ * paper compares against (appendix "Extended Single-Track Vehicle Dynamics
+ * Model"; lateral-acceleration constraint of section "OCP Formulation"): a
+ * planar single-track model on the plane tangent to the terrain under the
+ * CoM, roll and pitch taken from that plane's normal, normal loads by load
+ * transfer, the same sigmoid tire on a front and a rear virtual tire, and the
+ * soft constraint sigma * max(0, 1 + pi_ay / eps_ay)^2 with
+ * pi_ay = |a_y - g_y| - a_bar_y, a_bar_y = M g / (2 K_zy) = g e / (2 hR), in
+ * place of the ESM term. Same controls, cost terms (costmap at the four
+ * wheels), goal rule, clamps and +inf rule as plan_rollout.
+ *   state0:          host, 7 floats in the order of eq. models:3dof:state:
+ *                    x, y, psi, v_y, omega_z, delta, v_x.
+ *   final_state_dev: [7][K] or NULL.
+ * Uses M, Jzz, Lf, Lr, e, hR, C, mu and the limits of the vehicle (not Jxx,
+ * Jyy or the suspension). Errors: as plan_rollout. */
+plan_status_t plan_rollout_est(plan_ctx *ctx, const float state0[7],
+                               const float *controls_dev, int K, int N,
+                               float *cost_dev, float *final_state_dev);
+
 /* Resumable form of plan_rollout, for callers that advance candidates a few
  * control intervals at a time (a serving loop interleaving requests, or a
  * backward pass recomputing from checkpoints). state_dev [13][K] and
@@ -154,6 +175,28 @@ plan_status_t plan_rollout(plan_ctx *ctx, const float state0[13],
 plan_status_t plan_rollout_chunk(plan_ctx *ctx, float *state_dev, float *cost_dev,
                                  const float *controls_dev, int K, int N, int n0, int n1,
                                  int finalize);
+
+/* Gradient of each candidate's cost with respect to its controls, by a
+ * hand-written reverse pass through the forward-Euler rollout (gradient
+ * refinement of sampled candidates; the paper's optimiser is sampling-only,
+ * section "Real-Time Implementation").
+ *   controls_dev [N][2][K] as for plan_rollout;
+ *   weight_dev   [K] seeds w_k (the result is w_k dJ_k/du_k), or NULL for 1;
+ *   checkpoint_every: the forward pass stores every candidate's state every
+ *                this many control intervals; the backward pass recomputes
+ *                one such segment at a time (memory O(N/C + C) states);
+ *   cost_dev     [K] output: the costs, as plan_rollout computes them;
+ *   grad_dev     [N][2][K] output: dJ/du for the raw controls (zero where a
+ *                control lies outside the admissible set and is clamped, zero
+ *                after the goal exit, zero rows for a +inf candidate).
+ * Non-smooth points take the derivative of the branch the forward pass took.
+ * The library grows an internal workspace of 4*(13 K (N/C + 2) + 14 K C S)
+ * bytes on first use (may synchronise the stream then).
+ * Errors: PLAN_EINVAL, PLAN_ENOTERRAIN, PLAN_ENOMEM, PLAN_EDEVICE. */
+plan_status_t plan_rollout_grad(plan_ctx *ctx, const float state0[13],
+                                const float *controls_dev, int K, int N,
+                                const float *weight_dev, int checkpoint_every,
+                                float *cost_dev, float *grad_dev);
 
 /* Fill state_dev [13][K] with state0 (host, 13 floats) for every candidate
  * and cost_dev [K] with zero, on the context's stream.
@@ -177,6 +220,61 @@ plan_status_t plan_select(plan_ctx *ctx, int mode, float lambda,
                           const float *controls_dev, const float *cost_dev,
                           int K, int N, int *best_k, float *best_cost,
                           float *plan_dev);
+
+/* On-device candidate sampling (section "Real-Time Implementation": the
+ * candidate control sequences are drawn on the GPU by a counter-based
+ * generator; the published configuration draws the steering rate uniformly
+ * in [-1, 1] rad/s and holds the longitudinal acceleration at zero).
+ *
+ * Generator: Philox4x64-10 (Salmon, Moraes, Dror and Shaw, "Parallel random
+ * numbers: as easy as 1, 2, 3", SC 2011). Candidate k at control interval n
+ * uses the 64-bit word n mod 4 of the output block for counter
+ * (k, n div 4, 0, 0) and key (seed, stream); its bits 40..63 give a and bits
+ * 16..39 give b (24-bit integers).
+ *   PLAN_SAMPLE_UNIFORM:  u_c = nominal_c + scale_c (2 x_c - 1), x_0 = a/2^24,
+ *                         x_1 = b/2^24;
+ *   PLAN_SAMPLE_GAUSSIAN: u_c = nominal_c + scale_c z_c, with the Box-Muller
+ *                         pair z_0 = r cos(2 pi q), z_1 = r sin(2 pi q),
+ *                         r = sqrt(-2 ln p), p = (a+1)/2^24, q = b/2^24.
+ * keep_nominal != 0 makes candidate 0 the nominal sequence itself.
+ * nominal_dev is [N][2] FP32 on the device (steering rate, throttle) or NULL
+ * for zeros; it must stay valid until the calls using it have run. The raw
+ * u are what plan_rollout would read from controls_dev: they are clamped to
+ * the admissible set when applied. A sequence depends only on (seed, stream,
+ * k, n), so any call with the same spec and N sees the same candidates. */
+enum { PLAN_SAMPLE_UNIFORM = 0, PLAN_SAMPLE_GAUSSIAN = 1 };
+
+typedef struct {
+    int kind;                  /* PLAN_SAMPLE_UNIFORM or PLAN_SAMPLE_GAUSSIAN */
+    int keep_nominal;
+    unsigned long long seed;   /* key word 0 */
+    unsigned long long stream; /* key word 1 (e.g. the MPC iteration) */
+    float scale[2];            /* half-width (uniform) or std (Gaussian), >= 0 */
+    const float *nominal_dev;  /* [N][2] or NULL */
+} plan_sample_t;
+
+/* Write the sampled candidates to controls_dev [N][2][K] (the layout
+ * plan_rollout reads). Errors: PLAN_EINVAL (NULL ctx/spec/controls, K or N
+ * out of range, unknown kind, negative or non-finite scale); PLAN_EDEVICE. */
+plan_status_t plan_sample_controls(plan_ctx *ctx, const plan_sample_t *spec, int K, int N,
+                                   float *controls_dev);
+
+/* plan_rollout with the candidates drawn inside the rollout kernel instead of
+ * read from memory (no [N][2][K] array exists). Costs and final states are
+ * bit-identical to plan_sample_controls followed by plan_rollout.
+ * Errors: as plan_rollout, plus the spec errors of plan_sample_controls. */
+plan_status_t plan_rollout_sampled(plan_ctx *ctx, const float state0[13],
+                                   const plan_sample_t *spec, int K, int N,
+                                   float *cost_dev, float *final_state_dev);
+
+/* Argmin selection (as plan_select with PLAN_ARGMIN) over costs produced from
+ * spec: plan_dev [N][2] receives the winner's clamped controls, regenerated
+ * from the generator. Host outputs and synchronisation as plan_select.
+ * Errors: PLAN_EINVAL (NULL ctx/spec/cost/plan, K or N out of range, bad
+ * spec); PLAN_EDEVICE. */
+plan_status_t plan_select_sampled(plan_ctx *ctx, const plan_sample_t *spec,
+                                  const float *cost_dev, int K, int N, int *best_k,
+                                  float *best_cost, float *plan_dev);
 
 /* Launch shape of the rollout kernel: lanes per candidate (1, 2 or 4; the
  * four wheels are split over the lanes) and workgroup size (64 or 256).

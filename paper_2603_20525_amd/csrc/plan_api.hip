@@ -13,6 +13,11 @@
 
 using plan::RolloutArgs;
 using plan::SelectOut;
+using plan::auto_launch;
+using plan::finite_all;
+using plan::valid_cost;
+using plan::valid_integ;
+using plan::valid_vehicle;
 
 struct plan_ctx {
     int device = 0;
@@ -26,6 +31,7 @@ struct plan_ctx {
     int W = 0, H = 0;
     float x0 = 0, y0 = 0, res = 0;
     bool has_terrain = false;
+    bool has_costmap = false;
     int *bad_dev = nullptr;
     int *bad_host = nullptr;  // pinned
     // selection workspace
@@ -37,6 +43,9 @@ struct plan_ctx {
     // launch shape
     int lanes_opt = 0, block_opt = 0;
     int last_lanes = 0, last_block = 0;
+    // adjoint workspace (grown on demand): state, checkpoints, segment scratch
+    float *gws = nullptr;
+    size_t gws_floats = 0;
     // timing
     bool timing = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -72,33 +81,6 @@ static plan_status_t hip_fail(plan_ctx *c, const char *what, hipError_t e) {
         if (e__ != hipSuccess) return hip_fail((ctx), #call, e__); \
     } while (0)
 
-static bool finite_all(const float *p, int n) {
-    for (int i = 0; i < n; ++i)
-        if (!isfinite(p[i])) return false;
-    return true;
-}
-
-static bool valid_vehicle(const plan_vehicle_t &v) {
-    if (!finite_all(&v.M, sizeof(plan_vehicle_t) / sizeof(float))) return false;
-    return v.M > 0 && v.Jxx > 0 && v.Jyy > 0 && v.Jzz > 0 && v.Lf + v.Lr > 0 && v.e > 0 &&
-           v.hR > 0 && v.mu > 0 && v.g > 0 && v.delta_max >= 0 && v.delta_rate_max >= 0;
-}
-
-static bool valid_cost(const plan_cost_t &c) {
-    return finite_all(&c.w_t, sizeof(plan_cost_t) / sizeof(float)) && c.goal_r >= 0;
-}
-
-static bool valid_integ(const plan_integ_t &i) {
-    return isfinite(i.dt) && i.dt > 0 && i.substeps >= 1 && isfinite(i.accel_max) &&
-           isfinite(i.vx_min);
-}
-
-// ESM on level ground, M g (R_bar - (h+R)), in double.
-static double esm_level(const plan_vehicle_t &v) {
-    const double hR = v.hR, he = 0.5 * (double)v.e;
-    return (double)v.M * v.g * (sqrt(hR * hR + he * he) - hR);
-}
-
 static void release(plan_ctx *c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
@@ -108,11 +90,125 @@ static void release(plan_ctx *c) {
     (void)hipFree(c->counters);
     (void)hipFree(c->wpart);
     (void)hipFree(c->sel_dev);
+    (void)hipFree(c->gws);
     if (c->sel_host) (void)hipHostFree(c->sel_host);
     if (c->bad_host) (void)hipHostFree(c->bad_host);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
 }
+
+namespace plan {
+
+// Derived constants of one launch (double on the host, rounded once).
+void fill_rollout_args(RolloutArgs &a, const plan_vehicle_t &v, const plan_cost_t &co,
+                       const plan_integ_t &in, const float4 *tex, int W, int H, float x0,
+                       float y0, float res) {
+    memset(&a, 0, sizeof a);
+    const double L = (double)v.Lf + v.Lr;
+    a.invM = (float)(1.0 / v.M);
+    a.invJxx = (float)(1.0 / v.Jxx);
+    a.invJyy = (float)(1.0 / v.Jyy);
+    a.invJzz = (float)(1.0 / v.Jzz);
+    a.dJyz = (float)((double)v.Jyy - v.Jzz);
+    a.dJxz = (float)((double)v.Jxx - v.Jzz);
+    a.dJxy = (float)((double)v.Jxx - v.Jyy);
+    a.Lf = v.Lf;
+    a.Lr = v.Lr;
+    a.half_e = 0.5f * v.e;
+    a.hR = v.hR;
+    a.kf = v.kf;
+    a.kr = v.kr;
+    a.bf = v.bf;
+    a.br = v.br;
+    a.Fsf = (float)(0.5 * v.g * v.M * v.Lr / L);
+    a.Fsr = (float)(0.5 * v.g * v.M * v.Lf / L);
+    a.Mhalf = 0.5f * v.M;
+    a.C = v.C;
+    a.mu = v.mu;
+    a.mu2 = v.mu * v.mu;
+    a.delta_max = v.delta_max;
+    a.drate_max = v.delta_rate_max;
+    a.g = v.g;
+    const double he = 0.5 * (double)v.e;
+    a.MgRbar = (float)((double)v.M * v.g * sqrt((double)v.hR * v.hR + he * he));
+    a.phibar = (float)atan(2.0 * v.hR / v.e);
+    a.Kzzf = (float)((double)v.M * v.Lr / L);
+    a.Kzzr = (float)((double)v.M * v.Lf / L);
+    a.Kzx = (float)((double)v.M * v.hR / L);
+    const double a_bar_y = (double)v.g * v.e / (2.0 * v.hR);  // M g / (2 K_zy)
+    a.a_bar_y = (float)a_bar_y;
+    a.inv_eps_ay = (float)(1.0 / ((co.eps_ay > 0) ? (double)co.eps_ay : 0.1 * a_bar_y));
+    a.w_t = co.w_t;
+    a.w_c = co.w_c;
+    a.w_g = co.w_g;
+    a.goal_x = co.goal_x;
+    a.goal_y = co.goal_y;
+    a.goal_r2 = (float)((double)co.goal_r * co.goal_r);
+    a.sigma = co.sigma;
+    const double eps = (co.eps_esm > 0) ? (double)co.eps_esm : 0.1 * esm_level(v);
+    a.inv_eps_esm = (float)(1.0 / eps);
+    a.h = (float)((double)in.dt / in.substeps);
+    a.S = in.substeps;
+    a.accel_max = in.accel_max;
+    a.vx_min = in.vx_min;
+    a.tex = tex;
+    a.W = W;
+    a.H = H;
+    a.x0 = x0;
+    a.y0 = y0;
+    a.inv_res = (float)(1.0 / res);
+    a.umax = (float)(W - 1);
+    a.vmax = (float)(H - 1);
+}
+
+double esm_level(const plan_vehicle_t &v) {
+    const double hR = v.hR, he = 0.5 * (double)v.e;
+    return (double)v.M * v.g * (sqrt(hR * hR + he * he) - hR);
+}
+
+bool valid_vehicle(const plan_vehicle_t &v) {
+    if (!finite_all(&v.M, sizeof(plan_vehicle_t) / sizeof(float))) return false;
+    return v.M > 0 && v.Jxx > 0 && v.Jyy > 0 && v.Jzz > 0 && v.Lf + v.Lr > 0 && v.e > 0 &&
+           v.hR > 0 && v.mu > 0 && v.g > 0 && v.delta_max >= 0 && v.delta_rate_max >= 0;
+}
+
+bool valid_cost(const plan_cost_t &c) {
+    return finite_all(&c.w_t, sizeof(plan_cost_t) / sizeof(float)) && c.goal_r >= 0;
+}
+
+bool valid_integ(const plan_integ_t &i) {
+    return isfinite(i.dt) && i.dt > 0 && i.substeps >= 1 && isfinite(i.accel_max) &&
+           isfinite(i.vx_min);
+}
+
+bool finite_all(const float *p, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!isfinite(p[i])) return false;
+    return true;
+}
+
+void auto_launch(long long K, int *lanes, int *block) {
+    // Spread small candidate sets over more lanes (wheel-parallel); large
+    // sets use one lane per candidate to avoid redundant chassis work.
+    if (K <= 16384) {
+        *lanes = 4;
+    } else if (K <= 65536) {
+        *lanes = 2;
+    } else {
+        *lanes = 1;
+    }
+    const long long waves = (K * *lanes + 63) / 64;
+    *block = (waves < 4096) ? 64 : 256;
+}
+
+}  // namespace plan
+
+static void fill_args(const plan_ctx *c, RolloutArgs &a) {
+    plan::fill_rollout_args(a, c->veh, c->cost, c->integ, c->tex, c->W, c->H, c->x0, c->y0,
+                            c->res);
+    a.has_costmap = c->has_costmap;
+}
+
 
 extern "C" {
 
@@ -205,82 +301,12 @@ plan_status_t plan_set_terrain(plan_ctx *c, const float *height_dev, int W, int 
     c->x0 = x0;
     c->y0 = y0;
     c->res = res;
+    c->has_costmap = costmap_dev != nullptr;
     c->has_terrain = true;
     return PLAN_OK;
 }
 
-static void auto_launch(int K, int *lanes, int *block) {
-    // Spread small candidate sets over more lanes (wheel-parallel); large
-    // sets use one lane per candidate to avoid redundant chassis work.
-    if (K <= 16384) {
-        *lanes = 4;
-    } else if (K <= 65536) {
-        *lanes = 2;
-    } else {
-        *lanes = 1;
-    }
-    const long long waves = ((long long)K * *lanes + 63) / 64;
-    *block = (waves < 4096) ? 64 : 256;
-}
-
-// Derived constants of one launch (double on the host, rounded once).
-static void fill_args(const plan_ctx *c, RolloutArgs &a) {
-    const plan_vehicle_t &v = c->veh;
-    const plan_cost_t &co = c->cost;
-    const plan_integ_t &in = c->integ;
-    memset(&a, 0, sizeof a);
-    const double L = (double)v.Lf + v.Lr;
-    a.invM = (float)(1.0 / v.M);
-    a.invJxx = (float)(1.0 / v.Jxx);
-    a.invJyy = (float)(1.0 / v.Jyy);
-    a.invJzz = (float)(1.0 / v.Jzz);
-    a.dJyz = (float)((double)v.Jyy - v.Jzz);
-    a.dJxz = (float)((double)v.Jxx - v.Jzz);
-    a.dJxy = (float)((double)v.Jxx - v.Jyy);
-    a.Lf = v.Lf;
-    a.Lr = v.Lr;
-    a.half_e = 0.5f * v.e;
-    a.hR = v.hR;
-    a.kf = v.kf;
-    a.kr = v.kr;
-    a.bf = v.bf;
-    a.br = v.br;
-    a.Fsf = (float)(0.5 * v.g * v.M * v.Lr / L);
-    a.Fsr = (float)(0.5 * v.g * v.M * v.Lf / L);
-    a.Mhalf = 0.5f * v.M;
-    a.C = v.C;
-    a.mu = v.mu;
-    a.mu2 = v.mu * v.mu;
-    a.delta_max = v.delta_max;
-    a.drate_max = v.delta_rate_max;
-    a.g = v.g;
-    const double he = 0.5 * (double)v.e;
-    a.MgRbar = (float)((double)v.M * v.g * sqrt((double)v.hR * v.hR + he * he));
-    a.phibar = (float)atan(2.0 * v.hR / v.e);
-    a.w_t = co.w_t;
-    a.w_c = co.w_c;
-    a.w_g = co.w_g;
-    a.goal_x = co.goal_x;
-    a.goal_y = co.goal_y;
-    a.goal_r2 = (float)((double)co.goal_r * co.goal_r);
-    a.sigma = co.sigma;
-    const double eps = (co.eps_esm > 0) ? (double)co.eps_esm : 0.1 * esm_level(v);
-    a.inv_eps_esm = (float)(1.0 / eps);
-    a.h = (float)((double)in.dt / in.substeps);
-    a.S = in.substeps;
-    a.accel_max = in.accel_max;
-    a.vx_min = in.vx_min;
-    a.tex = c->tex;
-    a.W = c->W;
-    a.H = c->H;
-    a.x0 = c->x0;
-    a.y0 = c->y0;
-    a.inv_res = (float)(1.0 / c->res);
-    a.umax = (float)(c->W - 1);
-    a.vmax = (float)(c->H - 1);
-}
-
-static plan_status_t launch(plan_ctx *c, RolloutArgs &a, bool chunk) {
+static plan_status_t launch(plan_ctx *c, RolloutArgs &a, bool chunk, bool sampled = false) {
     int lanes, block;
     auto_launch(a.K, &lanes, &block);
     if (c->lanes_opt) lanes = c->lanes_opt;
@@ -289,7 +315,10 @@ static plan_status_t launch(plan_ctx *c, RolloutArgs &a, bool chunk) {
     c->last_block = block;
     HIP_TRY(c, hipSetDevice(c->device));
     if (c->timing) HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
-    HIP_TRY(c, plan::launch_rollout(a, lanes, block, chunk, c->stream));
+    if (sampled)
+        HIP_TRY(c, plan::launch_rollout_sampled(a, lanes, block, c->stream));
+    else
+        HIP_TRY(c, plan::launch_rollout(a, lanes, block, chunk, c->stream));
     if (c->timing) {
         HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
         c->ev_recorded = true;
@@ -317,6 +346,113 @@ plan_status_t plan_rollout(plan_ctx *c, const float state0[13], const float *con
     a.cost = cost_dev;
     a.final_state = final_state_dev;
     return launch(c, a, false);
+}
+
+// Validated generator arguments of a plan_sample_t.
+static plan_status_t sample_args(plan_ctx *c, const plan_sample_t *spec, plan::SampleArgs &sa) {
+    if (!spec) return fail(c, PLAN_EINVAL, "sample spec is NULL");
+    if (spec->kind != PLAN_SAMPLE_UNIFORM && spec->kind != PLAN_SAMPLE_GAUSSIAN)
+        return fail(c, PLAN_EINVAL, "sample kind must be PLAN_SAMPLE_UNIFORM or _GAUSSIAN");
+    if (!finite_all(spec->scale, 2) || spec->scale[0] < 0 || spec->scale[1] < 0)
+        return fail(c, PLAN_EINVAL, "sample scales must be finite and >= 0");
+    sa.kind = spec->kind;
+    sa.keep_nominal = spec->keep_nominal != 0;
+    sa.key0 = spec->seed;
+    sa.key1 = spec->stream;
+    sa.scale0 = spec->scale[0];
+    sa.scale1 = spec->scale[1];
+    sa.nominal = spec->nominal_dev;
+    return PLAN_OK;
+}
+
+plan_status_t plan_sample_controls(plan_ctx *c, const plan_sample_t *spec, int K, int N,
+                                   float *controls_dev) {
+    if (!c) return PLAN_EINVAL;
+    if (!controls_dev) return fail(c, PLAN_EINVAL, "NULL argument");
+    if (K < 1 || K > c->max_K) return fail(c, PLAN_EINVAL, "K outside [1, max_K]");
+    if (N < 1 || N > c->max_N) return fail(c, PLAN_EINVAL, "N outside [1, max_N]");
+    plan::SampleArgs sa;
+    plan_status_t st = sample_args(c, spec, sa);
+    if (st != PLAN_OK) return st;
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, plan::launch_sample_controls(sa, K, N, controls_dev, c->stream));
+    return PLAN_OK;
+}
+
+plan_status_t plan_rollout_sampled(plan_ctx *c, const float state0[13], const plan_sample_t *spec,
+                                   int K, int N, float *cost_dev, float *final_state_dev) {
+    if (!c) return PLAN_EINVAL;
+    if (!state0 || !cost_dev) return fail(c, PLAN_EINVAL, "NULL argument");
+    if (K < 1 || K > c->max_K) return fail(c, PLAN_EINVAL, "K outside [1, max_K]");
+    if (N < 1 || N > c->max_N) return fail(c, PLAN_EINVAL, "N outside [1, max_N]");
+    if (!finite_all(state0, 13)) return fail(c, PLAN_EINVAL, "state0 not finite");
+    RolloutArgs a;
+    fill_args(c, a);
+    plan_status_t st = sample_args(c, spec, a.smp);
+    if (st != PLAN_OK) return st;
+    if (!c->has_terrain) return fail(c, PLAN_ENOTERRAIN, "no terrain set");
+    for (int q = 0; q < 13; ++q) a.s0[q] = state0[q];
+    a.controls = nullptr;
+    a.K = K;
+    a.N = N;
+    a.n0 = 0;
+    a.n1 = N;
+    a.finalize = 1;
+    a.cost = cost_dev;
+    a.final_state = final_state_dev;
+    return launch(c, a, false, true);
+}
+
+plan_status_t plan_select_sampled(plan_ctx *c, const plan_sample_t *spec, const float *cost_dev,
+                                  int K, int N, int *best_k, float *best_cost, float *plan_dev) {
+    if (!c) return PLAN_EINVAL;
+    if (!cost_dev || !plan_dev) return fail(c, PLAN_EINVAL, "NULL argument");
+    if (K < 1 || K > c->max_K) return fail(c, PLAN_EINVAL, "K outside [1, max_K]");
+    if (N < 1 || N > c->max_N) return fail(c, PLAN_EINVAL, "N outside [1, max_N]");
+    plan::SampleArgs sa;
+    plan_status_t st = sample_args(c, spec, sa);
+    if (st != PLAN_OK) return st;
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, plan::launch_select_sampled(sa, cost_dev, K, N, c->veh.delta_rate_max, plan_dev,
+                                           c->part_keys, c->counters, c->sel_dev, c->stream));
+    if (best_k || best_cost) {
+        HIP_TRY(c, hipMemcpyAsync(c->sel_host, c->sel_dev, sizeof(SelectOut),
+                                  hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        if (best_k) *best_k = c->sel_host->best_k;
+        if (best_cost) *best_cost = c->sel_host->best_cost;
+    }
+    return PLAN_OK;
+}
+
+plan_status_t plan_rollout_est(plan_ctx *c, const float state0[7], const float *controls_dev,
+                               int K, int N, float *cost_dev, float *final_state_dev) {
+    if (!c) return PLAN_EINVAL;
+    if (!state0 || !controls_dev || !cost_dev) return fail(c, PLAN_EINVAL, "NULL argument");
+    if (K < 1 || K > c->max_K) return fail(c, PLAN_EINVAL, "K outside [1, max_K]");
+    if (N < 1 || N > c->max_N) return fail(c, PLAN_EINVAL, "N outside [1, max_N]");
+    if (!finite_all(state0, 7)) return fail(c, PLAN_EINVAL, "state0 not finite");
+    if (!c->has_terrain) return fail(c, PLAN_ENOTERRAIN, "no terrain set");
+    RolloutArgs a;
+    fill_args(c, a);
+    for (int q = 0; q < 7; ++q) a.s0[q] = state0[q];
+    a.controls = controls_dev;
+    a.K = K;
+    a.N = N;
+    a.n0 = 0;
+    a.n1 = N;
+    a.finalize = 1;
+    a.cost = cost_dev;
+    a.final_state = final_state_dev;
+    const int block = ((long long)K + 63) / 64 < 4096 ? 64 : 256;
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (c->timing) HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
+    HIP_TRY(c, plan::launch_rollout_est(a, block, c->stream));
+    if (c->timing) {
+        HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
+        c->ev_recorded = true;
+    }
+    return PLAN_OK;
 }
 
 plan_status_t plan_init_state(plan_ctx *c, const float state0[13], float *state_dev,
@@ -350,6 +486,68 @@ plan_status_t plan_rollout_chunk(plan_ctx *c, float *state_dev, float *cost_dev,
     a.cost = cost_dev;
     a.state = state_dev;
     return launch(c, a, true);
+}
+
+plan_status_t plan_rollout_grad(plan_ctx *c, const float state0[13], const float *controls_dev,
+                                int K, int N, const float *weight_dev, int checkpoint_every,
+                                float *cost_dev, float *grad_dev) {
+    if (!c) return PLAN_EINVAL;
+    if (!state0 || !controls_dev || !cost_dev || !grad_dev)
+        return fail(c, PLAN_EINVAL, "NULL argument");
+    if (K < 1 || K > c->max_K) return fail(c, PLAN_EINVAL, "K outside [1, max_K]");
+    if (N < 1 || N > c->max_N) return fail(c, PLAN_EINVAL, "N outside [1, max_N]");
+    if (checkpoint_every < 1) return fail(c, PLAN_EINVAL, "checkpoint_every must be >= 1");
+    if (!finite_all(state0, 13)) return fail(c, PLAN_EINVAL, "state0 not finite");
+    if (!c->has_terrain) return fail(c, PLAN_ENOTERRAIN, "no terrain set");
+    const int C = checkpoint_every < N ? checkpoint_every : N;
+    const int nseg = (N + C - 1) / C;
+    const size_t Kz = (size_t)K;
+    const size_t need = 13 * Kz                            // running state
+                        + (size_t)(nseg + 1) * 13 * Kz     // checkpoints
+                        + (size_t)C * c->integ.substeps * 14 * Kz;  // segment scratch
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (need > c->gws_floats) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        HIP_TRY(c, hipFree(c->gws));
+        c->gws = nullptr;
+        c->gws_floats = 0;
+        hipError_t e = hipMalloc(&c->gws, sizeof(float) * need);
+        if (e != hipSuccess) {
+            hip_fail(c, "hipMalloc(adjoint workspace)", e);
+            return e == hipErrorOutOfMemory ? PLAN_ENOMEM : PLAN_EDEVICE;
+        }
+        c->gws_floats = need;
+    }
+    float *state = c->gws;
+    float *ckpt = state + 13 * Kz;
+    float *scratch = ckpt + (size_t)(nseg + 1) * 13 * Kz;
+    RolloutArgs a;
+    fill_args(c, a);
+    a.controls = controls_dev;
+    a.K = K;
+    a.N = N;
+    a.cost = cost_dev;
+    a.state = state;
+    HIP_TRY(c, plan::launch_init_state(state0, state, cost_dev, K, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(ckpt, state, sizeof(float) * 13 * Kz, hipMemcpyDeviceToDevice,
+                              c->stream));
+    // forward pass, one segment of C intervals at a time, checkpointing the
+    // state at every segment boundary
+    for (int seg = 0; seg < nseg; ++seg) {
+        a.n0 = seg * C;
+        a.n1 = (seg + 1) * C < N ? (seg + 1) * C : N;
+        a.finalize = a.n1 == N;
+        plan_status_t st = launch(c, a, true);
+        if (st != PLAN_OK) return st;
+        HIP_TRY(c, hipMemcpyAsync(ckpt + (size_t)(seg + 1) * 13 * Kz, state,
+                                  sizeof(float) * 13 * Kz, hipMemcpyDeviceToDevice, c->stream));
+    }
+    a.n0 = 0;
+    a.n1 = N;
+    a.finalize = 1;
+    HIP_TRY(c, plan::launch_adjoint_backward(a, C, ckpt, weight_dev, scratch, grad_dev,
+                                             c->stream));
+    return PLAN_OK;
 }
 
 plan_status_t plan_select(plan_ctx *c, int mode, float lambda, const float *controls_dev,

@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/plan.h"
+#include "sample.h"
+
 namespace plan {
 
 // Everything one rollout needs, passed by value as the kernel argument
@@ -21,6 +24,10 @@ struct RolloutArgs {
     float C, mu, mu2;
     float delta_max, drate_max, g;
     float MgRbar, phibar;          // ESM: M g R_bar, phi_bar
+    // extended single-track baseline: load-transfer coefficients K_zz,f,
+    // K_zz,r, K_zx (kg), lateral-acceleration boundary and its normaliser
+    float Kzzf, Kzzr, Kzx;
+    float a_bar_y, inv_eps_ay;
     // cost
     float w_t, w_c, w_g;
     float goal_x, goal_y, goal_r2;
@@ -34,6 +41,7 @@ struct RolloutArgs {
     int W, H;
     float x0, y0, inv_res;
     float umax, vmax;              // W-1, H-1 as floats (clamp-to-edge)
+    int has_costmap;               // the texels' cost channel is not all zero
     // problem
     float s0[13];
     const float *controls;         // [N][2][K]
@@ -43,22 +51,67 @@ struct RolloutArgs {
     float *cost;                   // [K]: written (full) or read-modify-written (chunk)
     float *final_state;            // full: [13][K] or nullptr
     float *state;                  // chunk: [13][K], read and written
+    SampleArgs smp;                // sampled launches: the candidate generator
+};
+
+// One tick of the serving loop: which slots advance through which control
+// intervals, and which blocks of the launch belong to each slot.
+constexpr int MAX_TICK_SLOTS = 128;
+
+struct TickEntry {
+    int slot;
+    int block_start;
+    int n0, n1;
+    int finalize;
+};
+
+struct TickTable {
+    int count;
+    int total_blocks;
+    TickEntry e[MAX_TICK_SLOTS];
 };
 
 struct SelectOut {
     int best_k;
     float best_cost;
-    uint32_t pad[2];
+    uint32_t pad[2];  // pad[0]: status of the request (0 or a plan_status_t)
+};
+
+struct SlotList {
+    int count;
+    int slot[MAX_TICK_SLOTS];
 };
 
 // chunk = false: candidates start from s0 with zero cost. chunk = true:
 // they continue from a.state / a.cost. Both run the same step code.
 hipError_t launch_rollout(const RolloutArgs &a, int lanes, int block, bool chunk, hipStream_t s);
 
+// As launch_rollout (full horizon from a.s0) with the controls drawn in the
+// kernel from a.smp instead of read from a.controls.
+hipError_t launch_rollout_sampled(const RolloutArgs &a, int lanes, int block, hipStream_t s);
+
+// controls [N][2][K] from the generator.
+hipError_t launch_sample_controls(const SampleArgs &sa, int K, int N, float *controls,
+                                  hipStream_t s);
+
+// Extended single-track formulation (state [7]: x, y, psi, v_y, omega_z,
+// delta, v_x): full horizon from a.s0[0..6]; a.final_state is [7][K].
+hipError_t launch_rollout_est(const RolloutArgs &a, int block, hipStream_t s);
+
+hipError_t launch_rollout_slots(const RolloutArgs *slots, const TickTable &t, int lanes,
+                                int block, hipStream_t s);
+
+hipError_t launch_adjoint_backward(const RolloutArgs &a, int C, const float *ckpt,
+                                   const float *weight, float *scratch, float *grad,
+                                   hipStream_t s);
+
 hipError_t launch_init_state(const float *s0, float *state, float *cost, int K, hipStream_t s);
 
 hipError_t launch_pack_terrain(const float *h, const float *c, int W, int H, float inv_res,
                                float4 *tex, int *bad, hipStream_t s);
+
+hipError_t launch_select_slots(const RolloutArgs *slots, float *const *plans, const int *bad,
+                               SelectOut *out, const SlotList &l, hipStream_t s);
 
 // Selection workspace sizes for a given maximum K / N.
 int select_blocks(int K);
@@ -69,5 +122,22 @@ hipError_t launch_select(int mode, float lambda, const float *controls, const fl
                          int K, int N, float drate_max, float *plan_out,
                          unsigned long long *part_keys, unsigned int *counters,
                          float *wpart, SelectOut *out, hipStream_t s);
+
+// Argmin whose plan is the winner's sequence regenerated from the sampler.
+hipError_t launch_select_sampled(const SampleArgs &sa, const float *cost, int K, int N,
+                                 float drate_max, float *plan_out,
+                                 unsigned long long *part_keys, unsigned int *counters,
+                                 SelectOut *out, hipStream_t s);
+
+// Host helpers shared by the plan and server entry points.
+void fill_rollout_args(RolloutArgs &a, const plan_vehicle_t &v, const plan_cost_t &co,
+                       const plan_integ_t &in, const float4 *tex, int W, int H, float x0,
+                       float y0, float res);
+double esm_level(const plan_vehicle_t &v);
+bool finite_all(const float *p, int n);
+bool valid_vehicle(const plan_vehicle_t &v);
+bool valid_cost(const plan_cost_t &c);
+bool valid_integ(const plan_integ_t &i);
+void auto_launch(long long K, int *lanes, int *block);
 
 }  // namespace plan

@@ -1,0 +1,290 @@
+// Device code of one forward-Euler step of the SRB model with its stage
+// cost, shared by the rollout kernels and the adjoint (which recomputes the
+// forward pass from checkpoints and must see the same arithmetic).
+// Arithmetic is fixed by the source: the library is compiled without
+// floating-point contraction and every fused multiply-add is an explicit fmaf.
+#pragma once
+
+#include "plan_internal.h"
+
+namespace plan {
+
+// ----------------------------------------------------------------- math ----
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// DPP quad permutations: swap with lane^1 and lane^2 inside each quad.
+__device__ __forceinline__ float dpp_xor1(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float dpp_xor2(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, true));
+}
+
+template <int LANES>
+__device__ __forceinline__ float group_sum(float v) {
+    if constexpr (LANES >= 2) v = v + dpp_xor1(v);
+    if constexpr (LANES >= 4) v = v + dpp_xor2(v);
+    return v;
+}
+
+// NaN-propagating clamps (a NaN input stays NaN, as in the reference
+// arithmetic; the candidate is then scored +inf at the end).
+__device__ __forceinline__ float clampf_nan(float x, float lo, float hi) {
+    return x < lo ? lo : (x > hi ? hi : x);
+}
+
+// Attitude terms of the 3-2-1 rotation W <- B.
+// Hardware sine/cosine (v_sin_f32 / v_cos_f32): absolute error of order 1e-6,
+// far below the trajectory's own float32 sensitivity.
+struct Attitude {
+    float sth, cth, sph, cph;
+    float R11, R12, R13, R21, R22, R23, R31, R32, R33;
+};
+
+__device__ __forceinline__ Attitude attitude(float psi, float th, float ph) {
+    float sps, cps;
+    Attitude A;
+    __sincosf(psi, &sps, &cps);
+    __sincosf(th, &A.sth, &A.cth);
+    __sincosf(ph, &A.sph, &A.cph);
+    const float ss = A.sph * A.sth, cs = A.cph * A.sth;
+    A.R11 = cps * A.cth;
+    A.R12 = fmaf(cps, ss, -(A.cph * sps));
+    A.R13 = fmaf(cps, cs, A.sph * sps);
+    A.R21 = A.cth * sps;
+    A.R22 = fmaf(sps, ss, A.cph * cps);
+    A.R23 = fmaf(sps, cs, -(cps * A.sph));
+    A.R31 = -A.sth;
+    A.R32 = A.cth * A.sph;
+    A.R33 = A.cph * A.cth;
+    return A;
+}
+
+// Body-frame lever arm of wheel wi (fl, fr, rl, rr): constant in the body frame.
+struct Arm {
+    float rx, ry, rz;
+    bool front;
+};
+
+__device__ __forceinline__ Arm arm(const RolloutArgs &a, int wi) {
+    Arm r;
+    r.front = wi < 2;
+    r.rx = r.front ? a.Lf : -a.Lr;
+    r.ry = (wi & 1) ? -a.half_e : a.half_e;
+    r.rz = -a.hR;
+    return r;
+}
+
+// The four texels around a wheel's contact point plus the bilinear weights;
+// the loads are issued here and consumed in wheel(), so the gathers are in
+// flight while the chassis terms are computed.
+struct Gather {
+    float4 t00, t10, t01, t11;
+    float tx, ty, Pz;
+};
+
+__device__ __forceinline__ Gather gather(const RolloutArgs &a, const Attitude &A, float x,
+                                         float y, float z, const Arm &r) {
+    // contact point P = p + R rho (world)
+    const float Px = fmaf(A.R11, r.rx, fmaf(A.R12, r.ry, fmaf(A.R13, r.rz, x)));
+    const float Py = fmaf(A.R21, r.rx, fmaf(A.R22, r.ry, fmaf(A.R23, r.rz, y)));
+    Gather g;
+    g.Pz = fmaf(A.R31, r.rx, fmaf(A.R32, r.ry, fmaf(A.R33, r.rz, z)));
+    // clamp-to-edge; a NaN coordinate clamps to 0 through fmaxf, so the
+    // indices are always inside the grid
+    const float u = fminf(fmaxf((Px - a.x0) * a.inv_res, 0.0f), a.umax);
+    const float v = fminf(fmaxf((Py - a.y0) * a.inv_res, 0.0f), a.vmax);
+    const int i = min((int)u, a.W - 2);
+    const int j = min((int)v, a.H - 2);
+    g.tx = u - (float)i;
+    g.ty = v - (float)j;
+    const float4 *p = a.tex + (size_t)j * a.W + i;
+    g.t00 = p[0];
+    g.t10 = p[1];
+    g.t01 = p[a.W];
+    g.t11 = p[a.W + 1];
+    return g;
+}
+
+__device__ __forceinline__ float lerp2(float tx, float ty, float a00, float a10, float a01,
+                                       float a11) {
+    const float b0 = fmaf(tx, a10 - a00, a00), b1 = fmaf(tx, a11 - a01, a01);
+    return fmaf(ty, b1 - b0, b0);
+}
+
+// Force and moment contributions of one wheel (sums of the force and moment
+// equations of the SRB section).
+struct WheelOut {
+    float Fy, Fz, Mx, My, Mz, c;
+};
+
+struct Motion {
+    float vx, vy, vz, wx, wy, wz;
+    float delta, cosd, FxR;
+};
+
+__device__ __forceinline__ WheelOut wheel(const RolloutArgs &a, const Attitude &A,
+                                          const Motion &m, const Arm &r, const Gather &g) {
+    // contact-point velocity v + w x rho (body)
+    const float vix = fmaf(m.wy, r.rz, fmaf(-m.wz, r.ry, m.vx));
+    const float viy = fmaf(m.wz, r.rx, fmaf(-m.wx, r.rz, m.vy));
+    const float viz = fmaf(m.wx, r.ry, fmaf(-m.wy, r.rx, m.vz));
+    // bilinear height, slopes and cost rate at the contact point
+    const float th = lerp2(g.tx, g.ty, g.t00.x, g.t10.x, g.t01.x, g.t11.x);
+    const float tfx = lerp2(g.tx, g.ty, g.t00.y, g.t10.y, g.t01.y, g.t11.y);
+    const float tfy = lerp2(g.tx, g.ty, g.t00.z, g.t10.z, g.t01.z, g.t11.z);
+    const float tc = lerp2(g.tx, g.ty, g.t00.w, g.t10.w, g.t01.w, g.t11.w);
+    // upward terrain normal (-f_x, -f_y, 1) resolved in the body frame
+    const float nBx = fmaf(-A.R11, tfx, fmaf(-A.R21, tfy, A.R31));
+    const float nBy = fmaf(-A.R12, tfx, fmaf(-A.R22, tfy, A.R32));
+    const float nBz = fmaf(-A.R13, tfx, fmaf(-A.R23, tfy, A.R33));
+    const float inz = frcp(nBz);
+    // extension and its rate along b_z (omega x b_z = (w_y, -w_x, 0))
+    const float chi = (g.Pz - th) * inz;
+    const float relx = fmaf(-chi, m.wy, vix);
+    const float rely = fmaf(chi, m.wx, viy);
+    const float chid = fmaf(nBx, relx, fmaf(nBy, rely, nBz * viz)) * inz;
+    // spring-damper with liftoff
+    const float Fs = r.front ? a.Fsf : a.Fsr;
+    const float k = r.front ? a.kf : a.kr;
+    const float b = r.front ? a.bf : a.br;
+    const float Fk = fmaxf(fmaf(-k, chi, Fs), 0.0f);
+    const float Fb = (Fk > 0.0f) ? fmaxf(-b * chid, -Fk) : 0.0f;
+    const float Fz = Fk + Fb;
+    // slip angle (literal atan of the velocity ratio) and sigmoid tire
+    const float dl = r.front ? m.delta : 0.0f;
+    const float alpha = (vix == 0.0f && viy == 0.0f) ? -dl : atanf(viy * frcp(vix)) - dl;
+    const float Ca = a.C * alpha;
+    const float Fy = (Fz * (-Ca * a.mu)) * frsq(fmaf(Ca, Ca, a.mu2));
+    const float Fx = r.front ? 0.0f : m.FxR;
+    const float fy = r.front ? Fy * m.cosd : Fy;
+    WheelOut o;
+    o.Fy = fy;
+    o.Fz = Fz;
+    o.Mx = fmaf(r.ry, Fz, -(r.rz * fy));
+    o.My = fmaf(r.rz, Fx, -(r.rx * Fz));
+    o.Mz = fmaf(r.rx, fy, -(r.ry * Fx));
+    o.c = tc;
+    return o;
+}
+
+__device__ __forceinline__ WheelOut wadd(const WheelOut &p, const WheelOut &q) {
+    return WheelOut{p.Fy + q.Fy, p.Fz + q.Fz, p.Mx + q.Mx, p.My + q.My, p.Mz + q.Mz, p.c + q.c};
+}
+
+// One forward-Euler step of every quantity of the model for one candidate
+// (this lane's wheels, group sums over the candidate's lanes): the running
+// cost at the node is added to J and the state advanced in place.
+template <int LANES>
+__device__ __forceinline__ void euler_step(const RolloutArgs &a, const Arm (&arms)[4 / LANES],
+                                           float (&st)[13], float &J, float dd, float ax) {
+    constexpr int WPL = 4 / LANES;  // wheels per lane
+    const float h = a.h;
+    const float half_pi = 1.57079632679489662f;
+    float x = st[0], y = st[1], z = st[2];
+    float psi = st[3], th = st[4], ph = st[5];
+    float vx = st[6], vy = st[7], vz = st[8];
+    float wx = st[9], wy = st[10], wz = st[11];
+    float delta = st[12];
+    // attitude and this lane's terrain requests first, so the
+    // gathers overlap the chassis arithmetic below
+    const Attitude A = attitude(psi, th, ph);
+    Gather G[WPL];
+#pragma unroll
+    for (int q = 0; q < WPL; ++q) G[q] = gather(a, A, x, y, z, arms[q]);
+
+    // kinematics: world velocity, Euler-angle rates, gravity in the
+    // body frame, rear longitudinal constraint force
+    const float vWx = fmaf(A.R11, vx, fmaf(A.R12, vy, A.R13 * vz));
+    const float vWy = fmaf(A.R21, vx, fmaf(A.R22, vy, A.R23 * vz));
+    const float vWz = fmaf(A.R31, vx, fmaf(A.R32, vy, A.R33 * vz));
+    const float icth = frcp(A.cth);
+    const float t1 = fmaf(A.sph, wy, A.cph * wz);
+    const float psid = t1 * icth;
+    const float thd = fmaf(A.cph, wy, -(A.sph * wz));
+    const float phd = fmaf(psid, A.sth, wx);
+    const float gBx = a.g * A.sth;
+    const float gBy = (-a.g * A.cth) * A.sph;
+    const float gBz = (-a.g * A.cph) * A.cth;
+    Motion m;
+    m.vx = vx;
+    m.vy = vy;
+    m.vz = vz;
+    m.wx = wx;
+    m.wy = wy;
+    m.wz = wz;
+    m.delta = delta;
+    m.cosd = __cosf(delta);
+    m.FxR = a.Mhalf * fmaf(wy, vz, fmaf(-wz, vy, ax - gBx));
+
+    // ESM soft-constraint and control terms of the running cost
+    const float ang = fabsf(ph) + a.phibar;
+    float U = (a.MgRbar * (1.0f - __sinf(ang))) * A.cth;
+    U = (ang > half_pi) ? -U : U;
+    const float mm = fmaxf(0.0f, fmaf(-U, a.inv_eps_esm, 1.0f));
+    const float L0 = fmaf(a.w_c * dd, dd, a.w_t) + (a.sigma * mm) * mm;
+
+    // wheel forces: this lane's share, then the group sum in fixed
+    // order (w0 + w1) + (w2 + w3)
+    WheelOut sum;
+    if constexpr (WPL == 4) {
+        const WheelOut w0 = wheel(a, A, m, arms[0], G[0]);
+        const WheelOut w1 = wheel(a, A, m, arms[1], G[1]);
+        const WheelOut w2 = wheel(a, A, m, arms[2], G[2]);
+        const WheelOut w3 = wheel(a, A, m, arms[3], G[3]);
+        sum = wadd(wadd(w0, w1), wadd(w2, w3));
+    } else if constexpr (WPL == 2) {
+        sum = wadd(wheel(a, A, m, arms[0], G[0]), wheel(a, A, m, arms[1], G[1]));
+    } else {
+        sum = wheel(a, A, m, arms[0], G[0]);
+    }
+    const float Fy = group_sum<LANES>(sum.Fy);
+    const float Fz = group_sum<LANES>(sum.Fz);
+    const float Mx = group_sum<LANES>(sum.Mx);
+    const float My = group_sum<LANES>(sum.My);
+    const float Mz = group_sum<LANES>(sum.Mz);
+    const float csum = group_sum<LANES>(sum.c);
+
+    // right-hand side rows (Newton-Euler in the body frame)
+    const float vyd = fmaf(Fy, a.invM, gBy) + fmaf(wx, vz, -(wz * vx));
+    const float vzd = fmaf(Fz, a.invM, gBz) + fmaf(wy, vx, -(wx * vy));
+    const float wxd = fmaf(a.dJyz * wy, wz, Mx) * a.invJxx;
+    const float wyd = fmaf(-a.dJxz * wx, wz, My) * a.invJyy;
+    const float wzd = fmaf(a.dJxy * wx, wy, Mz) * a.invJzz;
+
+    // running cost at the node (left Riemann sum)
+    J = fmaf(h, L0 + csum, J);
+
+    // forward Euler
+    x = fmaf(h, vWx, x);
+    y = fmaf(h, vWy, y);
+    z = fmaf(h, vWz, z);
+    psi = fmaf(h, psid, psi);
+    th = fmaf(h, thd, th);
+    ph = fmaf(h, phd, ph);
+    vx = fmaf(h, ax, vx);
+    vy = fmaf(h, vyd, vy);
+    vz = fmaf(h, vzd, vz);
+    wx = fmaf(h, wxd, wx);
+    wy = fmaf(h, wyd, wy);
+    wz = fmaf(h, wzd, wz);
+    delta = fmaf(h, dd, delta);
+    delta = clampf_nan(delta, -a.delta_max, a.delta_max);
+    vx = (vx < a.vx_min) ? a.vx_min : vx;
+    st[0] = x;
+    st[1] = y;
+    st[2] = z;
+    st[3] = psi;
+    st[4] = th;
+    st[5] = ph;
+    st[6] = vx;
+    st[7] = vy;
+    st[8] = vz;
+    st[9] = wx;
+    st[10] = wy;
+    st[11] = wz;
+    st[12] = delta;
+}
+
+}  // namespace plan

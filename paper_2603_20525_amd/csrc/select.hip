@@ -89,12 +89,14 @@ __device__ __forceinline__ float clamp_ctrl(float u, int row, float drate_max) {
 }
 
 // One block per SEL_CHUNK candidates; the last block to finish reduces the
-// per-block keys, publishes (k*, J*) and, for argmin, gathers the plan.
+// per-block keys, publishes (k*, J*) and, for argmin, gathers the plan: from
+// controls, or (SAMPLED) by regenerating candidate k*'s sequence.
+template <bool SAMPLED>
 __global__ __launch_bounds__(SEL_BLOCK) void select_argmin(
     const float *__restrict__ cost, int K, const float *__restrict__ controls, int N,
     float drate_max, int gather, float *__restrict__ plan,
     unsigned long long *__restrict__ part, unsigned int *__restrict__ ticket,
-    SelectOut *__restrict__ out) {
+    SelectOut *__restrict__ out, const SampleArgs smp) {
     __shared__ unsigned long long red[SEL_BLOCK / 64];
     __shared__ unsigned long long best_sh;
     __shared__ int last_sh;
@@ -152,8 +154,23 @@ __global__ __launch_bounds__(SEL_BLOCK) void select_argmin(
     if (gather) {
         const unsigned long long m = best_sh;
         const int kb = (m == ~0ull) ? -1 : (int)(unsigned int)(m & 0xffffffffu);
-        for (int e = tid; e < 2 * N; e += SEL_BLOCK)
-            plan[e] = (kb < 0) ? 0.0f : clamp_ctrl(controls[(size_t)e * K + kb], e, drate_max);
+        if constexpr (SAMPLED) {
+            for (int n = tid; n < N; n += SEL_BLOCK) {
+                float u0 = 0.0f, u1 = 0.0f;
+                if (kb >= 0) {
+                    const PhiloxBlock blk = sample_block(smp, kb, n >> 2);
+                    draw_controls(smp, block_word(blk, n & 3), kb, n, u0, u1);
+                    u0 = clamp_ctrl(u0, 0, drate_max);
+                    u1 = clamp_ctrl(u1, 1, drate_max);
+                }
+                plan[2 * n] = u0;
+                plan[2 * n + 1] = u1;
+            }
+        } else {
+            for (int e = tid; e < 2 * N; e += SEL_BLOCK)
+                plan[e] =
+                    (kb < 0) ? 0.0f : clamp_ctrl(controls[(size_t)e * K + kb], e, drate_max);
+        }
     }
 }
 
@@ -233,7 +250,55 @@ __global__ __launch_bounds__(SEL_BLOCK) void select_softmin(
     if (tid == 0) *ticket = 0u;
 }
 
+// Argmin and plan gather for the slots that finished in a serving tick: one
+// block per slot, any K (strided), same keys and tie rule as select_argmin.
+constexpr int SLOT_SEL_BLOCK = 1024;
+
+__global__ __launch_bounds__(SLOT_SEL_BLOCK) void select_slots(
+    const RolloutArgs *__restrict__ slots, float *const *__restrict__ plans,
+    const int *__restrict__ bad, SelectOut *__restrict__ out, const SlotList l) {
+    __shared__ unsigned long long red[SLOT_SEL_BLOCK / 64];
+    __shared__ unsigned long long best_sh;
+    const int s = l.slot[blockIdx.x];
+    const RolloutArgs &a = slots[s];
+    const int K = a.K, N = a.N;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    unsigned long long key = ~0ull;
+    for (int k = tid; k < K; k += SLOT_SEL_BLOCK) {
+        const unsigned long long kk = cost_key(a.cost[k], k);
+        key = kk < key ? kk : key;
+    }
+    key = wave_min(key);
+    if (lane == 0) red[wv] = key;
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long m = red[0];
+        for (int q = 1; q < SLOT_SEL_BLOCK / 64; ++q) m = red[q] < m ? red[q] : m;
+        best_sh = m;
+        SelectOut o;
+        o.best_k = (m == ~0ull) ? -1 : (int)(unsigned int)(m & 0xffffffffu);
+        o.best_cost = (m == ~0ull) ? __builtin_inff() : key_cost(m);
+        o.pad[0] = bad[s] ? (uint32_t)(int32_t)PLAN_EINVAL : 0u;
+        o.pad[1] = 0;
+        out[s] = o;
+    }
+    __syncthreads();
+    const unsigned long long m = best_sh;
+    const int kb = (m == ~0ull) ? -1 : (int)(unsigned int)(m & 0xffffffffu);
+    float *plan = plans[s];
+    for (int e = tid; e < 2 * N; e += SLOT_SEL_BLOCK)
+        plan[e] = (kb < 0) ? 0.0f : clamp_ctrl(a.controls[(size_t)e * K + kb], e, a.drate_max);
+}
+
 }  // namespace
+
+hipError_t launch_select_slots(const RolloutArgs *slots, float *const *plans, const int *bad,
+                               SelectOut *out, const SlotList &l, hipStream_t s) {
+    if (l.count < 1) return hipSuccess;
+    hipLaunchKernelGGL(select_slots, dim3(l.count), dim3(SLOT_SEL_BLOCK), 0, s, slots, plans, bad,
+                       out, l);
+    return hipGetLastError();
+}
 
 int select_blocks(int K) { return (K + SEL_CHUNK - 1) / SEL_CHUNK; }
 int softmin_chunks(int K) { return (K + SM_CHUNK - 1) / SM_CHUNK; }
@@ -251,14 +316,25 @@ hipError_t launch_select(int mode, float lambda, const float *controls, const fl
                          unsigned long long *part_keys, unsigned int *counters, float *wpart,
                          SelectOut *out, hipStream_t s) {
     const int nb = select_blocks(K);
-    hipLaunchKernelGGL(select_argmin, dim3(nb), dim3(SEL_BLOCK), 0, s, cost, K, controls, N,
-                       drate_max, mode == 0 ? 1 : 0, plan_out, part_keys, counters + 0, out);
+    hipLaunchKernelGGL(select_argmin<false>, dim3(nb), dim3(SEL_BLOCK), 0, s, cost, K, controls,
+                       N, drate_max, mode == 0 ? 1 : 0, plan_out, part_keys, counters + 0, out,
+                       SampleArgs{});
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || mode == 0) return e;
     dim3 grid(softmin_chunks(K), softmin_row_groups(N));
     hipLaunchKernelGGL(select_softmin, grid, dim3(SEL_BLOCK), 0, s, cost, K, controls, N,
                        drate_max, 1.0f / lambda, plan_out, wpart, counters + 1,
                        (const SelectOut *)out);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_sampled(const SampleArgs &sa, const float *cost, int K, int N,
+                                 float drate_max, float *plan_out,
+                                 unsigned long long *part_keys, unsigned int *counters,
+                                 SelectOut *out, hipStream_t s) {
+    const int nb = select_blocks(K);
+    hipLaunchKernelGGL(select_argmin<true>, dim3(nb), dim3(SEL_BLOCK), 0, s, cost, K, nullptr, N,
+                       drate_max, 1, plan_out, part_keys, counters + 0, out, sa);
     return hipGetLastError();
 }
 

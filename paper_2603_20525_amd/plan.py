@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libplan.so")
 
 PLAN_OK, PLAN_EINVAL, PLAN_ENOMEM, PLAN_EDEVICE, PLAN_ENOTERRAIN = 0, -1, -2, -3, -4
 PLAN_ARGMIN, PLAN_SOFTMIN = 0, 1
+PLAN_SAMPLE_UNIFORM, PLAN_SAMPLE_GAUSSIAN = 0, 1
 STATUS_NAMES = {0: "PLAN_OK", -1: "PLAN_EINVAL", -2: "PLAN_ENOMEM", -3: "PLAN_EDEVICE",
                 -4: "PLAN_ENOTERRAIN"}
 
@@ -34,7 +35,8 @@ class Vehicle(C.Structure):
 
 class Cost(C.Structure):
     _fields_ = [(n, C.c_float) for n in (
-        "w_t", "w_c", "w_g", "goal_x", "goal_y", "goal_r", "sigma", "eps_esm", "eps_dist")]
+        "w_t", "w_c", "w_g", "goal_x", "goal_y", "goal_r", "sigma", "eps_esm", "eps_dist",
+        "eps_ay")]
 
 
 class Integ(C.Structure):
@@ -42,9 +44,16 @@ class Integ(C.Structure):
                 ("vx_min", C.c_float)]
 
 
+class Sample(C.Structure):
+    _fields_ = [("kind", C.c_int), ("keep_nominal", C.c_int), ("seed", C.c_ulonglong),
+                ("stream", C.c_ulonglong), ("scale", C.c_float * 2),
+                ("nominal_dev", C.c_void_p)]
+
+
 # every symbol include/plan.h declares
 EXPORTS = ("plan_create", "plan_set_stream", "plan_set_cost", "plan_set_terrain",
-           "plan_rollout", "plan_rollout_chunk", "plan_init_state", "plan_select",
+           "plan_rollout", "plan_rollout_est", "plan_rollout_chunk", "plan_init_state", "plan_rollout_grad",
+           "plan_select", "plan_sample_controls", "plan_rollout_sampled", "plan_select_sampled",
            "plan_set_launch", "plan_get_launch", "plan_enable_timing", "plan_last_rollout_ms",
            "plan_destroy", "plan_last_error")
 
@@ -67,10 +76,16 @@ def lib():
         L.plan_set_terrain.argtypes = [vp, vp, C.c_int, C.c_int, C.c_float, C.c_float,
                                        C.c_float, vp]
         L.plan_rollout.argtypes = [vp, fp, vp, C.c_int, C.c_int, vp, vp]
+        L.plan_rollout_est.argtypes = [vp, fp, vp, C.c_int, C.c_int, vp, vp]
         L.plan_rollout_chunk.argtypes = [vp, vp, vp, vp, C.c_int, C.c_int, C.c_int, C.c_int,
                                          C.c_int]
         L.plan_init_state.argtypes = [vp, fp, vp, vp, C.c_int]
+        L.plan_rollout_grad.argtypes = [vp, fp, vp, C.c_int, C.c_int, vp, C.c_int, vp, vp]
         L.plan_select.argtypes = [vp, C.c_int, C.c_float, vp, vp, C.c_int, C.c_int, ip, fp, vp]
+        sp = C.POINTER(Sample)
+        L.plan_sample_controls.argtypes = [vp, sp, C.c_int, C.c_int, vp]
+        L.plan_rollout_sampled.argtypes = [vp, fp, sp, C.c_int, C.c_int, vp, vp]
+        L.plan_select_sampled.argtypes = [vp, sp, vp, C.c_int, C.c_int, ip, fp, vp]
         L.plan_set_launch.argtypes = [vp, C.c_int, C.c_int]
         L.plan_get_launch.argtypes = [vp, ip, ip]
         L.plan_enable_timing.argtypes = [vp, C.c_int]
@@ -154,6 +169,20 @@ def plan_rollout(ctx, state0, controls, cost, final_state=None):
     _check("plan_rollout", st, ctx)
 
 
+def plan_rollout_est(ctx, state0, controls, cost, final_state=None):
+    """EST formulation: state0 7 host floats (x, y, psi, v_y, omega_z, delta,
+    v_x); controls [N][2][K], cost [K], final_state [7][K] on the GPU."""
+    N, two, K = controls.shape
+    if two != 2:
+        raise ValueError("controls must be [N][2][K]")
+    if len(state0) != 7:
+        raise ValueError("state0 must have 7 entries")
+    s0 = (C.c_float * 7)(*[float(v) for v in state0])
+    st = lib().plan_rollout_est(ctx, s0, _dptr(controls, "controls"), K, N,
+                                _dptr(cost, "cost", K), _dptr(final_state, "final_state", 7 * K))
+    _check("plan_rollout_est", st, ctx)
+
+
 def plan_rollout_chunk(ctx, state, cost, controls, n0: int, n1: int, finalize: bool):
     """Advance state [13][K] and running cost [K] (GPU, in place) through
     control intervals [n0, n1) of controls [N][2][K]."""
@@ -164,6 +193,18 @@ def plan_rollout_chunk(ctx, state, cost, controls, n0: int, n1: int, finalize: b
                                   _dptr(controls, "controls"), K, N, int(n0), int(n1),
                                   int(bool(finalize)))
     _check("plan_rollout_chunk", st, ctx)
+
+
+def plan_rollout_grad(ctx, state0, controls, cost, grad, weight=None, checkpoint_every=10):
+    """cost [K] and grad [N][2][K] (GPU) receive J and w_k dJ_k/du."""
+    N, two, K = controls.shape
+    if two != 2:
+        raise ValueError("controls must be [N][2][K]")
+    s0 = (C.c_float * 13)(*[float(v) for v in state0])
+    st = lib().plan_rollout_grad(ctx, s0, _dptr(controls, "controls"), K, N,
+                                 _dptr(weight, "weight", K), int(checkpoint_every),
+                                 _dptr(cost, "cost", K), _dptr(grad, "grad", 2 * N * K))
+    _check("plan_rollout_grad", st, ctx)
 
 
 def plan_init_state(ctx, state0, state, cost):
@@ -184,6 +225,48 @@ def plan_select(ctx, controls, cost, plan, mode: int = PLAN_ARGMIN, lam: float =
                            C.byref(bc) if want_result else None,
                            _dptr(plan, "plan", 2 * N))
     _check("plan_select", st, ctx)
+    return (bk.value, bc.value) if want_result else None
+
+
+def sample_spec(kind: int, seed: int, stream: int, scale, nominal=None,
+                keep_nominal: bool = False, N: int | None = None) -> Sample:
+    """plan_sample_t for the generator; nominal is a [N][2] float32 GPU tensor
+    or None. The tensor must outlive the calls that use the spec."""
+    if nominal is not None and N is not None and nominal.numel() != 2 * N:
+        raise ValueError("nominal must be [N][2]")
+    return Sample(kind=int(kind), keep_nominal=int(bool(keep_nominal)), seed=int(seed),
+                  stream=int(stream), scale=(C.c_float * 2)(float(scale[0]), float(scale[1])),
+                  nominal_dev=_dptr(nominal, "nominal"))
+
+
+def plan_sample_controls(ctx, spec: Sample, controls):
+    """Fill controls [N][2][K] (GPU) from the generator."""
+    N, two, K = controls.shape
+    if two != 2:
+        raise ValueError("controls must be [N][2][K]")
+    st = lib().plan_sample_controls(ctx, C.byref(spec), K, N, _dptr(controls, "controls"))
+    _check("plan_sample_controls", st, ctx)
+
+
+def plan_rollout_sampled(ctx, state0, spec: Sample, N: int, cost, final_state=None):
+    """Roll out cost.numel() candidates drawn inside the kernel from spec."""
+    K = cost.numel()
+    s0 = (C.c_float * 13)(*[float(v) for v in state0])
+    st = lib().plan_rollout_sampled(ctx, s0, C.byref(spec), K, int(N), _dptr(cost, "cost", K),
+                                    _dptr(final_state, "final_state", 13 * K))
+    _check("plan_rollout_sampled", st, ctx)
+
+
+def plan_select_sampled(ctx, spec: Sample, cost, plan, want_result: bool = True):
+    """Argmin over cost [K]; plan [N][2] gets the winner's regenerated controls."""
+    K = cost.numel()
+    N = plan.numel() // 2
+    bk, bc = C.c_int(0), C.c_float(0)
+    st = lib().plan_select_sampled(ctx, C.byref(spec), _dptr(cost, "cost", K), K, N,
+                                   C.byref(bk) if want_result else None,
+                                   C.byref(bc) if want_result else None,
+                                   _dptr(plan, "plan", 2 * N))
+    _check("plan_select_sampled", st, ctx)
     return (bk.value, bc.value) if want_result else None
 
 
@@ -247,8 +330,14 @@ class Planner:
     def rollout(self, state0, controls, cost, final_state=None):
         plan_rollout(self.ctx, state0, controls, cost, final_state)
 
+    def rollout_est(self, state0, controls, cost, final_state=None):
+        plan_rollout_est(self.ctx, state0, controls, cost, final_state)
+
     def rollout_chunk(self, state, cost, controls, n0, n1, finalize):
         plan_rollout_chunk(self.ctx, state, cost, controls, n0, n1, finalize)
+
+    def rollout_grad(self, state0, controls, cost, grad, weight=None, checkpoint_every=10):
+        plan_rollout_grad(self.ctx, state0, controls, cost, grad, weight, checkpoint_every)
 
     def init_state(self, state0, state, cost):
         plan_init_state(self.ctx, state0, state, cost)
@@ -256,8 +345,144 @@ class Planner:
     def select(self, controls, cost, plan, mode=PLAN_ARGMIN, lam=0.0, want_result=True):
         return plan_select(self.ctx, controls, cost, plan, mode, lam, want_result)
 
+    def sample_controls(self, spec, controls):
+        plan_sample_controls(self.ctx, spec, controls)
+
+    def rollout_sampled(self, state0, spec, N, cost, final_state=None):
+        plan_rollout_sampled(self.ctx, state0, spec, N, cost, final_state)
+
+    def select_sampled(self, spec, cost, plan, want_result=True):
+        return plan_select_sampled(self.ctx, spec, cost, plan, want_result)
+
     def set_launch(self, lanes=0, block=0):
         plan_set_launch(self.ctx, lanes, block)
 
     def get_launch(self):
         return plan_get_launch(self.ctx)
+
+
+# ----------------------------------------------------- serving (plan_serve.h)
+
+class Request(C.Structure):
+    _fields_ = [("height_dev", C.c_void_p), ("W", C.c_int), ("H", C.c_int),
+                ("x0", C.c_float), ("y0", C.c_float), ("res", C.c_float),
+                ("costmap_dev", C.c_void_p), ("state0", C.c_float * 13),
+                ("controls_dev", C.c_void_p), ("K", C.c_int), ("N", C.c_int),
+                ("cost", Cost), ("integ", Integ), ("plan_dev", C.c_void_p)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int), ("best_k", C.c_int), ("best_cost", C.c_float),
+                ("slot", C.c_int), ("t_submit", C.c_double), ("t_admit", C.c_double),
+                ("t_done", C.c_double)]
+
+
+SERVER_EXPORTS = ("plan_server_create", "plan_server_submit", "plan_server_step",
+                  "plan_server_drain", "plan_server_stats", "plan_server_result", "plan_server_now",
+                  "plan_server_destroy", "plan_server_last_error")
+
+_server_bound = False
+
+
+def _bind_server():
+    global _server_bound
+    L = lib()
+    if not _server_bound:
+        vp, ip = C.c_void_p, C.POINTER(C.c_int)
+        L.plan_server_create.argtypes = [C.POINTER(vp), C.POINTER(Vehicle), C.c_int, C.c_int,
+                                         C.c_int, C.c_int, C.c_int, C.c_ulonglong, C.c_int, vp]
+        L.plan_server_submit.argtypes = [vp, C.POINTER(Request), ip]
+        L.plan_server_step.argtypes = [vp, ip, ip]
+        L.plan_server_drain.argtypes = [vp]
+        L.plan_server_result.argtypes = [vp, C.c_int, C.POINTER(Result)]
+        L.plan_server_stats.argtypes = [vp, ip, ip, C.POINTER(C.c_ulonglong)]
+        L.plan_server_now.argtypes = [vp]
+        L.plan_server_now.restype = C.c_double
+        L.plan_server_destroy.argtypes = [vp]
+        L.plan_server_destroy.restype = None
+        L.plan_server_last_error.argtypes = [vp]
+        L.plan_server_last_error.restype = C.c_char_p
+        for n in ("plan_server_create", "plan_server_submit", "plan_server_step",
+                  "plan_server_drain", "plan_server_stats", "plan_server_result"):
+            getattr(L, n).restype = C.c_int
+        _server_bound = True
+    return L
+
+
+def _scheck(fn, st, h):
+    if st != PLAN_OK:
+        d = _bind_server().plan_server_last_error(h)
+        raise PlanError(fn, st, d.decode() if d else "")
+
+
+class Server:
+    """Continuous-batching planning server (one host thread)."""
+
+    def __init__(self, vehicle, max_slots, max_K, max_N, max_W, max_H, budget_bytes,
+                 chunk_intervals=16, stream=None):
+        import torch
+        L = _bind_server()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        v = _struct(Vehicle, vehicle)
+        st = L.plan_server_create(C.byref(h), C.byref(v), int(max_slots), int(max_K), int(max_N),
+                                  int(max_W), int(max_H), C.c_ulonglong(int(budget_bytes)),
+                                  int(chunk_intervals), _stream_handle(self.stream))
+        _scheck("plan_server_create", st, None)
+        self.h = h
+        self._keep = {}
+
+    def submit(self, height, x0, y0, res, state0, controls, cost, integ, plan, costmap=None):
+        """All tensors are kept referenced until the request is read back."""
+        H, W = height.shape
+        N, two, K = controls.shape
+        r = Request(height_dev=_dptr(height, "height").value, W=W, H=H, x0=float(x0),
+                    y0=float(y0), res=float(res),
+                    costmap_dev=None if costmap is None else _dptr(costmap, "costmap", H * W).value,
+                    state0=(C.c_float * 13)(*[float(v) for v in state0]),
+                    controls_dev=_dptr(controls, "controls").value, K=K, N=N,
+                    cost=_struct(Cost, cost), integ=_struct(Integ, integ),
+                    plan_dev=_dptr(plan, "plan", 2 * N).value)
+        rid = C.c_int(-1)
+        _scheck("plan_server_submit", _bind_server().plan_server_submit(self.h, C.byref(r),
+                                                                         C.byref(rid)), self.h)
+        self._keep[rid.value] = (height, controls, plan, costmap)
+        return rid.value
+
+    def step(self):
+        a, q = C.c_int(0), C.c_int(0)
+        _scheck("plan_server_step", _bind_server().plan_server_step(self.h, C.byref(a),
+                                                                     C.byref(q)), self.h)
+        return a.value, q.value
+
+    def stats(self):
+        a, q, u = C.c_int(0), C.c_int(0), C.c_ulonglong(0)
+        _scheck("plan_server_stats", _bind_server().plan_server_stats(
+            self.h, C.byref(a), C.byref(q), C.byref(u)), self.h)
+        return a.value, q.value, u.value
+
+    def drain(self):
+        _scheck("plan_server_drain", _bind_server().plan_server_drain(self.h), self.h)
+
+    def result(self, rid) -> dict:
+        r = Result()
+        _scheck("plan_server_result", _bind_server().plan_server_result(self.h, int(rid),
+                                                                         C.byref(r)), self.h)
+        out = {n: getattr(r, n) for n, _ in Result._fields_}
+        if out["status"] != 0:
+            self._keep.pop(rid, None)
+        return out
+
+    def now(self) -> float:
+        return _bind_server().plan_server_now(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _bind_server().plan_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -4,6 +4,7 @@ device."""
 import ctypes as C
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -14,9 +15,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    src = open(os.path.join(ROOT, "include", "plan.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(plan_[a-z_]+)\s*\(", src)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(plan_[a-z_]+)\s*\(", src))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -28,7 +32,7 @@ def lib():
 
 
 def test_header_declares_the_binding_surface():
-    assert _declared() == sorted(P.EXPORTS)
+    assert _declared() == sorted(P.EXPORTS + P.SERVER_EXPORTS)
 
 
 def test_library_exports_every_declared_symbol(lib):
@@ -72,7 +76,60 @@ def test_calls_on_null_context_are_rejected(lib):
     assert lib.plan_set_stream(None, None) == P.PLAN_EINVAL
     assert lib.plan_set_cost(None, None) == P.PLAN_EINVAL
     assert lib.plan_enable_timing(None, 1) == P.PLAN_EINVAL
+    sp = P.sample_spec(P.PLAN_SAMPLE_UNIFORM, 0, 0, (1.0, 0.0))
+    assert lib.plan_sample_controls(None, C.byref(sp), 1, 1, None) == P.PLAN_EINVAL
+    assert lib.plan_rollout_sampled(None, s0, C.byref(sp), 1, 1, None, None) == P.PLAN_EINVAL
+    assert lib.plan_select_sampled(None, C.byref(sp), None, 1, 1, None, None,
+                                   None) == P.PLAN_EINVAL
     lib.plan_destroy(None)
+
+
+def test_server_create_and_submit_reject_invalid_arguments(lib):
+    P._bind_server()
+    v = P._struct(P.Vehicle, inputs.WORKLOAD_VEHICLE)
+    h = C.c_void_p()
+    cr = lib.plan_server_create
+    assert cr(None, C.byref(v), 4, 8, 8, 8, 8, 1 << 20, 4, None) == P.PLAN_EINVAL
+    assert cr(C.byref(h), C.byref(v), 0, 8, 8, 8, 8, 1 << 20, 4, None) == P.PLAN_EINVAL
+    assert cr(C.byref(h), C.byref(v), 129, 8, 8, 8, 8, 1 << 20, 4, None) == P.PLAN_EINVAL
+    assert cr(C.byref(h), C.byref(v), 4, 8, 8, 8, 8, 0, 4, None) == P.PLAN_EINVAL
+    assert cr(C.byref(h), C.byref(v), 4, 8, 8, 8, 8, 1 << 20, 0, None) == P.PLAN_EINVAL
+    bad = P._struct(P.Vehicle, dict(inputs.WORKLOAD_VEHICLE, M=0.0))
+    assert cr(C.byref(h), C.byref(bad), 4, 8, 8, 8, 8, 1 << 20, 4, None) == P.PLAN_EINVAL
+    assert not h.value
+    rid = C.c_int(0)
+    assert lib.plan_server_submit(None, None, C.byref(rid)) == P.PLAN_EINVAL
+    assert lib.plan_server_step(None, None, None) == P.PLAN_EINVAL
+    assert lib.plan_server_drain(None) == P.PLAN_EINVAL
+    lib.plan_server_destroy(None)
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors have the sizes and offsets the C compiler gives the
+    header's structs."""
+    prog = tmp_path / "layout.c"
+    prog.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "plan.h"\n#include "plan_serve.h"\n'
+        "int main(void) {\n"
+        '  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(plan_sample_t),'
+        " offsetof(plan_sample_t, seed), offsetof(plan_sample_t, stream),"
+        " offsetof(plan_sample_t, scale), offsetof(plan_sample_t, nominal_dev),"
+        " sizeof(plan_vehicle_t));\n"
+        '  printf("%zu %zu %zu %zu\\n", sizeof(plan_request_t),'
+        " offsetof(plan_request_t, controls_dev), offsetof(plan_request_t, plan_dev),"
+        " sizeof(plan_result_t));\n"
+        "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(prog), "-o",
+                    str(exe)], check=True)
+    a, b = subprocess.run([str(exe)], check=True, capture_output=True,
+                          text=True).stdout.split("\n")[:2]
+    a = [int(x) for x in a.split()]
+    b = [int(x) for x in b.split()]
+    assert a == [C.sizeof(P.Sample), P.Sample.seed.offset, P.Sample.stream.offset,
+                 P.Sample.scale.offset, P.Sample.nominal_dev.offset, C.sizeof(P.Vehicle)]
+    assert b == [C.sizeof(P.Request), P.Request.controls_dev.offset, P.Request.plan_dev.offset,
+                 C.sizeof(P.Result)]
 
 
 def test_package_has_no_oracle_or_cpu_fallback():

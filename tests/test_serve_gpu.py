@@ -1,0 +1,175 @@
+"""GPU tests of the continuous-batching server (include/plan_serve.h): every
+request's result is bit-identical to the plain path (plan_rollout +
+plan_select) whether it runs alone or mixed with others, under any arrival
+pattern, tick length, slot limit or memory budget."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2603_20525_amd import inputs  # noqa: E402
+from paper_2603_20525_amd import plan as P  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    P.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+class Resident:
+    """One request's inputs uploaded to the GPU, plus its plain-path answer."""
+
+    def __init__(self, req: inputs.Request):
+        w = req.workload
+        self.w = w
+        self.arrival = req.arrival
+        self.h = dev(w.terrain.height)
+        self.u = dev(w.controls)
+        self.plan = torch.zeros(w.N, 2, device="cuda")
+
+    def plain(self):
+        w, T = self.w, self.w.terrain
+        pl = P.Planner(w.vehicle, w.cost, w.integ, w.K, w.N, T.W, T.H)
+        pl.set_terrain(self.h, T.x0, T.y0, T.res)
+        J = torch.empty(w.K, device="cuda")
+        plan = torch.empty(w.N, 2, device="cuda")
+        pl.rollout(w.state0, self.u, J)
+        k, jb = pl.select(self.u, J, plan)
+        pl.close()
+        return k, jb, plan.cpu().numpy()
+
+    def submit(self, srv):
+        w, T = self.w, self.w.terrain
+        self.plan.zero_()
+        return srv.submit(self.h, T.x0, T.y0, T.res, w.state0, self.u, w.cost, w.integ,
+                          self.plan)
+
+
+@pytest.fixture(scope="module")
+def trace():
+    reqs = [Resident(r) for r in inputs.c3_trace(n_req=12)]
+    for r in reqs:
+        r.ref = r.plain()
+    return reqs
+
+
+def _server(reqs, slots=16, budget=1 << 34, chunk=16):
+    K = max(r.w.K for r in reqs)
+    N = max(r.w.N for r in reqs)
+    return P.Server(inputs.WORKLOAD_VEHICLE, slots, K, N, 256, 256, budget, chunk)
+
+
+def _check(srv, reqs, ids):
+    for r, rid in zip(reqs, ids):
+        res = srv.result(rid)
+        assert res["status"] == 1, res
+        k, jb, plan = r.ref
+        assert res["best_k"] == k
+        assert np.float32(res["best_cost"]) == np.float32(jb)
+        np.testing.assert_array_equal(r.plan.cpu().numpy(), plan)
+        assert res["t_submit"] <= res["t_admit"] <= res["t_done"]
+
+
+def test_burst_results_identical_to_plain_path(trace):
+    srv = _server(trace)
+    ids = [r.submit(srv) for r in trace]
+    srv.drain()
+    _check(srv, trace, ids)
+    srv.close()
+
+
+def test_staggered_arrivals_and_tick_lengths(trace):
+    for chunk in (1, 7, 200):
+        srv = _server(trace, chunk=chunk)
+        ids = []
+        for i, r in enumerate(trace):
+            ids.append(r.submit(srv))
+            for _ in range(i % 3):
+                srv.step()
+        srv.drain()
+        _check(srv, trace, ids)
+        srv.close()
+
+
+def test_slot_limit_bounds_residency(trace):
+    srv = _server(trace, slots=2)
+    ids = [r.submit(srv) for r in trace]
+    peak = 0
+    while True:
+        a, q = srv.step()
+        peak = max(peak, a)
+        if a == 0 and q == 0:
+            break
+    srv.drain()
+    assert peak == 2
+    _check(srv, trace, ids)
+    srv.close()
+
+
+def test_memory_budget_admission(trace):
+    fp = [16 * 256 * 256 + 56 * r.w.K + 8 * r.w.K * r.w.N + 8 * r.w.N for r in trace]
+    budget = max(fp) + min(fp) - 1  # the largest never shares with another
+    srv = _server(trace, budget=budget)
+    ids = [r.submit(srv) for r in trace]
+    blocked = False
+    while True:
+        a, q = srv.step()
+        a2, q2, used = srv.stats()
+        assert used <= budget
+        blocked = blocked or (q2 > 0 and a2 < 16)  # waiting on memory, not on slots
+        if a == 0 and q == 0:
+            break
+    assert blocked
+    srv.drain()
+    _check(srv, trace, ids)
+    with pytest.raises(P.PlanError):
+        small = _server(trace, budget=min(fp) - 1)
+        trace[0].submit(small)
+    srv.close()
+
+
+def test_bad_terrain_request_fails_alone(trace):
+    srv = _server(trace)
+    bad = trace[1]
+    h = bad.w.terrain.height.copy()
+    h[10, 10] = np.nan
+    bad_h = dev(h)
+    ids = []
+    for i, r in enumerate(trace[:4]):
+        if i == 1:
+            T = r.w.terrain
+            ids.append(srv.submit(bad_h, T.x0, T.y0, T.res, r.w.state0, r.u, r.w.cost,
+                                  r.w.integ, r.plan))
+        else:
+            ids.append(r.submit(srv))
+    srv.drain()
+    assert srv.result(ids[1])["status"] == P.PLAN_EINVAL
+    good = [0, 2, 3]
+    _check(srv, [trace[i] for i in good], [ids[i] for i in good])
+    srv.close()
+
+
+def test_submit_validation(trace):
+    srv = _server(trace)
+    r = trace[0]
+    T = r.w.terrain
+    with pytest.raises(P.PlanError):
+        big_u = dev(np.zeros((r.w.N, 2, 20000), np.float32))
+        srv.submit(r.h, T.x0, T.y0, T.res, r.w.state0, big_u, r.w.cost, r.w.integ, r.plan)
+    s_bad = r.w.state0.copy()
+    s_bad[0] = np.nan
+    with pytest.raises(P.PlanError):
+        srv.submit(r.h, T.x0, T.y0, T.res, s_bad, r.u, r.w.cost, r.w.integ, r.plan)
+    with pytest.raises(P.PlanError):
+        srv.submit(r.h, T.x0, T.y0, 0.0, r.w.state0, r.u, r.w.cost, r.w.integ, r.plan)
+    srv.close()
