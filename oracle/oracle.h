@@ -174,7 +174,8 @@ int oracle_est_rhs(const oracle_ctx *o, const double xi[7], double delta_dot, do
                    double xidot[7], oracle_est_diag *diag);
 
 /* EST formulation rollout: same controls layout, goal test, quadrature,
- * clamps and +inf rule as oracle_rollout; final_state is [7][K]. */
+ * clamps, +inf rule and conditioning probe (oracle_set_round32) as
+ * oracle_rollout; final_state is [7][K]. */
 int oracle_est_rollout(const oracle_ctx *o, const float state0[7], const float *controls,
                        int K, int N, double *cost, double *final_state, int *exit_step);
 

@@ -747,6 +747,10 @@ int oracle_est_rollout(const oracle_ctx *o, const float state0[7], const float *
                 for (int q = 0; q < 7; ++q) xi[q] = xi[q] + h * xd[q];
                 xi[5] = clampd(xi[5], -o->v.delta_max, o->v.delta_max);
                 if (xi[6] < o->in.vx_min) xi[6] = o->in.vx_min;
+                if (o->round32) {
+                    for (int q = 0; q < 7; ++q) xi[q] = (double)(float)xi[q];
+                    J = (double)(float)J;
+                }
             }
         }
         J += o->c.w_g * goal_distance(o, xi[0], xi[1]);
