@@ -208,32 +208,55 @@ def main():
     plan = torch.empty(N, 2, device="cuda")
     stream = torch.cuda.current_stream()
 
-    def one_plan():
+    def fused_plan():
+        # one launch: rollout + argmin epilogue; the kernel writes (k*, J*)
+        # to pinned memory, the call waits for it
+        return pl.rollout_argmin(w.state0, u, J, plan)
+
+    def two_call_plan():
         pl.rollout(w.state0, u, J)
         return pl.select(u, J, plan)
 
     for _ in range(args.warmup):
-        one_plan()
+        fused_plan()
+        two_call_plan()
     torch.cuda.synchronize()
     print(f"[bench] warmup {args.warmup} done; launch {pl.get_launch()}", file=sys.stderr,
           flush=True)
 
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
+    # timed region: K plans through the one-launch path
     lat = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         ta = time.perf_counter()
-        ev[i][0].record(stream)
-        pl.rollout(w.state0, u, J)
-        ev[i][1].record(stream)
-        k_best, j_best = pl.select(u, J, plan)
+        k_best, j_best = fused_plan()
         lat.append(time.perf_counter() - ta)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    kern_ms = [a.elapsed_time(b) for a, b in ev]
     print(f"[bench] timed {args.steps} plans in {elapsed:.3f} s", file=sys.stderr, flush=True)
+
+    # kernel durations: the library brackets each rollout kernel with HIP
+    # events on its own stream (a separate pass, so the timed region above
+    # carries no event overhead)
+    pl.enable_timing(True)
+    kern_ms = []
+    for i in range(args.steps):
+        fused_plan()
+        kern_ms.append(pl.last_rollout_ms())
+
+    # the same plans through the two-call path (rollout, then argmin kernel)
+    lat2 = []
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for i in range(args.steps):
+        ta = time.perf_counter()
+        r2 = two_call_plan()
+        lat2.append(time.perf_counter() - ta)
+    torch.cuda.synchronize()
+    elapsed2 = time.perf_counter() - t2
+    pl.enable_timing(False)
+    assert r2 == (k_best, j_best), "fused and two-call plans differ"
 
     steps_per_plan = K * N * S
     value = steps_per_plan * args.steps / elapsed
@@ -254,10 +277,16 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": desc, "K": K, "N": N, "substeps": S, "dt": w.integ["dt"],
-                   "terrain": f"{T.W}x{T.H} at {T.res} m", "launch": {"lanes": lanes, "block": block}},
+                   "terrain": f"{T.W}x{T.H} at {T.res} m", "launch": {"lanes": lanes, "block": block},
+                   "path": "plan_rollout_argmin (rollout + argmin in one launch)"},
         "plan_latency_ms": {"p50": percentile(lat, 50) * 1e3, "p99": percentile(lat, 99) * 1e3,
-                            "path": "plain (one rollout + argmin + readback per plan)"},
-        "rollout_kernel_ms": {"avg": k_avg_s * 1e3, "min": min(kern_ms), "max": max(kern_ms)},
+                            "path": "one launch + wait for (k*, J*) per plan"},
+        "two_call_path": {"rollout_steps_per_s": steps_per_plan * args.steps / elapsed2,
+                          "p50_ms": percentile(lat2, 50) * 1e3,
+                          "p99_ms": percentile(lat2, 99) * 1e3,
+                          "path": "plan_rollout + plan_select(ARGMIN) + wait"},
+        "rollout_kernel_ms": {"avg": k_avg_s * 1e3, "min": min(kern_ms), "max": max(kern_ms),
+                              "kernel": "rollout_srb (fused argmin epilogue)"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_GOPS, "unit": "Gop/s",
                      "frac": achieved / ALU_PEAK_GOPS, "traffic": None,
                      "ops_per_rollout_step": OPS_PER_STEP},

@@ -276,6 +276,30 @@ plan_status_t plan_select_sampled(plan_ctx *ctx, const plan_sample_t *spec,
                                   const float *cost_dev, int K, int N, int *best_k,
                                   float *best_cost, float *plan_dev);
 
+/* plan_rollout followed by plan_select(PLAN_ARGMIN), in ONE kernel launch:
+ * the rollout kernel's last workgroup to finish reduces the candidates'
+ * costs and writes the plan, so a plan costs one launch and (optionally) one
+ * wait. cost_dev, final_state_dev and plan_dev receive bit-identical values
+ * to the two-call sequence; best_k / best_cost (host, NULL to stay
+ * asynchronous) as plan_select, written by the kernel into pinned memory.
+ * Calls on one context must not overlap (they share the context's reduction
+ * slot), which the single stream of a context already guarantees.
+ * Errors: as plan_rollout, plus PLAN_EINVAL for a NULL plan_dev. */
+plan_status_t plan_rollout_argmin(plan_ctx *ctx, const float state0[13],
+                                  const float *controls_dev, int K, int N,
+                                  float *cost_dev, float *final_state_dev,
+                                  float *plan_dev, int *best_k, float *best_cost);
+
+/* plan_rollout_sampled followed by plan_select_sampled, in one launch (the
+ * winner's sequence is regenerated from spec for plan_dev). The paper's
+ * configuration end to end: candidates drawn, simulated, scored and reduced
+ * without any [N][2][K] array in memory. Errors: as plan_rollout_sampled,
+ * plus PLAN_EINVAL for a NULL plan_dev. */
+plan_status_t plan_rollout_sampled_argmin(plan_ctx *ctx, const float state0[13],
+                                          const plan_sample_t *spec, int K, int N,
+                                          float *cost_dev, float *final_state_dev,
+                                          float *plan_dev, int *best_k, float *best_cost);
+
 /* Launch shape of the rollout kernel: lanes per candidate (1, 2 or 4; the
  * four wheels are split over the lanes) and workgroup size (64 or 256).
  * 0 restores the automatic choice. Results are identical for every shape up

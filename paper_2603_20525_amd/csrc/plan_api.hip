@@ -36,7 +36,8 @@ struct plan_ctx {
     int *bad_host = nullptr;  // pinned
     // selection workspace
     unsigned long long *part_keys = nullptr;
-    unsigned int *counters = nullptr;  // [0] argmin ticket, [1] softmin ticket
+    unsigned int *counters = nullptr;  // tickets: [0] argmin, [1] softmin, [2] fused argmin
+    unsigned long long *fused_key = nullptr;  // fused argmin slot, all ones between launches
     float *wpart = nullptr;
     SelectOut *sel_dev = nullptr;
     SelectOut *sel_host = nullptr;  // pinned
@@ -88,6 +89,7 @@ static void release(plan_ctx *c) {
     (void)hipFree(c->bad_dev);
     (void)hipFree(c->part_keys);
     (void)hipFree(c->counters);
+    (void)hipFree(c->fused_key);
     (void)hipFree(c->wpart);
     (void)hipFree(c->sel_dev);
     (void)hipFree(c->gws);
@@ -254,6 +256,8 @@ plan_status_t plan_create(plan_ctx **out, const plan_vehicle_t *veh, const plan_
     CREATE_TRY(hipMalloc(&c->part_keys, sizeof(unsigned long long) * nb));
     CREATE_TRY(hipMalloc(&c->counters, sizeof(unsigned int) * 4));
     CREATE_TRY(hipMemset(c->counters, 0, sizeof(unsigned int) * 4));
+    CREATE_TRY(hipMalloc(&c->fused_key, sizeof(unsigned long long)));
+    CREATE_TRY(hipMemset(c->fused_key, 0xFF, sizeof(unsigned long long)));
     const size_t wsz = (size_t)plan::softmin_chunks(max_K) * (2 * (size_t)max_N + 1);
     CREATE_TRY(hipMalloc(&c->wpart, sizeof(float) * wsz));
     CREATE_TRY(hipMalloc(&c->sel_dev, sizeof(SelectOut)));
@@ -306,7 +310,9 @@ plan_status_t plan_set_terrain(plan_ctx *c, const float *height_dev, int W, int 
     return PLAN_OK;
 }
 
-static plan_status_t launch(plan_ctx *c, RolloutArgs &a, bool chunk, bool sampled = false) {
+enum class Kind { plain, chunk, sampled, fused, fused_sampled };
+
+static plan_status_t launch(plan_ctx *c, RolloutArgs &a, Kind kind) {
     int lanes, block;
     auto_launch(a.K, &lanes, &block);
     if (c->lanes_opt) lanes = c->lanes_opt;
@@ -315,10 +321,20 @@ static plan_status_t launch(plan_ctx *c, RolloutArgs &a, bool chunk, bool sample
     c->last_block = block;
     HIP_TRY(c, hipSetDevice(c->device));
     if (c->timing) HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
-    if (sampled)
+    switch (kind) {
+    case Kind::plain:
+    case Kind::chunk:
+        HIP_TRY(c, plan::launch_rollout(a, lanes, block, kind == Kind::chunk, c->stream));
+        break;
+    case Kind::sampled:
         HIP_TRY(c, plan::launch_rollout_sampled(a, lanes, block, c->stream));
-    else
-        HIP_TRY(c, plan::launch_rollout(a, lanes, block, chunk, c->stream));
+        break;
+    case Kind::fused:
+    case Kind::fused_sampled:
+        HIP_TRY(c, plan::launch_rollout_argmin(a, lanes, block, kind == Kind::fused_sampled,
+                                               c->stream));
+        break;
+    }
     if (c->timing) {
         HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
         c->ev_recorded = true;
@@ -345,7 +361,7 @@ plan_status_t plan_rollout(plan_ctx *c, const float state0[13], const float *con
     a.finalize = 1;
     a.cost = cost_dev;
     a.final_state = final_state_dev;
-    return launch(c, a, false);
+    return launch(c, a, Kind::plain);
 }
 
 // Validated generator arguments of a plan_sample_t.
@@ -400,7 +416,7 @@ plan_status_t plan_rollout_sampled(plan_ctx *c, const float state0[13], const pl
     a.finalize = 1;
     a.cost = cost_dev;
     a.final_state = final_state_dev;
-    return launch(c, a, false, true);
+    return launch(c, a, Kind::sampled);
 }
 
 plan_status_t plan_select_sampled(plan_ctx *c, const plan_sample_t *spec, const float *cost_dev,
@@ -413,11 +429,11 @@ plan_status_t plan_select_sampled(plan_ctx *c, const plan_sample_t *spec, const 
     plan_status_t st = sample_args(c, spec, sa);
     if (st != PLAN_OK) return st;
     HIP_TRY(c, hipSetDevice(c->device));
+    const bool want = best_k || best_cost;
     HIP_TRY(c, plan::launch_select_sampled(sa, cost_dev, K, N, c->veh.delta_rate_max, plan_dev,
-                                           c->part_keys, c->counters, c->sel_dev, c->stream));
-    if (best_k || best_cost) {
-        HIP_TRY(c, hipMemcpyAsync(c->sel_host, c->sel_dev, sizeof(SelectOut),
-                                  hipMemcpyDeviceToHost, c->stream));
+                                           c->part_keys, c->counters, c->sel_dev,
+                                           want ? c->sel_host : nullptr, c->stream));
+    if (want) {
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         if (best_k) *best_k = c->sel_host->best_k;
         if (best_cost) *best_cost = c->sel_host->best_cost;
@@ -455,6 +471,74 @@ plan_status_t plan_rollout_est(plan_ctx *c, const float state0[7], const float *
     return PLAN_OK;
 }
 
+// Shared tail of the fused entry points: outputs of the epilogue, launch,
+// optional wait for the host copy of (k*, J*).
+static plan_status_t fused_launch(plan_ctx *c, RolloutArgs &a, bool sampled, float *plan_dev,
+                                  int *best_k, float *best_cost) {
+    const bool want = best_k || best_cost;
+    a.sel_key = c->fused_key;
+    a.sel_ticket = c->counters + 2;
+    a.plan = plan_dev;
+    a.sel_out = c->sel_dev;
+    a.sel_out_host = want ? c->sel_host : nullptr;
+    plan_status_t st = launch(c, a, sampled ? Kind::fused_sampled : Kind::fused);
+    if (st != PLAN_OK || !want) return st;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (best_k) *best_k = c->sel_host->best_k;
+    if (best_cost) *best_cost = c->sel_host->best_cost;
+    return PLAN_OK;
+}
+
+plan_status_t plan_rollout_argmin(plan_ctx *c, const float state0[13], const float *controls_dev,
+                                  int K, int N, float *cost_dev, float *final_state_dev,
+                                  float *plan_dev, int *best_k, float *best_cost) {
+    if (!c) return PLAN_EINVAL;
+    if (!state0 || !controls_dev || !cost_dev || !plan_dev)
+        return fail(c, PLAN_EINVAL, "NULL argument");
+    if (K < 1 || K > c->max_K) return fail(c, PLAN_EINVAL, "K outside [1, max_K]");
+    if (N < 1 || N > c->max_N) return fail(c, PLAN_EINVAL, "N outside [1, max_N]");
+    if (!finite_all(state0, 13)) return fail(c, PLAN_EINVAL, "state0 not finite");
+    if (!c->has_terrain) return fail(c, PLAN_ENOTERRAIN, "no terrain set");
+    RolloutArgs a;
+    fill_args(c, a);
+    for (int q = 0; q < 13; ++q) a.s0[q] = state0[q];
+    a.controls = controls_dev;
+    a.K = K;
+    a.N = N;
+    a.n0 = 0;
+    a.n1 = N;
+    a.finalize = 1;
+    a.cost = cost_dev;
+    a.final_state = final_state_dev;
+    return fused_launch(c, a, false, plan_dev, best_k, best_cost);
+}
+
+plan_status_t plan_rollout_sampled_argmin(plan_ctx *c, const float state0[13],
+                                          const plan_sample_t *spec, int K, int N,
+                                          float *cost_dev, float *final_state_dev,
+                                          float *plan_dev, int *best_k, float *best_cost) {
+    if (!c) return PLAN_EINVAL;
+    if (!state0 || !cost_dev || !plan_dev) return fail(c, PLAN_EINVAL, "NULL argument");
+    if (K < 1 || K > c->max_K) return fail(c, PLAN_EINVAL, "K outside [1, max_K]");
+    if (N < 1 || N > c->max_N) return fail(c, PLAN_EINVAL, "N outside [1, max_N]");
+    if (!finite_all(state0, 13)) return fail(c, PLAN_EINVAL, "state0 not finite");
+    RolloutArgs a;
+    fill_args(c, a);
+    plan_status_t st = sample_args(c, spec, a.smp);
+    if (st != PLAN_OK) return st;
+    if (!c->has_terrain) return fail(c, PLAN_ENOTERRAIN, "no terrain set");
+    for (int q = 0; q < 13; ++q) a.s0[q] = state0[q];
+    a.controls = nullptr;
+    a.K = K;
+    a.N = N;
+    a.n0 = 0;
+    a.n1 = N;
+    a.finalize = 1;
+    a.cost = cost_dev;
+    a.final_state = final_state_dev;
+    return fused_launch(c, a, true, plan_dev, best_k, best_cost);
+}
+
 plan_status_t plan_init_state(plan_ctx *c, const float state0[13], float *state_dev,
                               float *cost_dev, int K) {
     if (!c) return PLAN_EINVAL;
@@ -485,7 +569,7 @@ plan_status_t plan_rollout_chunk(plan_ctx *c, float *state_dev, float *cost_dev,
     a.finalize = finalize != 0;
     a.cost = cost_dev;
     a.state = state_dev;
-    return launch(c, a, true);
+    return launch(c, a, Kind::chunk);
 }
 
 plan_status_t plan_rollout_grad(plan_ctx *c, const float state0[13], const float *controls_dev,
@@ -537,7 +621,7 @@ plan_status_t plan_rollout_grad(plan_ctx *c, const float state0[13], const float
         a.n0 = seg * C;
         a.n1 = (seg + 1) * C < N ? (seg + 1) * C : N;
         a.finalize = a.n1 == N;
-        plan_status_t st = launch(c, a, true);
+        plan_status_t st = launch(c, a, Kind::chunk);
         if (st != PLAN_OK) return st;
         HIP_TRY(c, hipMemcpyAsync(ckpt + (size_t)(seg + 1) * 13 * Kz, state,
                                   sizeof(float) * 13 * Kz, hipMemcpyDeviceToDevice, c->stream));
@@ -561,12 +645,12 @@ plan_status_t plan_select(plan_ctx *c, int mode, float lambda, const float *cont
     if (mode == PLAN_SOFTMIN && !(lambda > 0 && isfinite(lambda)))
         return fail(c, PLAN_EINVAL, "softmin needs a finite lambda > 0");
     HIP_TRY(c, hipSetDevice(c->device));
+    const bool want = best_k || best_cost;
     HIP_TRY(c, plan::launch_select(mode, lambda, controls_dev, cost_dev, K, N,
                                    c->veh.delta_rate_max, plan_dev, c->part_keys, c->counters,
-                                   c->wpart, c->sel_dev, c->stream));
-    if (best_k || best_cost) {
-        HIP_TRY(c, hipMemcpyAsync(c->sel_host, c->sel_dev, sizeof(SelectOut),
-                                  hipMemcpyDeviceToHost, c->stream));
+                                   c->wpart, c->sel_dev, want ? c->sel_host : nullptr,
+                                   c->stream));
+    if (want) {
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         if (best_k) *best_k = c->sel_host->best_k;
         if (best_cost) *best_cost = c->sel_host->best_cost;

@@ -9,6 +9,12 @@
 
 namespace plan {
 
+struct SelectOut {
+    int best_k;
+    float best_cost;
+    uint32_t pad[2];  // pad[0]: status of the request (0 or a plan_status_t)
+};
+
 // Everything one rollout needs, passed by value as the kernel argument
 // (a few hundred bytes, well inside the kernarg limit). All derived constants
 // are computed once on the host in double precision and rounded to float.
@@ -52,6 +58,12 @@ struct RolloutArgs {
     float *final_state;            // full: [13][K] or nullptr
     float *state;                  // chunk: [13][K], read and written
     SampleArgs smp;                // sampled launches: the candidate generator
+    // fused argmin epilogue: packed-key slot (all ones between launches),
+    // arrival ticket (zero between launches), plan [N][2], result copies
+    unsigned long long *sel_key;
+    unsigned int *sel_ticket;
+    float *plan;
+    SelectOut *sel_out, *sel_out_host;
 };
 
 // One tick of the serving loop: which slots advance through which control
@@ -71,12 +83,6 @@ struct TickTable {
     TickEntry e[MAX_TICK_SLOTS];
 };
 
-struct SelectOut {
-    int best_k;
-    float best_cost;
-    uint32_t pad[2];  // pad[0]: status of the request (0 or a plan_status_t)
-};
-
 struct SlotList {
     int count;
     int slot[MAX_TICK_SLOTS];
@@ -85,6 +91,11 @@ struct SlotList {
 // chunk = false: candidates start from s0 with zero cost. chunk = true:
 // they continue from a.state / a.cost. Both run the same step code.
 hipError_t launch_rollout(const RolloutArgs &a, int lanes, int block, bool chunk, hipStream_t s);
+
+// Full-horizon rollout whose last workgroup to finish also selects the argmin
+// (a.sel_* and a.plan), with controls read (sampled = false) or drawn.
+hipError_t launch_rollout_argmin(const RolloutArgs &a, int lanes, int block, bool sampled,
+                                 hipStream_t s);
 
 // As launch_rollout (full horizon from a.s0) with the controls drawn in the
 // kernel from a.smp instead of read from a.controls.
@@ -121,13 +132,13 @@ int softmin_row_groups(int N);
 hipError_t launch_select(int mode, float lambda, const float *controls, const float *cost,
                          int K, int N, float drate_max, float *plan_out,
                          unsigned long long *part_keys, unsigned int *counters,
-                         float *wpart, SelectOut *out, hipStream_t s);
+                         float *wpart, SelectOut *out, SelectOut *out_host, hipStream_t s);
 
 // Argmin whose plan is the winner's sequence regenerated from the sampler.
 hipError_t launch_select_sampled(const SampleArgs &sa, const float *cost, int K, int N,
                                  float drate_max, float *plan_out,
                                  unsigned long long *part_keys, unsigned int *counters,
-                                 SelectOut *out, hipStream_t s);
+                                 SelectOut *out, SelectOut *out_host, hipStream_t s);
 
 // Host helpers shared by the plan and server entry points.
 void fill_rollout_args(RolloutArgs &a, const plan_vehicle_t &v, const plan_cost_t &co,

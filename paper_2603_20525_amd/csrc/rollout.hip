@@ -24,6 +24,7 @@
 
 #include "plan_internal.h"
 #include "rollout_step.h"
+#include "select_common.h"
 
 namespace plan {
 namespace {
@@ -36,7 +37,7 @@ namespace {
 // a.controls. Lanes with store == false run a duplicate candidate only to
 // keep their lane group complete.
 template <int LANES, bool CHUNK, bool SAMPLED = false>
-__device__ __forceinline__ void simulate(const RolloutArgs &a, int k, int sub, bool store) {
+__device__ __forceinline__ float simulate(const RolloutArgs &a, int k, int sub, bool store) {
     constexpr int WPL = 4 / LANES;  // wheels per lane
     const size_t K = (size_t)a.K;
 
@@ -113,18 +114,65 @@ __device__ __forceinline__ void simulate(const RolloutArgs &a, int k, int sub, b
                 if ((q & (LANES - 1)) == sub) out[(size_t)q * K + k] = st[q];
         }
     }
+    return J;
 }
 
-template <int LANES, int BLOCK, bool CHUNK, bool SAMPLED = false>
+// Fused argmin: every workgroup reduces its candidates' packed keys and
+// folds the result into a.sel_key with an atomic minimum (order-independent,
+// so the winner is the same as the separate selection kernel's); the last
+// workgroup to arrive publishes (k*, J*), writes the plan and resets the key
+// and the ticket for the next launch.
+template <int BLOCK, bool SAMPLED>
+__device__ __forceinline__ void argmin_epilogue(const RolloutArgs &a, unsigned long long key) {
+    __shared__ unsigned long long red[BLOCK / 64];
+    __shared__ int last_sh;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    key = wave_min(key);
+    if (lane == 0) red[wv] = key;
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long b = red[0];
+#pragma unroll
+        for (int q = 1; q < BLOCK / 64; ++q) b = red[q] < b ? red[q] : b;
+        if (b != ~0ull) atomicMin(a.sel_key, b);
+        __threadfence();
+        const unsigned int t = atomicAdd(a.sel_ticket, 1u);
+        last_sh = (t == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last_sh) return;
+    __threadfence();
+    if (tid == 0) {
+        const unsigned long long m = __atomic_load_n(a.sel_key, __ATOMIC_RELAXED);
+        red[0] = m;
+        SelectOut o;
+        o.best_k = (m == ~0ull) ? -1 : (int)(unsigned int)(m & 0xffffffffu);
+        o.best_cost = (m == ~0ull) ? __builtin_inff() : key_cost(m);
+        o.pad[0] = o.pad[1] = 0;
+        *a.sel_out = o;
+        if (a.sel_out_host) *a.sel_out_host = o;
+        *a.sel_key = ~0ull;
+        *a.sel_ticket = 0u;
+    }
+    __syncthreads();
+    const unsigned long long m = red[0];
+    const int kb = (m == ~0ull) ? -1 : (int)(unsigned int)(m & 0xffffffffu);
+    write_plan<SAMPLED>(kb, a.N, a.K, a.controls, a.smp, a.drate_max, a.plan, tid, BLOCK);
+}
+
+template <int LANES, int BLOCK, bool CHUNK, bool SAMPLED = false, bool FUSED = false>
 __global__ __launch_bounds__(BLOCK) void rollout_srb(const RolloutArgs a) {
     const int gtid = blockIdx.x * BLOCK + threadIdx.x;
     const int sub = gtid & (LANES - 1);
     int k = gtid / LANES;
     const bool store = k < a.K;
     // Lanes past K simulate the last candidate again so that every lane group
-    // is complete for the DPP sums; they store nothing.
+    // is complete for the DPP sums; they store nothing (and reach the fused
+    // epilogue's barriers like every other lane).
     if (!store) k = a.K - 1;
-    simulate<LANES, CHUNK, SAMPLED>(a, k, sub, store);
+    const float J = simulate<LANES, CHUNK, SAMPLED>(a, k, sub, store);
+    if constexpr (FUSED)
+        argmin_epilogue<BLOCK, SAMPLED>(a, (store && sub == 0) ? cost_key(J, k) : ~0ull);
 }
 
 // controls [N][2][K] from the generator: thread (k, b) draws intervals
@@ -221,6 +269,31 @@ hipError_t launch_rollout_sampled(const RolloutArgs &a, int lanes, int block, hi
     PLAN_LAUNCH(1, 256)
     PLAN_LAUNCH(2, 256)
     PLAN_LAUNCH(4, 256)
+#undef PLAN_LAUNCH
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_rollout_argmin(const RolloutArgs &a, int lanes, int block, bool sampled,
+                                 hipStream_t s) {
+    const long long threads = (long long)a.K * lanes;
+    const unsigned grid = (unsigned)((threads + block - 1) / block);
+#define PLAN_LAUNCH(L, B, SMP)                                                              \
+    if (lanes == L && block == B && sampled == SMP) {                                       \
+        hipLaunchKernelGGL((rollout_srb<L, B, false, SMP, true>), dim3(grid), dim3(B), 0, s, a); \
+        return hipGetLastError();                                                           \
+    }
+    PLAN_LAUNCH(1, 64, false)
+    PLAN_LAUNCH(2, 64, false)
+    PLAN_LAUNCH(4, 64, false)
+    PLAN_LAUNCH(1, 256, false)
+    PLAN_LAUNCH(2, 256, false)
+    PLAN_LAUNCH(4, 256, false)
+    PLAN_LAUNCH(1, 64, true)
+    PLAN_LAUNCH(2, 64, true)
+    PLAN_LAUNCH(4, 64, true)
+    PLAN_LAUNCH(1, 256, true)
+    PLAN_LAUNCH(2, 256, true)
+    PLAN_LAUNCH(4, 256, true)
 #undef PLAN_LAUNCH
     return hipErrorInvalidValue;
 }

@@ -124,12 +124,38 @@ struct Motion {
     float delta, cosd, FxR;
 };
 
-__device__ __forceinline__ WheelOut wheel(const RolloutArgs &a, const Attitude &A,
-                                          const Motion &m, const Arm &r, const Gather &g) {
+// Terrain-independent part of one wheel: contact-point velocity, slip angle
+// and the tire's force-per-load factor, computed while the gathers are in
+// flight.
+struct WheelPre {
+    float vix, viy, viz;
+    float tire, q;  // -C alpha mu and 1 / sqrt(mu^2 + (C alpha)^2)
+};
+
+__device__ __forceinline__ WheelPre wheel_pre(const RolloutArgs &a, const Motion &m,
+                                              const Arm &r) {
+    WheelPre p;
     // contact-point velocity v + w x rho (body)
-    const float vix = fmaf(m.wy, r.rz, fmaf(-m.wz, r.ry, m.vx));
-    const float viy = fmaf(m.wz, r.rx, fmaf(-m.wx, r.rz, m.vy));
-    const float viz = fmaf(m.wx, r.ry, fmaf(-m.wy, r.rx, m.vz));
+    p.vix = fmaf(m.wy, r.rz, fmaf(-m.wz, r.ry, m.vx));
+    p.viy = fmaf(m.wz, r.rx, fmaf(-m.wx, r.rz, m.vy));
+    p.viz = fmaf(m.wx, r.ry, fmaf(-m.wy, r.rx, m.vz));
+    // slip angle (literal atan of the velocity ratio; 0/0 gives -delta_i),
+    // evaluated without a branch so the step stays one basic block
+    const float dl = r.front ? m.delta : 0.0f;
+    const bool guard = (p.vix == 0.0f && p.viy == 0.0f);
+    const float ratio = guard ? 0.0f : p.viy * frcp(p.vix);
+    const float at = atanf(ratio);
+    const float alpha = guard ? -dl : at - dl;
+    const float Ca = a.C * alpha;
+    p.tire = -Ca * a.mu;
+    p.q = frsq(fmaf(Ca, Ca, a.mu2));
+    return p;
+}
+
+__device__ __forceinline__ WheelOut wheel(const RolloutArgs &a, const Attitude &A,
+                                          const Motion &m, const Arm &r, const Gather &g,
+                                          const WheelPre &p) {
+    const float vix = p.vix, viy = p.viy, viz = p.viz;
     // bilinear height, slopes and cost rate at the contact point
     const float th = lerp2(g.tx, g.ty, g.t00.x, g.t10.x, g.t01.x, g.t11.x);
     const float tfx = lerp2(g.tx, g.ty, g.t00.y, g.t10.y, g.t01.y, g.t11.y);
@@ -152,11 +178,8 @@ __device__ __forceinline__ WheelOut wheel(const RolloutArgs &a, const Attitude &
     const float Fk = fmaxf(fmaf(-k, chi, Fs), 0.0f);
     const float Fb = (Fk > 0.0f) ? fmaxf(-b * chid, -Fk) : 0.0f;
     const float Fz = Fk + Fb;
-    // slip angle (literal atan of the velocity ratio) and sigmoid tire
-    const float dl = r.front ? m.delta : 0.0f;
-    const float alpha = (vix == 0.0f && viy == 0.0f) ? -dl : atanf(viy * frcp(vix)) - dl;
-    const float Ca = a.C * alpha;
-    const float Fy = (Fz * (-Ca * a.mu)) * frsq(fmaf(Ca, Ca, a.mu2));
+    // sigmoid tire
+    const float Fy = (Fz * p.tire) * p.q;
     const float Fx = r.front ? 0.0f : m.FxR;
     const float fy = r.front ? Fy * m.cosd : Fy;
     WheelOut o;
@@ -225,19 +248,26 @@ __device__ __forceinline__ void euler_step(const RolloutArgs &a, const Arm (&arm
     const float mm = fmaxf(0.0f, fmaf(-U, a.inv_eps_esm, 1.0f));
     const float L0 = fmaf(a.w_c * dd, dd, a.w_t) + (a.sigma * mm) * mm;
 
+    WheelPre pre[WPL];
+#pragma unroll
+    for (int q = 0; q < WPL; ++q) pre[q] = wheel_pre(a, m, arms[q]);
+    // everything above is independent of the terrain: keep it between the
+    // gather issue and the first use of a texel
+    __builtin_amdgcn_sched_barrier(0);
+
     // wheel forces: this lane's share, then the group sum in fixed
     // order (w0 + w1) + (w2 + w3)
     WheelOut sum;
     if constexpr (WPL == 4) {
-        const WheelOut w0 = wheel(a, A, m, arms[0], G[0]);
-        const WheelOut w1 = wheel(a, A, m, arms[1], G[1]);
-        const WheelOut w2 = wheel(a, A, m, arms[2], G[2]);
-        const WheelOut w3 = wheel(a, A, m, arms[3], G[3]);
+        const WheelOut w0 = wheel(a, A, m, arms[0], G[0], pre[0]);
+        const WheelOut w1 = wheel(a, A, m, arms[1], G[1], pre[1]);
+        const WheelOut w2 = wheel(a, A, m, arms[2], G[2], pre[2]);
+        const WheelOut w3 = wheel(a, A, m, arms[3], G[3], pre[3]);
         sum = wadd(wadd(w0, w1), wadd(w2, w3));
     } else if constexpr (WPL == 2) {
-        sum = wadd(wheel(a, A, m, arms[0], G[0]), wheel(a, A, m, arms[1], G[1]));
+        sum = wadd(wheel(a, A, m, arms[0], G[0], pre[0]), wheel(a, A, m, arms[1], G[1], pre[1]));
     } else {
-        sum = wheel(a, A, m, arms[0], G[0]);
+        sum = wheel(a, A, m, arms[0], G[0], pre[0]);
     }
     const float Fy = group_sum<LANES>(sum.Fy);
     const float Fz = group_sum<LANES>(sum.Fz);

@@ -9,6 +9,7 @@
 // reductions finish in the last block to arrive (an atomic ticket), which
 // resets the ticket for the next call, so no memset is needed between calls.
 #include "plan_internal.h"
+#include "select_common.h"
 
 namespace plan {
 namespace {
@@ -50,28 +51,6 @@ __global__ __launch_bounds__(256) void pack_terrain(const float *__restrict__ hg
 }
 
 // ---------------------------------------------------------------- argmin ----
-__device__ __forceinline__ unsigned long long cost_key(float J, int k) {
-    if (!isfinite(J)) return ~0ull;
-    unsigned int b = __float_as_uint(J);
-    b = (b & 0x80000000u) ? ~b : (b | 0x80000000u);  // order-preserving
-    return ((unsigned long long)b << 32) | (unsigned int)k;
-}
-
-__device__ __forceinline__ float key_cost(unsigned long long key) {
-    unsigned int b = (unsigned int)(key >> 32);
-    b = (b & 0x80000000u) ? (b & 0x7fffffffu) : ~b;
-    return __uint_as_float(b);
-}
-
-__device__ __forceinline__ unsigned long long wave_min(unsigned long long v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        unsigned long long o = __shfl_xor(v, off, 64);
-        v = o < v ? o : v;
-    }
-    return v;
-}
-
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -83,11 +62,6 @@ __device__ __forceinline__ float load_partial(const float *p) {
     return __uint_as_float(__atomic_load_n((const unsigned int *)p, __ATOMIC_RELAXED));
 }
 
-__device__ __forceinline__ float clamp_ctrl(float u, int row, float drate_max) {
-    const float lim = (row & 1) ? 1.0f : drate_max;
-    return u < -lim ? -lim : (u > lim ? lim : u);
-}
-
 // One block per SEL_CHUNK candidates; the last block to finish reduces the
 // per-block keys, publishes (k*, J*) and, for argmin, gathers the plan: from
 // controls, or (SAMPLED) by regenerating candidate k*'s sequence.
@@ -96,7 +70,7 @@ __global__ __launch_bounds__(SEL_BLOCK) void select_argmin(
     const float *__restrict__ cost, int K, const float *__restrict__ controls, int N,
     float drate_max, int gather, float *__restrict__ plan,
     unsigned long long *__restrict__ part, unsigned int *__restrict__ ticket,
-    SelectOut *__restrict__ out, const SampleArgs smp) {
+    SelectOut *__restrict__ out, SelectOut *out_host, const SampleArgs smp) {
     __shared__ unsigned long long red[SEL_BLOCK / 64];
     __shared__ unsigned long long best_sh;
     __shared__ int last_sh;
@@ -148,29 +122,14 @@ __global__ __launch_bounds__(SEL_BLOCK) void select_argmin(
         }
         o.pad[0] = o.pad[1] = 0;
         *out = o;
+        if (out_host) *out_host = o;  // pinned host copy: no readback copy needed
         *ticket = 0u;  // ready for the next call
     }
     __syncthreads();
     if (gather) {
         const unsigned long long m = best_sh;
         const int kb = (m == ~0ull) ? -1 : (int)(unsigned int)(m & 0xffffffffu);
-        if constexpr (SAMPLED) {
-            for (int n = tid; n < N; n += SEL_BLOCK) {
-                float u0 = 0.0f, u1 = 0.0f;
-                if (kb >= 0) {
-                    const PhiloxBlock blk = sample_block(smp, kb, n >> 2);
-                    draw_controls(smp, block_word(blk, n & 3), kb, n, u0, u1);
-                    u0 = clamp_ctrl(u0, 0, drate_max);
-                    u1 = clamp_ctrl(u1, 1, drate_max);
-                }
-                plan[2 * n] = u0;
-                plan[2 * n + 1] = u1;
-            }
-        } else {
-            for (int e = tid; e < 2 * N; e += SEL_BLOCK)
-                plan[e] =
-                    (kb < 0) ? 0.0f : clamp_ctrl(controls[(size_t)e * K + kb], e, drate_max);
-        }
+        write_plan<SAMPLED>(kb, N, K, controls, smp, drate_max, plan, tid, SEL_BLOCK);
     }
 }
 
@@ -314,11 +273,11 @@ hipError_t launch_pack_terrain(const float *h, const float *c, int W, int H, flo
 hipError_t launch_select(int mode, float lambda, const float *controls, const float *cost,
                          int K, int N, float drate_max, float *plan_out,
                          unsigned long long *part_keys, unsigned int *counters, float *wpart,
-                         SelectOut *out, hipStream_t s) {
+                         SelectOut *out, SelectOut *out_host, hipStream_t s) {
     const int nb = select_blocks(K);
     hipLaunchKernelGGL(select_argmin<false>, dim3(nb), dim3(SEL_BLOCK), 0, s, cost, K, controls,
                        N, drate_max, mode == 0 ? 1 : 0, plan_out, part_keys, counters + 0, out,
-                       SampleArgs{});
+                       out_host, SampleArgs{});
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || mode == 0) return e;
     dim3 grid(softmin_chunks(K), softmin_row_groups(N));
@@ -331,10 +290,10 @@ hipError_t launch_select(int mode, float lambda, const float *controls, const fl
 hipError_t launch_select_sampled(const SampleArgs &sa, const float *cost, int K, int N,
                                  float drate_max, float *plan_out,
                                  unsigned long long *part_keys, unsigned int *counters,
-                                 SelectOut *out, hipStream_t s) {
+                                 SelectOut *out, SelectOut *out_host, hipStream_t s) {
     const int nb = select_blocks(K);
     hipLaunchKernelGGL(select_argmin<true>, dim3(nb), dim3(SEL_BLOCK), 0, s, cost, K, nullptr, N,
-                       drate_max, 1, plan_out, part_keys, counters + 0, out, sa);
+                       drate_max, 1, plan_out, part_keys, counters + 0, out, out_host, sa);
     return hipGetLastError();
 }
 

@@ -1,0 +1,72 @@
+// Device helpers shared by the selection kernels and the rollout kernel's
+// fused argmin epilogue (section "Real-Time Implementation": the sampled
+// candidate of minimal cost is the plan).
+//
+// The argmin reduces 64-bit keys (order-preserving cost bits << 32 | k): the
+// minimum of a set of keys does not depend on the order in which it is taken,
+// so any reduction tree gives the same winner, and equal costs resolve to the
+// lowest k. Non-finite costs map to the largest key and are never selected.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sample.h"
+
+namespace plan {
+
+__device__ __forceinline__ unsigned long long cost_key(float J, int k) {
+    if (!isfinite(J)) return ~0ull;
+    unsigned int b = __float_as_uint(J);
+    b = (b & 0x80000000u) ? ~b : (b | 0x80000000u);  // order-preserving
+    return ((unsigned long long)b << 32) | (unsigned int)k;
+}
+
+__device__ __forceinline__ float key_cost(unsigned long long key) {
+    unsigned int b = (unsigned int)(key >> 32);
+    b = (b & 0x80000000u) ? (b & 0x7fffffffu) : ~b;
+    return __uint_as_float(b);
+}
+
+__device__ __forceinline__ unsigned long long wave_min(unsigned long long v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        unsigned long long o = __shfl_xor(v, off, 64);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+// Admissible-set clamp of plan row `row` ([N][2] flattened: even rows are
+// steering rates, odd rows throttle).
+__device__ __forceinline__ float clamp_ctrl(float u, int row, float drate_max) {
+    const float lim = (row & 1) ? 1.0f : drate_max;
+    return u < -lim ? -lim : (u > lim ? lim : u);
+}
+
+// Plan output [N][2] for the selected candidate kb (zeros if kb < 0): its
+// clamped controls, read from controls [N][2][K] or, SAMPLED, regenerated
+// from the generator. Threads tid, tid + nthreads, ... share the work.
+template <bool SAMPLED>
+__device__ __forceinline__ void write_plan(int kb, int N, int K, const float *controls,
+                                           const SampleArgs &smp, float drate_max, float *plan,
+                                           int tid, int nthreads) {
+    if constexpr (SAMPLED) {
+        for (int n = tid; n < N; n += nthreads) {
+            float u0 = 0.0f, u1 = 0.0f;
+            if (kb >= 0) {
+                const PhiloxBlock blk = sample_block(smp, kb, n >> 2);
+                draw_controls(smp, block_word(blk, n & 3), kb, n, u0, u1);
+                u0 = clamp_ctrl(u0, 0, drate_max);
+                u1 = clamp_ctrl(u1, 1, drate_max);
+            }
+            plan[2 * n] = u0;
+            plan[2 * n + 1] = u1;
+        }
+    } else {
+        for (int e = tid; e < 2 * N; e += nthreads)
+            plan[e] = (kb < 0) ? 0.0f : clamp_ctrl(controls[(size_t)e * K + kb], e, drate_max);
+    }
+}
+
+}  // namespace plan

@@ -54,6 +54,7 @@ class Sample(C.Structure):
 EXPORTS = ("plan_create", "plan_set_stream", "plan_set_cost", "plan_set_terrain",
            "plan_rollout", "plan_rollout_est", "plan_rollout_chunk", "plan_init_state", "plan_rollout_grad",
            "plan_select", "plan_sample_controls", "plan_rollout_sampled", "plan_select_sampled",
+           "plan_rollout_argmin", "plan_rollout_sampled_argmin",
            "plan_set_launch", "plan_get_launch", "plan_enable_timing", "plan_last_rollout_ms",
            "plan_destroy", "plan_last_error")
 
@@ -86,6 +87,9 @@ def lib():
         L.plan_sample_controls.argtypes = [vp, sp, C.c_int, C.c_int, vp]
         L.plan_rollout_sampled.argtypes = [vp, fp, sp, C.c_int, C.c_int, vp, vp]
         L.plan_select_sampled.argtypes = [vp, sp, vp, C.c_int, C.c_int, ip, fp, vp]
+        L.plan_rollout_argmin.argtypes = [vp, fp, vp, C.c_int, C.c_int, vp, vp, vp, ip, fp]
+        L.plan_rollout_sampled_argmin.argtypes = [vp, fp, sp, C.c_int, C.c_int, vp, vp, vp, ip,
+                                                  fp]
         L.plan_set_launch.argtypes = [vp, C.c_int, C.c_int]
         L.plan_get_launch.argtypes = [vp, ip, ip]
         L.plan_enable_timing.argtypes = [vp, C.c_int]
@@ -270,6 +274,41 @@ def plan_select_sampled(ctx, spec: Sample, cost, plan, want_result: bool = True)
     return (bk.value, bc.value) if want_result else None
 
 
+def plan_rollout_argmin(ctx, state0, controls, cost, plan, final_state=None,
+                        want_result: bool = True):
+    """Rollout and argmin in one launch; returns (best_k, best_cost) when
+    want_result (waits), else None."""
+    N, two, K = controls.shape
+    if two != 2:
+        raise ValueError("controls must be [N][2][K]")
+    s0 = (C.c_float * 13)(*[float(v) for v in state0])
+    bk, bc = C.c_int(0), C.c_float(0)
+    st = lib().plan_rollout_argmin(ctx, s0, _dptr(controls, "controls"), K, N,
+                                   _dptr(cost, "cost", K),
+                                   _dptr(final_state, "final_state", 13 * K),
+                                   _dptr(plan, "plan", 2 * N),
+                                   C.byref(bk) if want_result else None,
+                                   C.byref(bc) if want_result else None)
+    _check("plan_rollout_argmin", st, ctx)
+    return (bk.value, bc.value) if want_result else None
+
+
+def plan_rollout_sampled_argmin(ctx, state0, spec: Sample, N: int, cost, plan,
+                                final_state=None, want_result: bool = True):
+    """Sampled rollout and argmin in one launch."""
+    K = cost.numel()
+    s0 = (C.c_float * 13)(*[float(v) for v in state0])
+    bk, bc = C.c_int(0), C.c_float(0)
+    st = lib().plan_rollout_sampled_argmin(ctx, s0, C.byref(spec), K, int(N),
+                                           _dptr(cost, "cost", K),
+                                           _dptr(final_state, "final_state", 13 * K),
+                                           _dptr(plan, "plan", 2 * int(N)),
+                                           C.byref(bk) if want_result else None,
+                                           C.byref(bc) if want_result else None)
+    _check("plan_rollout_sampled_argmin", st, ctx)
+    return (bk.value, bc.value) if want_result else None
+
+
 def plan_set_launch(ctx, lanes: int = 0, block: int = 0):
     _check("plan_set_launch", lib().plan_set_launch(ctx, int(lanes), int(block)), ctx)
 
@@ -354,8 +393,23 @@ class Planner:
     def select_sampled(self, spec, cost, plan, want_result=True):
         return plan_select_sampled(self.ctx, spec, cost, plan, want_result)
 
+    def rollout_argmin(self, state0, controls, cost, plan, final_state=None, want_result=True):
+        return plan_rollout_argmin(self.ctx, state0, controls, cost, plan, final_state,
+                                   want_result)
+
+    def rollout_sampled_argmin(self, state0, spec, N, cost, plan, final_state=None,
+                               want_result=True):
+        return plan_rollout_sampled_argmin(self.ctx, state0, spec, N, cost, plan, final_state,
+                                           want_result)
+
     def set_launch(self, lanes=0, block=0):
         plan_set_launch(self.ctx, lanes, block)
+
+    def enable_timing(self, on=True):
+        plan_enable_timing(self.ctx, on)
+
+    def last_rollout_ms(self):
+        return plan_last_rollout_ms(self.ctx)
 
     def get_launch(self):
         return plan_get_launch(self.ctx)
