@@ -35,6 +35,12 @@ OPS_PER_STEP = 532
 # MI355X vector ALU issue: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz, one
 # non-packed FP32 operation per lane per clock.
 ALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
+# HBM bytes per launch of the fused rollout kernel on the single-plan
+# workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per dispatch) scaled
+# by what the same counters read for a 256 MiB device copy (fetch x2.0,
+# write x1.0); profiles/rollout_srb_c2_hbm_counters.md has the commands. Valid
+# for the kernel as profiled; None for other workloads.
+C2_TRAFFIC_BYTES = (3744.94 * 262144.0 / 131084.5 + 32.91) * 1024
 
 
 def workload(name):
@@ -181,6 +187,9 @@ def main():
                     help="seconds of oracle work for cpu_baseline (0 = skip)")
     ap.add_argument("--serving", type=int, default=1,
                     help="also replay the serving trace (plain vs continuous batching)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB and exit (the "
+                         "reference kernel for scaling the HBM byte counters)")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     args = ap.parse_args()
@@ -195,6 +204,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty(n, device="cuda")
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": 4 * n, "copies": 5}), flush=True)
+        return
     w, desc = workload(args.workload)
     T = w.terrain
     K, N, S = w.K, w.N, w.integ["substeps"]
@@ -288,7 +306,9 @@ def main():
         "rollout_kernel_ms": {"avg": k_avg_s * 1e3, "min": min(kern_ms), "max": max(kern_ms),
                               "kernel": "rollout_srb (fused argmin epilogue)"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_GOPS, "unit": "Gop/s",
-                     "frac": achieved / ALU_PEAK_GOPS, "traffic": None,
+                     "frac": achieved / ALU_PEAK_GOPS,
+                     "traffic": C2_TRAFFIC_BYTES if args.workload == "c2" else None,
+                     "traffic_unit": "bytes per launch (HBM, counter-derived)",
                      "ops_per_rollout_step": OPS_PER_STEP},
         "best": {"k": k_best, "J": j_best},
     }
