@@ -67,7 +67,10 @@ typedef struct {
  * A request's footprint is 16*W*H (texels) + 56*K (state, cost) + 8*K*N
  * (controls) + 8*N (plan) bytes; a request is admitted only while the summed
  * footprint of resident requests stays within budget_bytes.
- * chunk_intervals (>= 1) is how many control intervals one step advances.
+ * chunk_intervals (>= 1) is how many control intervals one step advances
+ * while requests are waiting (for a slot or for memory), so that waiting
+ * requests join after a short launch; when nothing waits, a step runs every
+ * resident request to the end of its horizon.
  * Errors: PLAN_EINVAL, PLAN_ENOMEM, PLAN_EDEVICE. */
 plan_status_t plan_server_create(plan_server **out, const plan_vehicle_t *veh, int max_slots,
                                  int max_K, int max_N, int max_W, int max_H,

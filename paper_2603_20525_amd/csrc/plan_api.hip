@@ -35,7 +35,7 @@ struct plan_ctx {
     int *bad_dev = nullptr;
     int *bad_host = nullptr;  // pinned
     // selection workspace
-    unsigned long long *part_keys = nullptr;
+    unsigned long long *part_keys = nullptr;  // argmin slot, all ones between launches
     unsigned int *counters = nullptr;  // tickets: [0] argmin, [1] softmin, [2] fused argmin
     unsigned long long *fused_key = nullptr;  // fused argmin slot, all ones between launches
     float *wpart = nullptr;
@@ -252,8 +252,8 @@ plan_status_t plan_create(plan_ctx **out, const plan_vehicle_t *veh, const plan_
     CREATE_TRY(hipMalloc(&c->tex, sizeof(float4) * (size_t)max_W * max_H));
     CREATE_TRY(hipMalloc(&c->bad_dev, sizeof(int)));
     CREATE_TRY(hipHostMalloc(&c->bad_host, sizeof(int), hipHostMallocDefault));
-    const int nb = plan::select_blocks(max_K);
-    CREATE_TRY(hipMalloc(&c->part_keys, sizeof(unsigned long long) * nb));
+    CREATE_TRY(hipMalloc(&c->part_keys, sizeof(unsigned long long)));
+    CREATE_TRY(hipMemset(c->part_keys, 0xFF, sizeof(unsigned long long)));
     CREATE_TRY(hipMalloc(&c->counters, sizeof(unsigned int) * 4));
     CREATE_TRY(hipMemset(c->counters, 0, sizeof(unsigned int) * 4));
     CREATE_TRY(hipMalloc(&c->fused_key, sizeof(unsigned long long)));

@@ -122,7 +122,8 @@ hipError_t launch_pack_terrain(const float *h, const float *c, int W, int H, flo
                                float4 *tex, int *bad, hipStream_t s);
 
 hipError_t launch_select_slots(const RolloutArgs *slots, float *const *plans, const int *bad,
-                               SelectOut *out, const SlotList &l, hipStream_t s);
+                               SelectOut *out, SelectOut *out_host, const SlotList &l,
+                               hipStream_t s);
 
 // Selection workspace sizes for a given maximum K / N.
 int select_blocks(int K);

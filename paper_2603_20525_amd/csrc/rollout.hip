@@ -134,16 +134,12 @@ __device__ __forceinline__ void argmin_epilogue(const RolloutArgs &a, unsigned l
         unsigned long long b = red[0];
 #pragma unroll
         for (int q = 1; q < BLOCK / 64; ++q) b = red[q] < b ? red[q] : b;
-        if (b != ~0ull) atomicMin(a.sel_key, b);
-        __threadfence();
-        const unsigned int t = atomicAdd(a.sel_ticket, 1u);
-        last_sh = (t == gridDim.x - 1);
+        last_sh = fold_key_and_take_ticket(a.sel_key, a.sel_ticket, b, gridDim.x);
     }
     __syncthreads();
     if (!last_sh) return;
-    __threadfence();
     if (tid == 0) {
-        const unsigned long long m = __atomic_load_n(a.sel_key, __ATOMIC_RELAXED);
+        const unsigned long long m = take_key_and_reset(a.sel_key, a.sel_ticket);
         red[0] = m;
         SelectOut o;
         o.best_k = (m == ~0ull) ? -1 : (int)(unsigned int)(m & 0xffffffffu);
@@ -151,8 +147,6 @@ __device__ __forceinline__ void argmin_epilogue(const RolloutArgs &a, unsigned l
         o.pad[0] = o.pad[1] = 0;
         *a.sel_out = o;
         if (a.sel_out_host) *a.sel_out_host = o;
-        *a.sel_key = ~0ull;
-        *a.sel_ticket = 0u;
     }
     __syncthreads();
     const unsigned long long m = red[0];

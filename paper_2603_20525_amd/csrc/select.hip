@@ -62,8 +62,9 @@ __device__ __forceinline__ float load_partial(const float *p) {
     return __uint_as_float(__atomic_load_n((const unsigned int *)p, __ATOMIC_RELAXED));
 }
 
-// One block per SEL_CHUNK candidates; the last block to finish reduces the
-// per-block keys, publishes (k*, J*) and, for argmin, gathers the plan: from
+// One block per SEL_CHUNK candidates; each folds its minimum key into the
+// slot part[0] (atomics only, see fold_key_and_take_ticket); the last block
+// to arrive publishes (k*, J*) and, for argmin, writes the plan: from
 // controls, or (SAMPLED) by regenerating candidate k*'s sequence.
 template <bool SAMPLED>
 __global__ __launch_bounds__(SEL_BLOCK) void select_argmin(
@@ -72,7 +73,6 @@ __global__ __launch_bounds__(SEL_BLOCK) void select_argmin(
     unsigned long long *__restrict__ part, unsigned int *__restrict__ ticket,
     SelectOut *__restrict__ out, SelectOut *out_host, const SampleArgs smp) {
     __shared__ unsigned long long red[SEL_BLOCK / 64];
-    __shared__ unsigned long long best_sh;
     __shared__ int last_sh;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int base = blockIdx.x * SEL_CHUNK;
@@ -91,27 +91,13 @@ __global__ __launch_bounds__(SEL_BLOCK) void select_argmin(
     if (tid == 0) {
         unsigned long long b = red[0];
         for (int q = 1; q < SEL_BLOCK / 64; ++q) b = red[q] < b ? red[q] : b;
-        part[blockIdx.x] = b;
-        __threadfence();
-        const unsigned int t = atomicAdd(ticket, 1u);
-        last_sh = (t == gridDim.x - 1);
+        last_sh = fold_key_and_take_ticket(part, ticket, b, gridDim.x);
     }
     __syncthreads();
     if (!last_sh) return;
-    __threadfence();
-    // last block: reduce the per-block keys
-    unsigned long long b = ~0ull;
-    for (int q = tid; q < (int)gridDim.x; q += SEL_BLOCK) {
-        const unsigned long long v = __atomic_load_n(&part[q], __ATOMIC_RELAXED);
-        b = v < b ? v : b;
-    }
-    b = wave_min(b);
-    if (lane == 0) red[wv] = b;
-    __syncthreads();
     if (tid == 0) {
-        unsigned long long m = red[0];
-        for (int q = 1; q < SEL_BLOCK / 64; ++q) m = red[q] < m ? red[q] : m;
-        best_sh = m;
+        const unsigned long long m = take_key_and_reset(part, ticket);
+        red[0] = m;
         SelectOut o;
         if (m == ~0ull) {
             o.best_k = -1;
@@ -123,11 +109,10 @@ __global__ __launch_bounds__(SEL_BLOCK) void select_argmin(
         o.pad[0] = o.pad[1] = 0;
         *out = o;
         if (out_host) *out_host = o;  // pinned host copy: no readback copy needed
-        *ticket = 0u;  // ready for the next call
     }
     __syncthreads();
     if (gather) {
-        const unsigned long long m = best_sh;
+        const unsigned long long m = red[0];
         const int kb = (m == ~0ull) ? -1 : (int)(unsigned int)(m & 0xffffffffu);
         write_plan<SAMPLED>(kb, N, K, controls, smp, drate_max, plan, tid, SEL_BLOCK);
     }
@@ -215,7 +200,8 @@ constexpr int SLOT_SEL_BLOCK = 1024;
 
 __global__ __launch_bounds__(SLOT_SEL_BLOCK) void select_slots(
     const RolloutArgs *__restrict__ slots, float *const *__restrict__ plans,
-    const int *__restrict__ bad, SelectOut *__restrict__ out, const SlotList l) {
+    const int *__restrict__ bad, SelectOut *__restrict__ out, SelectOut *out_host,
+    const SlotList l) {
     __shared__ unsigned long long red[SLOT_SEL_BLOCK / 64];
     __shared__ unsigned long long best_sh;
     const int s = l.slot[blockIdx.x];
@@ -240,6 +226,7 @@ __global__ __launch_bounds__(SLOT_SEL_BLOCK) void select_slots(
         o.pad[0] = bad[s] ? (uint32_t)(int32_t)PLAN_EINVAL : 0u;
         o.pad[1] = 0;
         out[s] = o;
+        out_host[s] = o;  // pinned ring entry the host polls
     }
     __syncthreads();
     const unsigned long long m = best_sh;
@@ -252,10 +239,11 @@ __global__ __launch_bounds__(SLOT_SEL_BLOCK) void select_slots(
 }  // namespace
 
 hipError_t launch_select_slots(const RolloutArgs *slots, float *const *plans, const int *bad,
-                               SelectOut *out, const SlotList &l, hipStream_t s) {
+                               SelectOut *out, SelectOut *out_host, const SlotList &l,
+                               hipStream_t s) {
     if (l.count < 1) return hipSuccess;
     hipLaunchKernelGGL(select_slots, dim3(l.count), dim3(SLOT_SEL_BLOCK), 0, s, slots, plans, bad,
-                       out, l);
+                       out, out_host, l);
     return hipGetLastError();
 }
 

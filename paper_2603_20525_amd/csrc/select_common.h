@@ -44,6 +44,35 @@ __device__ __forceinline__ float clamp_ctrl(float u, int row, float drate_max) {
     return u < -lim ? -lim : (u > lim ? lim : u);
 }
 
+// Cross-workgroup argmin without memory fences. Each workgroup folds its
+// minimum key into *slot with an atomic minimum and then takes a ticket; the
+// ticket increment is made data-dependent on the minimum's returned value, so
+// it is issued only after the minimum has been performed. The workgroup that
+// draws the last ticket reads the slot with an atomic (every other
+// workgroup's minimum was performed before its ticket) and resets slot and
+// ticket for the next launch. Only atomics cross workgroups, so no cache
+// writeback or invalidation is needed (a fence would write back and
+// invalidate the whole L2 of each XCD). Called by one thread per workgroup;
+// returns whether this workgroup is the last.
+__device__ __forceinline__ bool fold_key_and_take_ticket(unsigned long long *slot,
+                                                         unsigned int *ticket,
+                                                         unsigned long long key,
+                                                         unsigned int nblocks) {
+    // keys are never 0 (that would be a NaN cost), so the increment is 1
+    const unsigned long long old = atomicMin(slot, key);
+    const unsigned int t = atomicAdd(ticket, old == 0ull ? 2u : 1u);
+    return t == nblocks - 1;
+}
+
+// The last workgroup's read of the folded key, with the reset for the next
+// launch (slot all ones, ticket zero).
+__device__ __forceinline__ unsigned long long take_key_and_reset(unsigned long long *slot,
+                                                                 unsigned int *ticket) {
+    const unsigned long long m = atomicExch(slot, ~0ull);
+    atomicExch(ticket, 0u);
+    return m;
+}
+
 // Plan output [N][2] for the selected candidate kb (zeros if kb < 0): its
 // clamped controls, read from controls [N][2][K] or, SAMPLED, regenerated
 // from the generator. Threads tid, tid + nthreads, ... share the work.

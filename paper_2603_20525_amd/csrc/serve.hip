@@ -236,7 +236,10 @@ static plan_status_t launch_step(plan_server *s) {
         e.slot = i;
         e.block_start = blocks;
         e.n0 = sl.progress;
-        e.n1 = sl.progress + s->chunk < r.N ? sl.progress + s->chunk : r.N;
+        // a slice of `chunk` intervals while requests wait for a slot or for
+        // memory; with nothing waiting, run to the horizon's end in this launch
+        const int slice = s->queue.empty() ? r.N : s->chunk;
+        e.n1 = sl.progress + slice < r.N ? sl.progress + slice : r.N;
         e.finalize = e.n1 == r.N;
         blocks += (int)(((long long)r.K * lanes + block - 1) / block);
         if (e.finalize) {
@@ -249,9 +252,8 @@ static plan_status_t launch_step(plan_server *s) {
     st.ring = s->ring_next;
     s->ring_next = (s->ring_next + 1) % RING;
     if (fin.count) {
-        SHIP(s, plan::launch_select_slots(s->slot_args, s->plans, s->bad, s->sel, fin, s->stream));
-        SHIP(s, hipMemcpyAsync(s->ring_host[st.ring], s->sel, sizeof(SelectOut) * s->max_slots,
-                               hipMemcpyDeviceToHost, s->stream));
+        SHIP(s, plan::launch_select_slots(s->slot_args, s->plans, s->bad, s->sel,
+                                          s->ring_host[st.ring], fin, s->stream));
     }
     if (s->ev_pool.empty()) {
         hipEvent_t e;
