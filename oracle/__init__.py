@@ -122,6 +122,9 @@ def lib():
         L.oracle_set_round32.restype = None
         L.oracle_est_rhs.argtypes = [vp, dp, C.c_double, C.c_double, dp, C.POINTER(EstDiag)]
         L.oracle_est_rollout.argtypes = [vp, fp, fp, C.c_int, C.c_int, dp, dp, ip]
+        L.oracle_smooth_terrain.argtypes = [fp, C.c_int, C.c_int, C.c_double, C.c_double, dp]
+        L.oracle_costmap_polygons.argtypes = [dp, ip, ip, C.c_int, C.c_int, C.c_int, C.c_double,
+                                              C.c_double, C.c_double, C.c_double, C.c_double, dp]
         u64p = C.POINTER(C.c_uint64)
         L.oracle_philox4x64.argtypes = [u64p, u64p, u64p]
         L.oracle_philox4x64.restype = None
@@ -153,6 +156,43 @@ def philox4x64(counter, key):
 
 
 SAMPLE_UNIFORM, SAMPLE_GAUSSIAN = 0, 1
+OBSTACLE, PATH_BOUNDARY = 0, 1
+
+
+def smooth_terrain(height, res, sigma):
+    """Gaussian level-of-detail smoothing of a float32 [H][W] heightmap (double out)."""
+    h = _f32(height)
+    H, W = h.shape
+    out = np.zeros((H, W))
+    rc = lib().oracle_smooth_terrain(_ptr(h, C.c_float), W, H, float(res), float(sigma),
+                                     _ptr(out, C.c_double))
+    if rc != 0:
+        raise ValueError("oracle_smooth_terrain rejected the arguments")
+    return out
+
+
+def polygon_arrays(polygons):
+    """[(kind, [(x, y), ...]), ...] -> (verts [V][2] double, offsets [P+1], kinds [P])."""
+    verts = np.ascontiguousarray(np.concatenate([np.asarray(v, np.float64).reshape(-1, 2)
+                                                 for _, v in polygons]) if polygons
+                                 else np.zeros((0, 2)))
+    offsets = np.zeros(len(polygons) + 1, np.int32)
+    offsets[1:] = np.cumsum([len(v) for _, v in polygons])
+    kinds = np.asarray([k for k, _ in polygons], np.int32)
+    return verts, offsets, kinds
+
+
+def costmap_polygons(polygons, W, H, x0, y0, res, sigma, eps_dist):
+    """Distance-constraint cost rate at every node (double [H][W])."""
+    verts, offsets, kinds = polygon_arrays(polygons)
+    out = np.zeros((H, W))
+    rc = lib().oracle_costmap_polygons(_ptr(verts, C.c_double), _ptr(offsets, C.c_int),
+                                       _ptr(kinds, C.c_int), len(polygons), int(W), int(H),
+                                       float(x0), float(y0), float(res), float(sigma),
+                                       float(eps_dist), _ptr(out, C.c_double))
+    if rc != 0:
+        raise ValueError("oracle_costmap_polygons rejected the arguments")
+    return out
 
 
 def sample_controls(kind, seed, stream, scale, K, N, nominal=None, keep_nominal=False):

@@ -179,6 +179,29 @@ int oracle_est_rhs(const oracle_ctx *o, const double xi[7], double delta_dot, do
 int oracle_est_rollout(const oracle_ctx *o, const float state0[7], const float *controls,
                        int K, int N, double *cost, double *final_state, int *exit_step);
 
+/* ---- terrain preparation (off the per-plan path) -------------------------
+ * Level-of-detail smoothing (section "Terrain Smoothing"): the heightmap
+ * convolved with a 2-D Gaussian of standard deviation sigma (m), weights
+ * exp(-(di^2 + dj^2) res^2 / (2 sigma^2)) over the square of half-width
+ * r = ceil(3 sigma / res) nodes, normalised to sum 1; nodes outside the grid
+ * take the value of the nearest edge node (clamp-to-edge). out is [H][W].
+ * Returns 0, or -1 on invalid arguments. */
+int oracle_smooth_terrain(const float *height, int W, int H, double res, double sigma,
+                          double *out);
+
+/* Costmap of the distance constraints (sections "OCP Formulation" and
+ * "Real-Time Implementation"): at every node, the sum over perimeters p of
+ * sigma * max(0, 1 + pi_p / eps_dist)^2 with pi_p = -sdist_p, sdist_p the
+ * signed 2-D distance from the node to perimeter p: for an obstacle
+ * (kind 0) negative inside and positive outside, for a path boundary
+ * (kind 1) the reverse. Polygon p has vertices verts[offsets[p]] ..
+ * verts[offsets[p+1]-1] (x, y pairs, implicitly closed); inside is the
+ * even-odd rule. out is [H][W], node (i, j) at (x0 + i res, y0 + j res).
+ * Returns 0, or -1 on invalid arguments. */
+int oracle_costmap_polygons(const double *verts, const int *offsets, const int *kinds, int P,
+                            int W, int H, double x0, double y0, double res, double sigma,
+                            double eps_dist, double *out);
+
 /* Philox4x64-10 (Salmon et al., SC 2011): out = bijection of the 256-bit
  * counter under the 128-bit key. */
 void oracle_philox4x64(const unsigned long long ctr[4], const unsigned long long key[2],

@@ -765,6 +765,96 @@ int oracle_est_rollout(const oracle_ctx *o, const float state0[7], const float *
     return 0;
 }
 
+/* ------------------------------------------------- terrain preparation ---- */
+
+int oracle_smooth_terrain(const float *height, int W, int H, double res, double sigma,
+                          double *out)
+{
+    if (!height || !out || W < 1 || H < 1 || !(res > 0) || !(sigma > 0)) return -1;
+    const int r = (int)ceil(3.0 * sigma / res);
+    /* unnormalised 2-D weights and their sum */
+    const int n = 2 * r + 1;
+    double *wt = (double *)malloc(sizeof(double) * (size_t)n * n);
+    if (!wt) return -1;
+    double total = 0.0;
+    for (int dj = -r; dj <= r; ++dj)
+        for (int di = -r; di <= r; ++di) {
+            double d2 = ((double)di * di + (double)dj * dj) * res * res;
+            double w = exp(-d2 / (2.0 * sigma * sigma));
+            wt[(size_t)(dj + r) * n + (di + r)] = w;
+            total += w;
+        }
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < H; ++j) {
+        for (int i = 0; i < W; ++i) {
+            double acc = 0.0;
+            for (int dj = -r; dj <= r; ++dj) {
+                int jj = j + dj;
+                if (jj < 0) jj = 0;
+                if (jj > H - 1) jj = H - 1;
+                for (int di = -r; di <= r; ++di) {
+                    int ii = i + di;
+                    if (ii < 0) ii = 0;
+                    if (ii > W - 1) ii = W - 1;
+                    acc += wt[(size_t)(dj + r) * n + (di + r)] * (double)height[(size_t)jj * W + ii];
+                }
+            }
+            out[(size_t)j * W + i] = acc / total;
+        }
+    }
+    free(wt);
+    return 0;
+}
+
+/* Distance from (px, py) to the segment a-b. */
+static double segment_distance(double px, double py, double ax, double ay, double bx, double by)
+{
+    double ex = bx - ax, ey = by - ay;
+    double len2 = ex * ex + ey * ey;
+    double t = 0.0;
+    if (len2 > 0.0) t = clampd(((px - ax) * ex + (py - ay) * ey) / len2, 0.0, 1.0);
+    double qx = ax + t * ex - px, qy = ay + t * ey - py;
+    return sqrt(qx * qx + qy * qy);
+}
+
+int oracle_costmap_polygons(const double *verts, const int *offsets, const int *kinds, int P,
+                            int W, int H, double x0, double y0, double res, double sigma,
+                            double eps_dist, double *out)
+{
+    if (!out || W < 1 || H < 1 || !(res > 0) || !(eps_dist > 0) || P < 0) return -1;
+    if (P > 0 && (!verts || !offsets || !kinds)) return -1;
+    for (int p = 0; p < P; ++p)
+        if (offsets[p + 1] - offsets[p] < 3 || (kinds[p] != 0 && kinds[p] != 1)) return -1;
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < H; ++j) {
+        for (int i = 0; i < W; ++i) {
+            double px = x0 + i * res, py = y0 + j * res;
+            double c = 0.0;
+            for (int p = 0; p < P; ++p) {
+                int a = offsets[p], b = offsets[p + 1], m = b - a;
+                double dmin = INFINITY;
+                int inside = 0;
+                for (int e = 0; e < m; ++e) {
+                    const double *v0 = verts + 2 * (size_t)(a + e);
+                    const double *v1 = verts + 2 * (size_t)(a + (e + 1) % m);
+                    double d = segment_distance(px, py, v0[0], v0[1], v1[0], v1[1]);
+                    if (d < dmin) dmin = d;
+                    /* even-odd rule: count edges crossing the ray to +x */
+                    if ((v0[1] > py) != (v1[1] > py)) {
+                        double xc = v0[0] + (py - v0[1]) * (v1[0] - v0[0]) / (v1[1] - v0[1]);
+                        if (px < xc) inside = !inside;
+                    }
+                }
+                /* obstacle: negative inside; path boundary: negative outside */
+                double sdist = (inside == (kinds[p] == 0)) ? -dmin : dmin;
+                c += oracle_soft(sigma, eps_dist, -sdist);
+            }
+            out[(size_t)j * W + i] = c;
+        }
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------ sampling ---- */
 /* The paper draws the candidate controls on the GPU with a counter-based
  * generator ("Real-Time Implementation": the random samples are produced with
