@@ -122,6 +122,37 @@ plan_status_t plan_set_terrain(plan_ctx *ctx, const float *height_dev, int W, in
                                float x0, float y0, float res,
                                const float *costmap_dev);
 
+/* Terrain level-of-detail smoothing (section "Terrain Smoothing": the
+ * models need terrain smooth at their own length scale; the paper smooths
+ * with a Gaussian of standard deviation 0.3 m for the SRB model and 1.5 m for
+ * the extended single-track model). out_dev [H][W] receives height_dev
+ * [H][W] convolved with the Gaussian exp(-d^2 / (2 sigma^2)) over the square
+ * of half-width r = ceil(3 sigma / res - 1e-6) nodes, normalised to sum 1, nodes
+ * beyond the grid taking the nearest edge value. out_dev may equal
+ * height_dev. Asynchronous. Errors: PLAN_EINVAL (NULL pointers, W or H
+ * outside [1, max], res or sigma not finite and > 0, r > 127); PLAN_EDEVICE. */
+plan_status_t plan_smooth_terrain(plan_ctx *ctx, const float *height_dev, int W, int H,
+                                  float res, float sigma, float *out_dev);
+
+/* Costmap of the distance constraints (section "OCP Formulation": signed
+ * distances between each wheel and each obstacle or path-boundary
+ * perimeter; section "Real-Time Implementation": pre-computed and summed for
+ * all features into a costmap interpolated at run time). costmap_dev [H][W]
+ * (node (i, j) at (x0 + i res, y0 + j res)) receives, or with accumulate != 0
+ * has added to it, sum_p sigma * max(0, 1 - sdist_p / eps_dist)^2, where
+ * sdist_p is the signed distance from the node to polygon p: negative inside
+ * an obstacle (kind 0), negative outside a path boundary (kind 1); inside is
+ * the even-odd rule. Polygon p is vertices offsets[p] .. offsets[p+1]-1 of
+ * verts_dev ([V][2] FP32 x, y on the device), implicitly closed.
+ * offsets ([P+1], offsets[0] = 0, offsets[P] = V, at least 3 vertices each)
+ * and kinds ([P]) are host arrays; P <= 64 per call (accumulate for more).
+ * Errors: PLAN_EINVAL (NULL pointers, bad offsets or kinds, P outside
+ * [0, 64], W or H < 1, res or eps_dist <= 0, sigma < 0); PLAN_EDEVICE. */
+plan_status_t plan_costmap_polygons(plan_ctx *ctx, const float *verts_dev, int V,
+                                    const int *offsets, const int *kinds, int P, int W, int H,
+                                    float x0, float y0, float res, float sigma,
+                                    float eps_dist, int accumulate, float *costmap_dev);
+
 /* Roll out K candidates for N zero-order-hold intervals of `substeps` Euler
  * steps each and write their costs (eq. framework:cost, horizon ended early
  * at the goal per eq. formulation:goal).

@@ -183,7 +183,7 @@ int oracle_est_rollout(const oracle_ctx *o, const float state0[7], const float *
  * Level-of-detail smoothing (section "Terrain Smoothing"): the heightmap
  * convolved with a 2-D Gaussian of standard deviation sigma (m), weights
  * exp(-(di^2 + dj^2) res^2 / (2 sigma^2)) over the square of half-width
- * r = ceil(3 sigma / res) nodes, normalised to sum 1; nodes outside the grid
+ * r = ceil(3 sigma / res - 1e-6) nodes, normalised to sum 1; nodes outside the grid
  * take the value of the nearest edge node (clamp-to-edge). out is [H][W].
  * Returns 0, or -1 on invalid arguments. */
 int oracle_smooth_terrain(const float *height, int W, int H, double res, double sigma,

@@ -771,7 +771,9 @@ int oracle_smooth_terrain(const float *height, int W, int H, double res, double 
                           double *out)
 {
     if (!height || !out || W < 1 || H < 1 || !(res > 0) || !(sigma > 0)) return -1;
-    const int r = (int)ceil(3.0 * sigma / res);
+    /* truncation at 3 sigma; the 1e-6 node slack keeps decimal inputs such as
+     * sigma = 0.3 m at 0.1 m on 9 nodes whatever precision they arrive in */
+    const int r = (int)ceil(3.0 * sigma / res - 1e-6);
     /* unnormalised 2-D weights and their sum */
     const int n = 2 * r + 1;
     double *wt = (double *)malloc(sizeof(double) * (size_t)n * n);

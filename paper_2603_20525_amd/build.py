@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libplan.so")
-SOURCES = ["rollout.hip", "est.hip", "select.hip", "plan_api.hip", "serve.hip", "adjoint.hip"]
+SOURCES = ["rollout.hip", "est.hip", "select.hip", "plan_api.hip", "serve.hip", "adjoint.hip", "terrain_prep.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

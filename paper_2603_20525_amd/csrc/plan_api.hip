@@ -44,6 +44,8 @@ struct plan_ctx {
     // launch shape
     int lanes_opt = 0, block_opt = 0;
     int last_lanes = 0, last_block = 0;
+    // terrain preparation: intermediate grid of the separable smoothing
+    float *smooth_tmp = nullptr;
     // adjoint workspace (grown on demand): state, checkpoints, segment scratch
     float *gws = nullptr;
     size_t gws_floats = 0;
@@ -93,6 +95,7 @@ static void release(plan_ctx *c) {
     (void)hipFree(c->wpart);
     (void)hipFree(c->sel_dev);
     (void)hipFree(c->gws);
+    (void)hipFree(c->smooth_tmp);
     if (c->sel_host) (void)hipHostFree(c->sel_host);
     if (c->bad_host) (void)hipHostFree(c->bad_host);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -250,6 +253,7 @@ plan_status_t plan_create(plan_ctx **out, const plan_vehicle_t *veh, const plan_
     } while (0)
     CREATE_TRY(hipGetDevice(&c->device));
     CREATE_TRY(hipMalloc(&c->tex, sizeof(float4) * (size_t)max_W * max_H));
+    CREATE_TRY(hipMalloc(&c->smooth_tmp, sizeof(float) * (size_t)max_W * max_H));
     CREATE_TRY(hipMalloc(&c->bad_dev, sizeof(int)));
     CREATE_TRY(hipHostMalloc(&c->bad_host, sizeof(int), hipHostMallocDefault));
     CREATE_TRY(hipMalloc(&c->part_keys, sizeof(unsigned long long)));
@@ -537,6 +541,69 @@ plan_status_t plan_rollout_sampled_argmin(plan_ctx *c, const float state0[13],
     a.cost = cost_dev;
     a.final_state = final_state_dev;
     return fused_launch(c, a, true, plan_dev, best_k, best_cost);
+}
+
+plan_status_t plan_smooth_terrain(plan_ctx *c, const float *height_dev, int W, int H, float res,
+                                  float sigma, float *out_dev) {
+    if (!c) return PLAN_EINVAL;
+    if (!height_dev || !out_dev) return fail(c, PLAN_EINVAL, "NULL argument");
+    if (W < 1 || H < 1 || W > c->max_W || H > c->max_H)
+        return fail(c, PLAN_EINVAL, "terrain size outside [1, max] in W or H");
+    if (!(res > 0) || !isfinite(res) || !(sigma > 0) || !isfinite(sigma))
+        return fail(c, PLAN_EINVAL, "res and sigma must be finite and > 0");
+    // 3-sigma truncation; the 1e-6 node slack keeps decimal inputs such as
+    // 0.3 m at 0.1 m on 9 nodes although they arrive rounded to float
+    const double rr = ceil(3.0 * (double)sigma / (double)res - 1e-6);
+    if (rr > plan::MAX_SMOOTH_RADIUS)
+        return fail(c, PLAN_EINVAL, "sigma / res too large (3 sigma / res > 127 nodes)");
+    plan::SmoothTaps taps;
+    memset(&taps, 0, sizeof taps);
+    taps.r = (int)rr;
+    double g[2 * plan::MAX_SMOOTH_RADIUS + 1], sum = 0.0;
+    for (int k = -taps.r; k <= taps.r; ++k) {
+        const double d = k * (double)res;
+        g[k + taps.r] = exp(-d * d / (2.0 * (double)sigma * sigma));
+        sum += g[k + taps.r];
+    }
+    for (int k = 0; k <= 2 * taps.r; ++k) taps.w[k] = (float)(g[k] / sum);
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, plan::launch_smooth(height_dev, W, H, taps, c->smooth_tmp, out_dev, c->stream));
+    return PLAN_OK;
+}
+
+plan_status_t plan_costmap_polygons(plan_ctx *c, const float *verts_dev, int V, const int *offsets,
+                                    const int *kinds, int P, int W, int H, float x0, float y0,
+                                    float res, float sigma, float eps_dist, int accumulate,
+                                    float *costmap_dev) {
+    if (!c) return PLAN_EINVAL;
+    if (!costmap_dev) return fail(c, PLAN_EINVAL, "costmap is NULL");
+    if (P < 0 || P > plan::MAX_POLYGONS) return fail(c, PLAN_EINVAL, "P outside [0, 64]");
+    if (P > 0 && (!verts_dev || !offsets || !kinds))
+        return fail(c, PLAN_EINVAL, "NULL polygon array");
+    if (W < 1 || H < 1) return fail(c, PLAN_EINVAL, "W and H must be >= 1");
+    if (!(res > 0) || !isfinite(res) || !isfinite(x0) || !isfinite(y0) || !(eps_dist > 0) ||
+        !isfinite(eps_dist) || !(sigma >= 0) || !isfinite(sigma))
+        return fail(c, PLAN_EINVAL, "grid or cost parameters invalid");
+    plan::PolygonSet ps;
+    memset(&ps, 0, sizeof ps);
+    ps.count = P;
+    if (P > 0) {
+        if (offsets[0] != 0) return fail(c, PLAN_EINVAL, "offsets[0] must be 0");
+        for (int p = 0; p < P; ++p) {
+            if (offsets[p + 1] - offsets[p] < 3)
+                return fail(c, PLAN_EINVAL, "a polygon needs at least 3 vertices");
+            if (kinds[p] != 0 && kinds[p] != 1)
+                return fail(c, PLAN_EINVAL, "polygon kind must be 0 (obstacle) or 1 (boundary)");
+            ps.offsets[p] = offsets[p];
+            ps.kinds[p] = kinds[p];
+        }
+        if (offsets[P] != V) return fail(c, PLAN_EINVAL, "offsets[P] must equal V");
+        ps.offsets[P] = offsets[P];
+    }
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, plan::launch_costmap_polygons(verts_dev, ps, W, H, x0, y0, res, sigma, eps_dist,
+                                             accumulate != 0, costmap_dev, c->stream));
+    return PLAN_OK;
 }
 
 plan_status_t plan_init_state(plan_ctx *c, const float state0[13], float *state_dev,

@@ -125,6 +125,33 @@ hipError_t launch_select_slots(const RolloutArgs *slots, float *const *plans, co
                                SelectOut *out, SelectOut *out_host, const SlotList &l,
                                hipStream_t s);
 
+// Terrain preparation. Gaussian taps w[0 .. 2r] (normalised, FP32) of the
+// separable level-of-detail kernel; r <= MAX_SMOOTH_RADIUS.
+constexpr int MAX_SMOOTH_RADIUS = 127;
+
+struct SmoothTaps {
+    int r;
+    float w[2 * MAX_SMOOTH_RADIUS + 1];
+};
+
+// Polygons of one costmap call: vertices offsets[p] .. offsets[p+1]-1 of the
+// vertex array, kind 0 obstacle / 1 path boundary.
+constexpr int MAX_POLYGONS = 64;
+
+struct PolygonSet {
+    int count;
+    int offsets[MAX_POLYGONS + 1];
+    int kinds[MAX_POLYGONS];
+};
+
+// Row pass into tmp, column pass into out (both [H][W]).
+hipError_t launch_smooth(const float *h, int W, int H, const SmoothTaps &taps, float *tmp,
+                         float *out, hipStream_t s);
+
+hipError_t launch_costmap_polygons(const float *verts, const PolygonSet &ps, int W, int H,
+                                   float x0, float y0, float res, float sigma, float eps,
+                                   int accumulate, float *cm, hipStream_t s);
+
 // Selection workspace sizes for a given maximum K / N.
 int select_blocks(int K);
 int softmin_chunks(int K);

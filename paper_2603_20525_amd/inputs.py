@@ -199,24 +199,29 @@ def side_slope_terrain(seed: int, n: int = 2048, res: float = 0.05,
     return Terrain(h.astype(np.float32), 0.0, 0.0, res)
 
 
-def disk_costmap(terrain: Terrain, seed: int, count: int = 6, radius=(0.8, 2.0),
-                 sigma: float = 1.0e6, eps: float = 0.25) -> np.ndarray:
-    """Cost-rate grid for ``count`` circular obstacles: at each node the sum
-    over obstacles of sigma*max(0, 1 - sdist/eps)^2 (signed distance, negative
-    inside). Test input only; the obstacles are synthetic disks."""
+def obstacle_polygons(terrain: Terrain, seed: int, count: int = 6, radius=(0.8, 2.0),
+                      sides: int = 12, boundary: bool = False) -> list:
+    """Seeded obstacle perimeters: ``count`` regular polygons (kind 0) with
+    circumradius in ``radius`` placed over the map, plus, with ``boundary``,
+    a path-boundary rectangle (kind 1) 1 m inside the map edge. Geometry only:
+    each side turns it into a costmap with its own code."""
     rng = np.random.default_rng(seed)
-    X, Y = terrain.node_xy()
     ext_x = terrain.W * terrain.res
     ext_y = terrain.H * terrain.res
-    c = np.zeros(X.shape)
+    polys = []
     for _ in range(count):
-        cx = rng.uniform(0.2 * ext_x, 0.9 * ext_x)
-        cy = rng.uniform(0.2 * ext_y, 0.8 * ext_y)
+        cx = terrain.x0 + rng.uniform(0.2 * ext_x, 0.9 * ext_x)
+        cy = terrain.y0 + rng.uniform(0.2 * ext_y, 0.8 * ext_y)
         r = rng.uniform(*radius)
-        sd = np.hypot(X - cx, Y - cy) - r
-        m = np.maximum(0.0, 1.0 - sd / eps)
-        c += sigma * m * m
-    return c.astype(np.float32)
+        ph = rng.uniform(0.0, 2.0 * math.pi)
+        t = ph + 2.0 * math.pi * np.arange(sides) / sides
+        polys.append((0, [(cx + r * math.cos(a), cy + r * math.sin(a)) for a in t]))
+    if boundary:
+        x0, y0 = terrain.x0 + 1.0, terrain.y0 + 1.0
+        x1 = terrain.x0 + (terrain.W - 1) * terrain.res - 1.0
+        y1 = terrain.y0 + (terrain.H - 1) * terrain.res - 1.0
+        polys.append((1, [(x0, y0), (x1, y0), (x1, y1), (x0, y1)]))
+    return polys
 
 
 # -------------------------------------------------------------- initial state

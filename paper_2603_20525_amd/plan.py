@@ -55,6 +55,7 @@ EXPORTS = ("plan_create", "plan_set_stream", "plan_set_cost", "plan_set_terrain"
            "plan_rollout", "plan_rollout_est", "plan_rollout_chunk", "plan_init_state", "plan_rollout_grad",
            "plan_select", "plan_sample_controls", "plan_rollout_sampled", "plan_select_sampled",
            "plan_rollout_argmin", "plan_rollout_sampled_argmin",
+           "plan_smooth_terrain", "plan_costmap_polygons",
            "plan_set_launch", "plan_get_launch", "plan_enable_timing", "plan_last_rollout_ms",
            "plan_destroy", "plan_last_error")
 
@@ -90,6 +91,10 @@ def lib():
         L.plan_rollout_argmin.argtypes = [vp, fp, vp, C.c_int, C.c_int, vp, vp, vp, ip, fp]
         L.plan_rollout_sampled_argmin.argtypes = [vp, fp, sp, C.c_int, C.c_int, vp, vp, vp, ip,
                                                   fp]
+        L.plan_smooth_terrain.argtypes = [vp, vp, C.c_int, C.c_int, C.c_float, C.c_float, vp]
+        L.plan_costmap_polygons.argtypes = [vp, vp, C.c_int, ip, ip, C.c_int, C.c_int, C.c_int,
+                                            C.c_float, C.c_float, C.c_float, C.c_float,
+                                            C.c_float, C.c_int, vp]
         L.plan_set_launch.argtypes = [vp, C.c_int, C.c_int]
         L.plan_get_launch.argtypes = [vp, ip, ip]
         L.plan_enable_timing.argtypes = [vp, C.c_int]
@@ -309,6 +314,30 @@ def plan_rollout_sampled_argmin(ctx, state0, spec: Sample, N: int, cost, plan,
     return (bk.value, bc.value) if want_result else None
 
 
+def plan_smooth_terrain(ctx, height, res: float, sigma: float, out):
+    """Gaussian level-of-detail smoothing of height [H][W] into out [H][W] (GPU)."""
+    H, W = height.shape
+    st = lib().plan_smooth_terrain(ctx, _dptr(height, "height"), W, H, float(res), float(sigma),
+                                   _dptr(out, "out", H * W))
+    _check("plan_smooth_terrain", st, ctx)
+
+
+def plan_costmap_polygons(ctx, verts, offsets, kinds, costmap, x0: float, y0: float,
+                          res: float, sigma: float, eps_dist: float, accumulate=False):
+    """Distance-constraint costmap [H][W] (GPU) from polygons: verts [V][2]
+    (GPU float32), offsets [P+1] and kinds [P] (host int sequences)."""
+    H, W = costmap.shape
+    P = len(kinds)
+    off = (C.c_int * (P + 1))(*[int(v) for v in offsets])
+    kd = (C.c_int * max(P, 1))(*[int(v) for v in kinds])
+    V = 0 if verts is None else verts.shape[0]
+    st = lib().plan_costmap_polygons(ctx, _dptr(verts, "verts") if V else None, V, off, kd, P,
+                                     W, H, float(x0), float(y0), float(res), float(sigma),
+                                     float(eps_dist), int(bool(accumulate)),
+                                     _dptr(costmap, "costmap", H * W))
+    _check("plan_costmap_polygons", st, ctx)
+
+
 def plan_set_launch(ctx, lanes: int = 0, block: int = 0):
     _check("plan_set_launch", lib().plan_set_launch(ctx, int(lanes), int(block)), ctx)
 
@@ -401,6 +430,14 @@ class Planner:
                                want_result=True):
         return plan_rollout_sampled_argmin(self.ctx, state0, spec, N, cost, plan, final_state,
                                            want_result)
+
+    def smooth_terrain(self, height, res, sigma, out):
+        plan_smooth_terrain(self.ctx, height, res, sigma, out)
+
+    def costmap_polygons(self, verts, offsets, kinds, costmap, x0, y0, res, sigma, eps_dist,
+                         accumulate=False):
+        plan_costmap_polygons(self.ctx, verts, offsets, kinds, costmap, x0, y0, res, sigma,
+                              eps_dist, accumulate)
 
     def set_launch(self, lanes=0, block=0):
         plan_set_launch(self.ctx, lanes, block)

@@ -86,7 +86,9 @@ def test_est_c2_full_size():
 
 def test_est_costmap_parity():
     w = inputs.c1(K=512)
-    cm = inputs.disk_costmap(w.terrain, seed=77, count=8)
+    T = w.terrain
+    cm = oracle.costmap_polygons(inputs.obstacle_polygons(T, seed=77, count=8), T.W, T.H, T.x0,
+                                 T.y0, T.res, 1.0e6, 0.25).astype(np.float32)
     EstCase(w, costmap=cm).check("est c1 costmap")
 
 

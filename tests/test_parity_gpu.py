@@ -197,7 +197,9 @@ def test_paper_step_map_at_5ms():
 
 def test_costmap_obstacles_parity():
     w = inputs.c1(K=512)
-    cm = inputs.disk_costmap(w.terrain, seed=77, count=8)
+    T = w.terrain
+    cm = oracle.costmap_polygons(inputs.obstacle_polygons(T, seed=77, count=8), T.W, T.H, T.x0,
+                                 T.y0, T.res, 1.0e6, 0.25).astype(np.float32)
     case = Case(w, costmap=cm)
     Jo, _, _ = case.oracle()
     assert (Jo > 1e3).sum() > 10  # obstacles are actually hit

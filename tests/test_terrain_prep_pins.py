@@ -14,7 +14,7 @@ import oracle
 
 def g1(res, sigma):
     """1-D weights of the truncated Gaussian (unnormalised) and offsets."""
-    r = math.ceil(3 * sigma / res)
+    r = math.ceil(3 * sigma / res - 1e-6)
     k = np.arange(-r, r + 1)
     return k, np.exp(-(k * res) ** 2 / (2 * sigma ** 2))
 
