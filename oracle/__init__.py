@@ -46,7 +46,7 @@ class Cost(C.Structure):
 
 class Integ(C.Structure):
     _fields_ = [("dt", C.c_double), ("substeps", C.c_int),
-                ("accel_max", C.c_double), ("vx_min", C.c_double)]
+                ("accel_max", C.c_double), ("vx_min", C.c_double), ("method", C.c_int)]
 
 
 class Diag(C.Structure):
@@ -217,7 +217,7 @@ class Oracle:
         self._cost = Cost(**{k: float(cost.get(k, 0.0)) for k, _ in Cost._fields_})
         self._integ = Integ(dt=float(integ["dt"]), substeps=int(integ["substeps"]),
                             accel_max=float(integ["accel_max"]),
-                            vx_min=float(integ["vx_min"]))
+                            vx_min=float(integ["vx_min"]), method=int(integ.get("method", 0)))
         self._h = lib().oracle_create(C.byref(self._veh), C.byref(self._cost),
                                       C.byref(self._integ))
         if not self._h:

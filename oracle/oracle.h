@@ -53,6 +53,8 @@ typedef struct {
     double dt;
     int substeps;
     double accel_max, vx_min;
+    int method; /* 0 forward Euler (the paper's), 1 classical fourth-order
+                 * Runge-Kutta (the alternative the paper compared against) */
 } oracle_integ;
 
 /* Per-wheel diagnostic of one right-hand-side evaluation (wheel order

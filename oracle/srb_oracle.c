@@ -100,6 +100,7 @@ oracle_ctx *oracle_create(const oracle_vehicle *veh, const oracle_cost *cost,
         return NULL;
     if (!(veh->Lf + veh->Lr > 0) || !(veh->e > 0) || !(veh->hR > 0)) return NULL;
     if (!(integ->dt > 0) || integ->substeps < 1) return NULL;
+    if (integ->method != 0 && integ->method != 1) return NULL;
     oracle_ctx *o = (oracle_ctx *)calloc(1, sizeof(oracle_ctx));
     if (!o) return NULL;
     o->v = *veh;
@@ -456,8 +457,26 @@ static void span_one(const oracle_ctx *o, double xi[13], double *J_io,
             oracle_diag d;
             oracle_rhs(o, xi, delta_dot, vx_dot, xd, &d);
             if (td && sl && tilt) discontinuity_margins(o, &d, xi, td, sl, tilt);
-            J += h * d.L;
-            for (int q = 0; q < 13; ++q) xi[q] = xi[q] + h * xd[q];
+            if (o->in.method == 1) {
+                /* classical fourth-order Runge-Kutta on (xi, J), J' = L, with
+                 * the control held; the limits apply to the completed step */
+                double k[4][13], Ls[4], stage[13];
+                for (int q = 0; q < 13; ++q) k[0][q] = xd[q];
+                Ls[0] = d.L;
+                const double c[3] = {0.5 * h, 0.5 * h, h};
+                for (int st = 1; st < 4; ++st) {
+                    oracle_diag ds;
+                    for (int q = 0; q < 13; ++q) stage[q] = xi[q] + c[st - 1] * k[st - 1][q];
+                    oracle_rhs(o, stage, delta_dot, vx_dot, k[st], &ds);
+                    Ls[st] = ds.L;
+                }
+                J += h / 6.0 * (Ls[0] + 2.0 * Ls[1] + 2.0 * Ls[2] + Ls[3]);
+                for (int q = 0; q < 13; ++q)
+                    xi[q] = xi[q] + h / 6.0 * (k[0][q] + 2.0 * k[1][q] + 2.0 * k[2][q] + k[3][q]);
+            } else {
+                J += h * d.L;
+                for (int q = 0; q < 13; ++q) xi[q] = xi[q] + h * xd[q];
+            }
             xi[12] = clampd(xi[12], -o->v.delta_max, o->v.delta_max);
             if (xi[6] < o->in.vx_min) xi[6] = o->in.vx_min;
             if (round32) {
