@@ -75,8 +75,8 @@ typedef struct {
 } plan_cost_t;
 
 /* Integration (sections "OCP Formulation" and "Real-Time Implementation"):
- * dt = zero-order-hold period of one control; substeps = forward-Euler steps
- * per control (Euler step h = dt / substeps); accel_max maps the throttle
+ * dt = zero-order-hold period of one control; substeps = integration steps
+ * per control (step h = dt / substeps); accel_max maps the throttle
  * channel in [-1, 1] to the prescribed longitudinal acceleration vx_dot;
  * vx_min is the floor kept on the CoM longitudinal speed (the model assumes it
  * positive). */
@@ -85,7 +85,17 @@ typedef struct {
     int substeps;
     float accel_max;
     float vx_min;
+    int method; /* PLAN_EULER (the paper's forward Euler) or PLAN_RK4 */
 } plan_integ_t;
+
+/* Integration method. PLAN_EULER: forward Euler, running cost by the left
+ * Riemann sum at the Euler nodes. PLAN_RK4: the classical fourth-order
+ * Runge-Kutta method the paper compared Euler against, applied to (state, J)
+ * with J' = L and the control held over the step; the steering limit and the
+ * speed floor apply to each completed step. PLAN_RK4 is available through
+ * plan_rollout and plan_rollout_chunk; the other rollout calls, the adjoint,
+ * the serving loop and the EST rollout accept PLAN_EULER only. */
+enum { PLAN_EULER = 0, PLAN_RK4 = 1 };
 
 enum { PLAN_ARGMIN = 0, PLAN_SOFTMIN = 1 };
 

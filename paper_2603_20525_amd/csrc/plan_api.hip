@@ -153,7 +153,10 @@ void fill_rollout_args(RolloutArgs &a, const plan_vehicle_t &v, const plan_cost_
     const double eps = (co.eps_esm > 0) ? (double)co.eps_esm : 0.1 * esm_level(v);
     a.inv_eps_esm = (float)(1.0 / eps);
     a.h = (float)((double)in.dt / in.substeps);
+    a.h_half = (float)(0.5 * (double)in.dt / in.substeps);
+    a.h_sixth = (float)((double)in.dt / in.substeps / 6.0);
     a.S = in.substeps;
+    a.method = in.method;
     a.accel_max = in.accel_max;
     a.vx_min = in.vx_min;
     a.tex = tex;
@@ -183,7 +186,7 @@ bool valid_cost(const plan_cost_t &c) {
 
 bool valid_integ(const plan_integ_t &i) {
     return isfinite(i.dt) && i.dt > 0 && i.substeps >= 1 && isfinite(i.accel_max) &&
-           isfinite(i.vx_min);
+           isfinite(i.vx_min) && (i.method == PLAN_EULER || i.method == PLAN_RK4);
 }
 
 bool finite_all(const float *p, int n) {
@@ -402,6 +405,8 @@ plan_status_t plan_sample_controls(plan_ctx *c, const plan_sample_t *spec, int K
 plan_status_t plan_rollout_sampled(plan_ctx *c, const float state0[13], const plan_sample_t *spec,
                                    int K, int N, float *cost_dev, float *final_state_dev) {
     if (!c) return PLAN_EINVAL;
+    if (c->integ.method != PLAN_EULER)
+        return fail(c, PLAN_EINVAL, "%s supports PLAN_EULER integration only", "plan_rollout_sampled");
     if (!state0 || !cost_dev) return fail(c, PLAN_EINVAL, "NULL argument");
     if (K < 1 || K > c->max_K) return fail(c, PLAN_EINVAL, "K outside [1, max_K]");
     if (N < 1 || N > c->max_N) return fail(c, PLAN_EINVAL, "N outside [1, max_N]");
@@ -448,6 +453,8 @@ plan_status_t plan_select_sampled(plan_ctx *c, const plan_sample_t *spec, const 
 plan_status_t plan_rollout_est(plan_ctx *c, const float state0[7], const float *controls_dev,
                                int K, int N, float *cost_dev, float *final_state_dev) {
     if (!c) return PLAN_EINVAL;
+    if (c->integ.method != PLAN_EULER)
+        return fail(c, PLAN_EINVAL, "%s supports PLAN_EULER integration only", "plan_rollout_est");
     if (!state0 || !controls_dev || !cost_dev) return fail(c, PLAN_EINVAL, "NULL argument");
     if (K < 1 || K > c->max_K) return fail(c, PLAN_EINVAL, "K outside [1, max_K]");
     if (N < 1 || N > c->max_N) return fail(c, PLAN_EINVAL, "N outside [1, max_N]");
@@ -497,6 +504,8 @@ plan_status_t plan_rollout_argmin(plan_ctx *c, const float state0[13], const flo
                                   int K, int N, float *cost_dev, float *final_state_dev,
                                   float *plan_dev, int *best_k, float *best_cost) {
     if (!c) return PLAN_EINVAL;
+    if (c->integ.method != PLAN_EULER)
+        return fail(c, PLAN_EINVAL, "%s supports PLAN_EULER integration only", "plan_rollout_argmin");
     if (!state0 || !controls_dev || !cost_dev || !plan_dev)
         return fail(c, PLAN_EINVAL, "NULL argument");
     if (K < 1 || K > c->max_K) return fail(c, PLAN_EINVAL, "K outside [1, max_K]");
@@ -522,6 +531,8 @@ plan_status_t plan_rollout_sampled_argmin(plan_ctx *c, const float state0[13],
                                           float *cost_dev, float *final_state_dev,
                                           float *plan_dev, int *best_k, float *best_cost) {
     if (!c) return PLAN_EINVAL;
+    if (c->integ.method != PLAN_EULER)
+        return fail(c, PLAN_EINVAL, "%s supports PLAN_EULER integration only", "plan_rollout_sampled_argmin");
     if (!state0 || !cost_dev || !plan_dev) return fail(c, PLAN_EINVAL, "NULL argument");
     if (K < 1 || K > c->max_K) return fail(c, PLAN_EINVAL, "K outside [1, max_K]");
     if (N < 1 || N > c->max_N) return fail(c, PLAN_EINVAL, "N outside [1, max_N]");
@@ -643,6 +654,8 @@ plan_status_t plan_rollout_grad(plan_ctx *c, const float state0[13], const float
                                 int K, int N, const float *weight_dev, int checkpoint_every,
                                 float *cost_dev, float *grad_dev) {
     if (!c) return PLAN_EINVAL;
+    if (c->integ.method != PLAN_EULER)
+        return fail(c, PLAN_EINVAL, "%s supports PLAN_EULER integration only", "plan_rollout_grad");
     if (!state0 || !controls_dev || !cost_dev || !grad_dev)
         return fail(c, PLAN_EINVAL, "NULL argument");
     if (K < 1 || K > c->max_K) return fail(c, PLAN_EINVAL, "K outside [1, max_K]");

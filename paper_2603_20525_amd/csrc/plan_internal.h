@@ -39,8 +39,10 @@ struct RolloutArgs {
     float goal_x, goal_y, goal_r2;
     float sigma, inv_eps_esm;
     // integration
-    float h;                       // Euler step dt / substeps
+    float h;                       // integration step dt / substeps
+    float h_half, h_sixth;         // h / 2 and h / 6 (fourth-order Runge-Kutta)
     int S;                         // substeps per control
+    int method;                    // 0 forward Euler, 1 fourth-order Runge-Kutta
     float accel_max, vx_min;
     // terrain: float4 texels (h, f_x, f_y, cost) on a W x H grid
     const float4 *tex;

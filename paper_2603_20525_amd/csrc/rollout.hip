@@ -36,7 +36,7 @@ namespace {
 // generator block per four intervals, kept in registers) instead of reading
 // a.controls. Lanes with store == false run a duplicate candidate only to
 // keep their lane group complete.
-template <int LANES, bool CHUNK, bool SAMPLED = false>
+template <int LANES, bool CHUNK, bool SAMPLED = false, bool RK4 = false>
 __device__ __forceinline__ float simulate(const RolloutArgs &a, int k, int sub, bool store) {
     constexpr int WPL = 4 / LANES;  // wheels per lane
     const size_t K = (size_t)a.K;
@@ -89,7 +89,10 @@ __device__ __forceinline__ float simulate(const RolloutArgs &a, int k, int sub, 
                     break;
                 }
             }
-            euler_step<LANES>(a, arms, st, J, dd, ax);
+            if constexpr (RK4)
+                rk4_step<LANES>(a, arms, st, J, dd, ax);
+            else
+                euler_step<LANES>(a, arms, st, J, dd, ax);
         }
     }
 
@@ -154,7 +157,8 @@ __device__ __forceinline__ void argmin_epilogue(const RolloutArgs &a, unsigned l
     write_plan<SAMPLED>(kb, a.N, a.K, a.controls, a.smp, a.drate_max, a.plan, tid, BLOCK);
 }
 
-template <int LANES, int BLOCK, bool CHUNK, bool SAMPLED = false, bool FUSED = false>
+template <int LANES, int BLOCK, bool CHUNK, bool SAMPLED = false, bool FUSED = false,
+          bool RK4 = false>
 __global__ __launch_bounds__(BLOCK) void rollout_srb(const RolloutArgs a) {
     const int gtid = blockIdx.x * BLOCK + threadIdx.x;
     const int sub = gtid & (LANES - 1);
@@ -164,7 +168,7 @@ __global__ __launch_bounds__(BLOCK) void rollout_srb(const RolloutArgs a) {
     // is complete for the DPP sums; they store nothing (and reach the fused
     // epilogue's barriers like every other lane).
     if (!store) k = a.K - 1;
-    const float J = simulate<LANES, CHUNK, SAMPLED>(a, k, sub, store);
+    const float J = simulate<LANES, CHUNK, SAMPLED, RK4>(a, k, sub, store);
     if constexpr (FUSED)
         argmin_epilogue<BLOCK, SAMPLED>(a, (store && sub == 0) ? cost_key(J, k) : ~0ull);
 }
@@ -228,10 +232,14 @@ hipError_t launch_rollout(const RolloutArgs &a, int lanes, int block, bool chunk
                           hipStream_t s) {
     const long long threads = (long long)a.K * lanes;
     const unsigned grid = (unsigned)((threads + block - 1) / block);
-#define PLAN_LAUNCH(L, B, C)                                                       \
-    if (lanes == L && block == B && chunk == C) {                                  \
-        hipLaunchKernelGGL((rollout_srb<L, B, C>), dim3(grid), dim3(B), 0, s, a); \
-        return hipGetLastError();                                                  \
+#define PLAN_LAUNCH(L, B, C)                                                                   \
+    if (lanes == L && block == B && chunk == C) {                                              \
+        if (a.method == 1)                                                                     \
+            hipLaunchKernelGGL((rollout_srb<L, B, C, false, false, true>), dim3(grid), dim3(B), \
+                               0, s, a);                                                       \
+        else                                                                                   \
+            hipLaunchKernelGGL((rollout_srb<L, B, C>), dim3(grid), dim3(B), 0, s, a);          \
+        return hipGetLastError();                                                              \
     }
     PLAN_LAUNCH(1, 64, false)
     PLAN_LAUNCH(2, 64, false)

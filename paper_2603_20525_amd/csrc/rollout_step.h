@@ -196,14 +196,14 @@ __device__ __forceinline__ WheelOut wadd(const WheelOut &p, const WheelOut &q) {
     return WheelOut{p.Fy + q.Fy, p.Fz + q.Fz, p.Mx + q.Mx, p.My + q.My, p.Mz + q.Mz, p.c + q.c};
 }
 
-// One forward-Euler step of every quantity of the model for one candidate
-// (this lane's wheels, group sums over the candidate's lanes): the running
-// cost at the node is added to J and the state advanced in place.
+// Right-hand side of the model for one candidate (this lane's wheels, group
+// sums over the candidate's lanes): xd receives the state derivative and the
+// return value is the running cost rate L at the state.
 template <int LANES>
-__device__ __forceinline__ void euler_step(const RolloutArgs &a, const Arm (&arms)[4 / LANES],
-                                           float (&st)[13], float &J, float dd, float ax) {
+__device__ __forceinline__ float srb_rhs(const RolloutArgs &a, const Arm (&arms)[4 / LANES],
+                                         const float (&st)[13], float dd, float ax,
+                                         float (&xd)[13]) {
     constexpr int WPL = 4 / LANES;  // wheels per lane
-    const float h = a.h;
     const float half_pi = 1.57079632679489662f;
     float x = st[0], y = st[1], z = st[2];
     float psi = st[3], th = st[4], ph = st[5];
@@ -283,38 +283,75 @@ __device__ __forceinline__ void euler_step(const RolloutArgs &a, const Arm (&arm
     const float wyd = fmaf(-a.dJxz * wx, wz, My) * a.invJyy;
     const float wzd = fmaf(a.dJxy * wx, wy, Mz) * a.invJzz;
 
-    // running cost at the node (left Riemann sum)
-    J = fmaf(h, L0 + csum, J);
+    xd[0] = vWx;
+    xd[1] = vWy;
+    xd[2] = vWz;
+    xd[3] = psid;
+    xd[4] = thd;
+    xd[5] = phd;
+    xd[6] = ax;
+    xd[7] = vyd;
+    xd[8] = vzd;
+    xd[9] = wxd;
+    xd[10] = wyd;
+    xd[11] = wzd;
+    xd[12] = dd;
+    return L0 + csum;
+}
 
-    // forward Euler
-    x = fmaf(h, vWx, x);
-    y = fmaf(h, vWy, y);
-    z = fmaf(h, vWz, z);
-    psi = fmaf(h, psid, psi);
-    th = fmaf(h, thd, th);
-    ph = fmaf(h, phd, ph);
-    vx = fmaf(h, ax, vx);
-    vy = fmaf(h, vyd, vy);
-    vz = fmaf(h, vzd, vz);
-    wx = fmaf(h, wxd, wx);
-    wy = fmaf(h, wyd, wy);
-    wz = fmaf(h, wzd, wz);
-    delta = fmaf(h, dd, delta);
-    delta = clampf_nan(delta, -a.delta_max, a.delta_max);
-    vx = (vx < a.vx_min) ? a.vx_min : vx;
-    st[0] = x;
-    st[1] = y;
-    st[2] = z;
-    st[3] = psi;
-    st[4] = th;
-    st[5] = ph;
-    st[6] = vx;
-    st[7] = vy;
-    st[8] = vz;
-    st[9] = wx;
-    st[10] = wy;
-    st[11] = wz;
-    st[12] = delta;
+// Steering-angle limit and speed floor, applied to a completed step.
+__device__ __forceinline__ void apply_limits(const RolloutArgs &a, float (&st)[13]) {
+    st[12] = clampf_nan(st[12], -a.delta_max, a.delta_max);
+    st[6] = (st[6] < a.vx_min) ? a.vx_min : st[6];
+}
+
+// One forward-Euler step (the paper's integrator): the running cost at the
+// node is added to J (left Riemann sum) and the state advanced in place.
+template <int LANES>
+__device__ __forceinline__ void euler_step(const RolloutArgs &a, const Arm (&arms)[4 / LANES],
+                                           float (&st)[13], float &J, float dd, float ax) {
+    float xd[13];
+    const float L = srb_rhs<LANES>(a, arms, st, dd, ax, xd);
+    J = fmaf(a.h, L, J);
+#pragma unroll
+    for (int q = 0; q < 13; ++q) st[q] = fmaf(a.h, xd[q], st[q]);
+    apply_limits(a, st);
+}
+
+// One classical fourth-order Runge-Kutta step on (state, J) with J' = L and
+// the control held (the alternative integrator the paper compared Euler
+// with); the limits apply to the completed step.
+template <int LANES>
+__device__ __forceinline__ void rk4_step(const RolloutArgs &a, const Arm (&arms)[4 / LANES],
+                                         float (&st)[13], float &J, float dd, float ax) {
+    float k[13], acc[13], stage[13];
+    float L = srb_rhs<LANES>(a, arms, st, dd, ax, k);
+    float Lacc = L;
+#pragma unroll
+    for (int q = 0; q < 13; ++q) {
+        acc[q] = k[q];
+        stage[q] = fmaf(a.h_half, k[q], st[q]);
+    }
+    L = srb_rhs<LANES>(a, arms, stage, dd, ax, k);
+    Lacc = fmaf(2.0f, L, Lacc);
+#pragma unroll
+    for (int q = 0; q < 13; ++q) {
+        acc[q] = fmaf(2.0f, k[q], acc[q]);
+        stage[q] = fmaf(a.h_half, k[q], st[q]);
+    }
+    L = srb_rhs<LANES>(a, arms, stage, dd, ax, k);
+    Lacc = fmaf(2.0f, L, Lacc);
+#pragma unroll
+    for (int q = 0; q < 13; ++q) {
+        acc[q] = fmaf(2.0f, k[q], acc[q]);
+        stage[q] = fmaf(a.h, k[q], st[q]);
+    }
+    L = srb_rhs<LANES>(a, arms, stage, dd, ax, k);
+    Lacc = Lacc + L;
+    J = fmaf(a.h_sixth, Lacc, J);
+#pragma unroll
+    for (int q = 0; q < 13; ++q) st[q] = fmaf(a.h_sixth, acc[q] + k[q], st[q]);
+    apply_limits(a, st);
 }
 
 }  // namespace plan

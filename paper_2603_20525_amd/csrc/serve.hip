@@ -341,6 +341,8 @@ plan_status_t plan_server_submit(plan_server *s, const plan_request_t *r, int *i
         return sfail(s, PLAN_EINVAL, "terrain origin/resolution invalid");
     if (!plan::valid_cost(r->cost) || !plan::valid_integ(r->integ))
         return sfail(s, PLAN_EINVAL, "invalid cost or integration parameters");
+    if (r->integ.method != PLAN_EULER)
+        return sfail(s, PLAN_EINVAL, "the server integrates with PLAN_EULER only");
     if (!plan::finite_all(r->state0, 13)) return sfail(s, PLAN_EINVAL, "state0 not finite");
     Req q;
     q.r = *r;

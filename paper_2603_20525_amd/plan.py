@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libplan.so")
 PLAN_OK, PLAN_EINVAL, PLAN_ENOMEM, PLAN_EDEVICE, PLAN_ENOTERRAIN = 0, -1, -2, -3, -4
 PLAN_ARGMIN, PLAN_SOFTMIN = 0, 1
 PLAN_SAMPLE_UNIFORM, PLAN_SAMPLE_GAUSSIAN = 0, 1
+PLAN_EULER, PLAN_RK4 = 0, 1
 STATUS_NAMES = {0: "PLAN_OK", -1: "PLAN_EINVAL", -2: "PLAN_ENOMEM", -3: "PLAN_EDEVICE",
                 -4: "PLAN_ENOTERRAIN"}
 
@@ -41,7 +42,7 @@ class Cost(C.Structure):
 
 class Integ(C.Structure):
     _fields_ = [("dt", C.c_float), ("substeps", C.c_int), ("accel_max", C.c_float),
-                ("vx_min", C.c_float)]
+                ("vx_min", C.c_float), ("method", C.c_int)]
 
 
 class Sample(C.Structure):
