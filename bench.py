@@ -100,6 +100,134 @@ def _summ(lat, t_first, t_last, steps, n):
             "max_ms": max(lat) * 1e3, "req_per_s": n / span, "rollout_steps_per_s": steps / span}
 
 
+# Algorithmic FP32 operations per step of the other rollout variants (same
+# counting rules as OPS_PER_STEP; tabulated in the design notes).
+EST_OPS_PER_STEP = 130
+RK4_OPS_PER_STEP = 4 * (OPS_PER_STEP - 24) + 24 + 3 * 13 * 2 + 2 * 13
+HBM_PEAK_GBS = 8000.0
+
+
+def _time_ms(fn, reps=5, warm=2):
+    """Median duration (ms) of fn() between HIP events on the current stream."""
+    import torch
+    for _ in range(warm):
+        fn()
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def rows_leg():
+    """One measurement per widened row of the path, each against its bound:
+    the paper's own solver shape end to end (in-kernel sampling, rollout and
+    argmin in one launch), the extended single-track baseline, the RK4
+    option, the adjoint, and the terrain preparation kernels."""
+    import numpy as np
+    import torch
+    from paper_2603_20525_amd import inputs
+    from paper_2603_20525_amd import plan as P
+    out = {}
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()  # noqa: E731
+    alu = lambda ops, sec: ops / sec / 1e9 / ALU_PEAK_GOPS  # noqa: E731
+
+    # paper shape: K = 204 288 uniform steering-rate samples, 16 x 0.25 s, 5 ms Euler
+    T = inputs.fbm_berm_terrain(2000)
+    w = inputs.paper_shape(K=8, terrain=T)
+    K, N, S = 204288, 16, w.integ["substeps"]
+    pl = P.Planner(w.vehicle, w.cost, w.integ, K, N, T.W, T.H)
+    pl.set_terrain(dev(T.height), T.x0, T.y0, T.res)
+    spec = P.sample_spec(P.PLAN_SAMPLE_UNIFORM, 6000, 0, (1.0, 0.0))
+    J = torch.empty(K, device="cuda")
+    plan = torch.empty(N, 2, device="cuda")
+    ms = _time_ms(lambda: pl.rollout_sampled_argmin(w.state0, spec, N, J, plan,
+                                                    want_result=False))
+    steps = K * N * S
+    out["paper_shape_sampled_one_launch"] = {
+        "ms_per_plan": ms, "plans_per_s": 1e3 / ms, "samples_per_s": K * 1e3 / ms,
+        "rollout_steps_per_s": steps * 1e3 / ms, "alu_frac": alu(OPS_PER_STEP * steps, ms / 1e3),
+        "paper_context": "11e6 samples/s (80 Hz) on an RTX 5000 Ada Mobile; about 21e6 on an "
+                         "RTX 6000 Ada (other hardware, scanned terrain)"}
+    # extended single-track formulation at the same shape (materialised samples)
+    u = torch.empty(N, 2, K, device="cuda")
+    pl.sample_controls(spec, u)
+    s13 = w.state0
+    s7 = [s13[0], s13[1], s13[3], s13[7], s13[11], s13[12], s13[6]]
+    ms_est = _time_ms(lambda: pl.rollout_est(s7, u, J))
+    ms_srb = _time_ms(lambda: pl.rollout(w.state0, u, J))
+    out["est_paper_shape"] = {
+        "ms": ms_est, "rollout_steps_per_s": steps * 1e3 / ms_est,
+        "alu_frac": alu(EST_OPS_PER_STEP * steps, ms_est / 1e3),
+        "srb_ms_same_samples": ms_srb}
+    pl.close()
+
+    # RK4 on the single-plan workload
+    w = inputs.c2()
+    w.integ = dict(w.integ, method=P.PLAN_RK4)
+    pl = P.Planner(w.vehicle, w.cost, w.integ, w.K, w.N, w.terrain.W, w.terrain.H)
+    pl.set_terrain(dev(w.terrain.height), w.terrain.x0, w.terrain.y0, w.terrain.res)
+    uc = dev(w.controls)
+    Jc = torch.empty(w.K, device="cuda")
+    ms = _time_ms(lambda: pl.rollout(w.state0, uc, Jc))
+    steps = w.K * w.N
+    out["rk4_single_plan"] = {"ms": ms, "rollout_steps_per_s": steps * 1e3 / ms,
+                              "alu_frac": alu(RK4_OPS_PER_STEP * steps, ms / 1e3)}
+    pl.close()
+
+    # adjoint: forward (checkpoints every 10 intervals) + backward, K = 1024
+    # and the top-32 refinement set
+    w = inputs.c4()
+    pl = P.Planner(w.vehicle, w.cost, w.integ, w.K, w.N, w.terrain.W, w.terrain.H)
+    pl.set_terrain(dev(w.terrain.height), w.terrain.x0, w.terrain.y0, w.terrain.res)
+    res = {}
+    for name, Kk in (("K1024", w.K), ("top32", 32)):
+        uk = dev(np.ascontiguousarray(w.controls[:, :, :Kk]))
+        Jk = torch.empty(Kk, device="cuda")
+        gk = torch.empty_like(uk)
+        msg = _time_ms(lambda: pl.rollout_grad(w.state0, uk, Jk, gk, checkpoint_every=10))
+        res[name] = {"ms": msg, "forward_steps_per_s": Kk * w.N * 1e3 / msg}
+    out["adjoint_c4"] = res
+    pl.close()
+
+    # terrain preparation on the 2048 x 2048 map: level-of-detail smoothing
+    # (HBM: two passes, each reading and writing the grid once) and the costmap
+    T = inputs.side_slope_terrain(5000)
+    pl = P.Planner(inputs.WORKLOAD_VEHICLE, inputs.BASE_COST, inputs.BASE_INTEG, 8, 8, T.W, T.H)
+    h = dev(T.height)
+    o_ = torch.empty_like(h)
+    sm = {}
+    for sigma in (0.3, 1.5):
+        ms = _time_ms(lambda: pl.smooth_terrain(h, T.res, sigma, o_))
+        r = int(np.ceil(3 * sigma / T.res - 1e-6))
+        nbytes = 2 * 2 * 4 * T.W * T.H
+        sm[f"sigma_{sigma}"] = {
+            "ms": ms, "taps": 2 * r + 1, "gb_per_s": nbytes / ms / 1e6,
+            "hbm_frac": nbytes / ms / 1e6 / HBM_PEAK_GBS,
+            "alu_frac": alu(2 * (2 * r + 1) * T.W * T.H, ms / 1e3)}
+    out["lod_smoothing_2048"] = sm
+    polys = inputs.obstacle_polygons(T, seed=5, count=20, boundary=True)
+    verts = np.concatenate([np.asarray(v, np.float32).reshape(-1, 2) for _, v in polys])
+    offsets = np.concatenate([[0], np.cumsum([len(v) for _, v in polys])]).astype(int)
+    kinds = [k for k, _ in polys]
+    vd = dev(verts)
+    cm = torch.empty_like(h)
+    ms = _time_ms(lambda: pl.costmap_polygons(vd, offsets, kinds, cm, T.x0, T.y0, T.res, 1e6,
+                                              0.25))
+    edges = int(offsets[-1])
+    out["costmap_2048"] = {"ms": ms, "polygons": len(polys), "edges": edges,
+                           "node_edge_tests_per_s": T.W * T.H * edges * 1e3 / ms,
+                           "alu_frac": alu(25 * T.W * T.H * edges, ms / 1e3)}
+    pl.close()
+    return out
+
+
 def serving_leg(scale=1.0, chunk=16, slots=64):
     """Replay the 64-request serving trace (Poisson arrivals at 200 req/s,
     K in {512..8192}, N in 40..160, own 256x256 terrain each) through the
@@ -190,6 +318,9 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB and exit (the "
                          "reference kernel for scaling the HBM byte counters)")
+    ap.add_argument("--rows", type=int, default=1,
+                    help="also measure the widened rows (paper shape, EST, RK4, adjoint, "
+                         "terrain preparation)")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     args = ap.parse_args()
@@ -320,6 +451,9 @@ def main():
             "at_200_req_s": serving_leg(1.0),
             "burst_all_at_once": serving_leg(0.0),
         }
+    if args.rows:
+        print("[bench] widened rows", file=sys.stderr, flush=True)
+        out["rows"] = rows_leg()
     if args.cpu_seconds > 0:
         print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
