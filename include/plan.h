@@ -231,8 +231,13 @@ plan_status_t plan_rollout_chunk(plan_ctx *ctx, float *state_dev, float *cost_de
  *                control lies outside the admissible set and is clamped, zero
  *                after the goal exit, zero rows for a +inf candidate).
  * Non-smooth points take the derivative of the branch the forward pass took.
- * The library grows an internal workspace of 4*(13 K (N/C + 2) + 14 K C S)
- * bytes on first use (may synchronise the stream then).
+ * The backward kernel splits each candidate's wheels over 1, 2 or 4 lanes
+ * (the automatic choice of plan_rollout, or the lanes set by
+ * plan_set_launch); the result is bit-identical for every choice.
+ * The forward pass is one launch that stores the checkpoints; the backward
+ * pass is a second. The library grows an internal workspace of
+ * 4*(13 K (ceil(N/C) + 1) + 14 K C S) bytes when a call needs more than the
+ * previous ones (may synchronise the stream then).
  * Errors: PLAN_EINVAL, PLAN_ENOTERRAIN, PLAN_ENOMEM, PLAN_EDEVICE. */
 plan_status_t plan_rollout_grad(plan_ctx *ctx, const float state0[13],
                                 const float *controls_dev, int K, int N,

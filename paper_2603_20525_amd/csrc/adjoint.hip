@@ -34,11 +34,56 @@ __device__ __forceinline__ float dlerp_dty(float tx, float a00, float a10, float
     return b1 - b0;
 }
 
+// Adjoint contributions of one wheel to the chassis quantities it reads:
+// the rotation matrix, the rear constraint force, cos(delta), delta, the
+// body velocities and rates, and the CoM position.
+struct WheelAdj {
+    float R11, R12, R13, R21, R22, R23, R31, R32, R33;
+    float FxR, cosd, delta;
+    float vx, vy, vz, wx, wy, wz;
+    float x, y, z;
+};
+
+__device__ __forceinline__ WheelAdj adj_add(const WheelAdj &p, const WheelAdj &q) {
+    WheelAdj o;
+    o.R11 = p.R11 + q.R11; o.R12 = p.R12 + q.R12; o.R13 = p.R13 + q.R13;
+    o.R21 = p.R21 + q.R21; o.R22 = p.R22 + q.R22; o.R23 = p.R23 + q.R23;
+    o.R31 = p.R31 + q.R31; o.R32 = p.R32 + q.R32; o.R33 = p.R33 + q.R33;
+    o.FxR = p.FxR + q.FxR; o.cosd = p.cosd + q.cosd; o.delta = p.delta + q.delta;
+    o.vx = p.vx + q.vx; o.vy = p.vy + q.vy; o.vz = p.vz + q.vz;
+    o.wx = p.wx + q.wx; o.wy = p.wy + q.wy; o.wz = p.wz + q.wz;
+    o.x = p.x + q.x; o.y = p.y + q.y; o.z = p.z + q.z;
+    return o;
+}
+
+// Sum over the candidate's lanes, in the forward pass's fixed order
+// (w0 + w1) + (w2 + w3).
+template <int LANES>
+__device__ __forceinline__ WheelAdj adj_group_sum(WheelAdj v) {
+    v.R11 = group_sum<LANES>(v.R11); v.R12 = group_sum<LANES>(v.R12);
+    v.R13 = group_sum<LANES>(v.R13); v.R21 = group_sum<LANES>(v.R21);
+    v.R22 = group_sum<LANES>(v.R22); v.R23 = group_sum<LANES>(v.R23);
+    v.R31 = group_sum<LANES>(v.R31); v.R32 = group_sum<LANES>(v.R32);
+    v.R33 = group_sum<LANES>(v.R33);
+    v.FxR = group_sum<LANES>(v.FxR); v.cosd = group_sum<LANES>(v.cosd);
+    v.delta = group_sum<LANES>(v.delta);
+    v.vx = group_sum<LANES>(v.vx); v.vy = group_sum<LANES>(v.vy);
+    v.vz = group_sum<LANES>(v.vz); v.wx = group_sum<LANES>(v.wx);
+    v.wy = group_sum<LANES>(v.wy); v.wz = group_sum<LANES>(v.wz);
+    v.x = group_sum<LANES>(v.x); v.y = group_sum<LANES>(v.y); v.z = group_sum<LANES>(v.z);
+    return v;
+}
+
 // Vector-Jacobian product of one Euler step (state st, applied controls dd,
-// ax). In: lam = dJ/d(next state), wJ = dJ/d(running cost). Out: lam =
-// dJ/d(this state), *g_dd, *g_ax = dJ/d(dd), dJ/d(ax) through this step.
-__device__ void step_vjp(const RolloutArgs &a, const float (&st)[13], float dd, float ax,
-                         float wJ, float (&lam)[13], float *g_dd, float *g_ax) {
+// ax) for one candidate whose wheels are split over LANES lanes (this lane
+// holds `arms`). In: lam = dJ/d(next state), wJ = dJ/d(running cost). Out:
+// lam = dJ/d(this state), *g_dd, *g_ax = dJ/d(dd), dJ/d(ax) through this
+// step; identical in every lane of the group.
+template <int LANES>
+__device__ void step_vjp(const RolloutArgs &a, const Arm (&arms)[4 / LANES],
+                         const float (&st)[13], float dd, float ax, float wJ, float (&lam)[13],
+                         float *g_dd, float *g_ax) {
+    constexpr int WPL = 4 / LANES;
     const float h = a.h;
     const float half_pi = 1.57079632679489662f;
     const float x = st[0], y = st[1], z = st[2];
@@ -65,16 +110,17 @@ __device__ void step_vjp(const RolloutArgs &a, const float (&st)[13], float dd, 
     const float mm_raw = fmaf(-U, a.inv_eps_esm, 1.0f);
     const float mm = fmaxf(0.0f, mm_raw);
 
-    // per-wheel forward quantities
-    float P_x[4], P_y[4], P_z[4], cl_u[4], cl_v[4], txv[4], tyv[4];
-    float4 T00[4], T10[4], T01[4], T11[4];
-    float vix[4], viy[4], viz[4], th_[4], tfx[4], tfy[4];
-    float nBx[4], nBy[4], nBz[4], inz[4], chi[4], relx[4], rely[4], Dv[4], chid[4];
-    float Fkr[4], Fk[4], Fb[4], Fz[4], rr[4], alpha[4], Ca[4], qq[4], Fyv[4];
-    bool guard[4], fb_first[4];
+    // this lane's wheels: forward quantities
+    float P_x[WPL], P_y[WPL], P_z[WPL], cl_u[WPL], cl_v[WPL], txv[WPL], tyv[WPL];
+    float4 T00[WPL], T10[WPL], T01[WPL], T11[WPL];
+    float vix[WPL], viy[WPL], viz[WPL], th_[WPL], tfx[WPL], tfy[WPL];
+    float nBx[WPL], nBy[WPL], nBz[WPL], inz[WPL], chi[WPL], relx[WPL], rely[WPL], Dv[WPL],
+        chid[WPL];
+    float Fkr[WPL], Fk[WPL], Fb[WPL], Fz[WPL], rr[WPL], alpha[WPL], Ca[WPL], qq[WPL], Fyv[WPL];
+    bool guard[WPL], fb_first[WPL];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const Arm r = arm(a, i);
+    for (int i = 0; i < WPL; ++i) {
+        const Arm r = arms[i];
         P_x[i] = fmaf(A.R11, r.rx, fmaf(A.R12, r.ry, fmaf(A.R13, r.rz, x)));
         P_y[i] = fmaf(A.R21, r.rx, fmaf(A.R22, r.ry, fmaf(A.R23, r.rz, y)));
         P_z[i] = fmaf(A.R31, r.rx, fmaf(A.R32, r.ry, fmaf(A.R33, r.rz, z)));
@@ -169,21 +215,21 @@ __device__ void step_vjp(const RolloutArgs &a, const float (&st)[13], float dd, 
     L_wx += a.dJxy * wy * L_Mz;
     L_wy += a.dJxy * wx * L_Mz;
 
-    // per-wheel reverse
-    float L_R11 = 0, L_R12 = 0, L_R13 = 0, L_R21 = 0, L_R22 = 0, L_R23 = 0;
-    float L_R31 = 0, L_R32 = 0, L_R33 = 0;
-    float L_FxR = 0, L_cosd = 0;
+    // per-wheel reverse: each of this lane's wheels into its own WheelAdj,
+    // then the fixed-order sum over the candidate's wheels
+    WheelAdj wadj[WPL];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const Arm r = arm(a, i);
+    for (int i = 0; i < WPL; ++i) {
+        const Arm r = arms[i];
+        WheelAdj W = {};
         // moments and force sums
         float L_fy = L_Fy - r.rz * L_Mx + r.rx * L_Mz;
         float L_Fzw = L_Fz + r.ry * L_Mx - r.rx * L_My;
         const float L_Fxw = r.rz * L_My - r.ry * L_Mz;
-        if (!r.front) L_FxR += L_Fxw;
+        if (!r.front) W.FxR += L_Fxw;
         float L_Fyw = L_fy;
         if (r.front) {
-            L_cosd += Fyv[i] * L_fy;
+            W.cosd += Fyv[i] * L_fy;
             L_Fyw = cosd * L_fy;
         }
         // Fy = (Fz * (-Ca mu)) * q, q = rsqrt(mu^2 + Ca^2)
@@ -194,7 +240,7 @@ __device__ void step_vjp(const RolloutArgs &a, const float (&st)[13], float dd, 
         float L_Ca = Fz[i] * (-a.mu) * L_P1;
         L_Ca += -Ca[i] * qq[i] * qq[i] * qq[i] * L_q;
         const float L_alpha = a.C * L_Ca;
-        if (r.front) L_delta -= L_alpha;
+        if (r.front) W.delta -= L_alpha;
         float L_vix = 0.0f, L_viy = 0.0f, L_viz = 0.0f;
         if (!guard[i]) {
             const float L_r = L_alpha / fmaf(rr[i], rr[i], 1.0f);
@@ -222,25 +268,25 @@ __device__ void step_vjp(const RolloutArgs &a, const float (&st)[13], float dd, 
         L_viz += nBz[i] * L_D;
         L_vix += L_relx;
         L_chi += -wy * L_relx;
-        L_wy += -chi[i] * L_relx;
+        W.wy += -chi[i] * L_relx;
         L_viy += L_rely;
         L_chi += wx * L_rely;
-        L_wx += chi[i] * L_rely;
+        W.wx += chi[i] * L_rely;
         // chi = (Pz - h) * inz
         float L_Pz = inz[i] * L_chi;
         const float L_hgt = -inz[i] * L_chi;
         L_inz += (P_z[i] - th_[i]) * L_chi;
         L_nBz += -inz[i] * inz[i] * L_inz;
         // normal in body frame
-        L_R31 += L_nBx;
-        L_R11 += -tfx[i] * L_nBx;
-        L_R21 += -tfy[i] * L_nBx;
-        L_R32 += L_nBy;
-        L_R12 += -tfx[i] * L_nBy;
-        L_R22 += -tfy[i] * L_nBy;
-        L_R33 += L_nBz;
-        L_R13 += -tfx[i] * L_nBz;
-        L_R23 += -tfy[i] * L_nBz;
+        W.R31 += L_nBx;
+        W.R11 += -tfx[i] * L_nBx;
+        W.R21 += -tfy[i] * L_nBx;
+        W.R32 += L_nBy;
+        W.R12 += -tfx[i] * L_nBy;
+        W.R22 += -tfy[i] * L_nBy;
+        W.R33 += L_nBz;
+        W.R13 += -tfx[i] * L_nBz;
+        W.R23 += -tfy[i] * L_nBz;
         const float L_tfx = -A.R11 * L_nBx - A.R12 * L_nBy - A.R13 * L_nBz;
         const float L_tfy = -A.R21 * L_nBx - A.R22 * L_nBy - A.R23 * L_nBz;
         // bilinear terrain: d/dtx, d/dty of (h, f_x, f_y, c)
@@ -257,29 +303,53 @@ __device__ void step_vjp(const RolloutArgs &a, const float (&st)[13], float dd, 
         const float L_Px = cl_u[i] * a.inv_res * L_tx;
         const float L_Py = cl_v[i] * a.inv_res * L_ty;
         // contact-point velocity
-        L_vx += L_vix;
-        L_wy += r.rz * L_vix;
-        L_wz += -r.ry * L_vix;
-        L_vy += L_viy;
-        L_wz += r.rx * L_viy;
-        L_wx += -r.rz * L_viy;
-        L_vz += L_viz;
-        L_wx += r.ry * L_viz;
-        L_wy += -r.rx * L_viz;
+        W.vx += L_vix;
+        W.wy += r.rz * L_vix;
+        W.wz += -r.ry * L_vix;
+        W.vy += L_viy;
+        W.wz += r.rx * L_viy;
+        W.wx += -r.rz * L_viy;
+        W.vz += L_viz;
+        W.wx += r.ry * L_viz;
+        W.wy += -r.rx * L_viz;
         // contact point
-        L_x += L_Px;
-        L_R11 += r.rx * L_Px;
-        L_R12 += r.ry * L_Px;
-        L_R13 += r.rz * L_Px;
-        L_y += L_Py;
-        L_R21 += r.rx * L_Py;
-        L_R22 += r.ry * L_Py;
-        L_R23 += r.rz * L_Py;
-        L_z += L_Pz;
-        L_R31 += r.rx * L_Pz;
-        L_R32 += r.ry * L_Pz;
-        L_R33 += r.rz * L_Pz;
+        W.x += L_Px;
+        W.R11 += r.rx * L_Px;
+        W.R12 += r.ry * L_Px;
+        W.R13 += r.rz * L_Px;
+        W.y += L_Py;
+        W.R21 += r.rx * L_Py;
+        W.R22 += r.ry * L_Py;
+        W.R23 += r.rz * L_Py;
+        W.z += L_Pz;
+        W.R31 += r.rx * L_Pz;
+        W.R32 += r.ry * L_Pz;
+        W.R33 += r.rz * L_Pz;
+        wadj[i] = W;
     }
+    WheelAdj wsum;
+    if constexpr (WPL == 4)
+        wsum = adj_add(adj_add(wadj[0], wadj[1]), adj_add(wadj[2], wadj[3]));
+    else if constexpr (WPL == 2)
+        wsum = adj_add(wadj[0], wadj[1]);
+    else
+        wsum = wadj[0];
+    wsum = adj_group_sum<LANES>(wsum);
+    float L_R11 = wsum.R11, L_R12 = wsum.R12, L_R13 = wsum.R13;
+    float L_R21 = wsum.R21, L_R22 = wsum.R22, L_R23 = wsum.R23;
+    float L_R31 = wsum.R31, L_R32 = wsum.R32, L_R33 = wsum.R33;
+    const float L_FxR = wsum.FxR, L_cosd = wsum.cosd;
+    L_delta += wsum.delta;
+    L_vx += wsum.vx;
+    L_vy += wsum.vy;
+    L_vz += wsum.vz;
+    L_wx += wsum.wx;
+    L_wy += wsum.wy;
+    L_wz += wsum.wz;
+    L_x += wsum.x;
+    L_y += wsum.y;
+    L_z += wsum.z;
+
 
     // chassis
     L_delta += -sind * L_cosd;
@@ -375,19 +445,26 @@ __device__ void step_vjp(const RolloutArgs &a, const float (&st)[13], float dd, 
     *g_ax = L_ax;
 }
 
-// Backward pass over checkpointed segments, one lane per candidate.
+// Backward pass over checkpointed segments; LANES lanes per candidate, the
+// wheels split over them as in the forward kernel.
 //   ckpt:    [nseg+1][13][K]: state at the start of each segment of C
 //            intervals (segment nseg: the final state)
 //   weight:  [K] dJ/dJ_k seeds (NULL = 1)
 //   cost:    [K] the forward costs (+inf rows get zero gradients)
-//   scratch: [C*S][14][K] recomputed states plus an executed flag
+//   scratch: [C*S][14][K] recomputed states plus an executed flag (every
+//            lane of a group writes and reads back the same values)
 //   grad:    [N][2][K] output dJ/du
+template <int LANES>
 __global__ __launch_bounds__(64) void adjoint_backward(const RolloutArgs a, int C,
                                                        const float *__restrict__ ckpt,
                                                        const float *__restrict__ weight,
                                                        float *__restrict__ scratch,
                                                        float *__restrict__ grad) {
-    const int k = blockIdx.x * 64 + threadIdx.x;
+    constexpr int WPL = 4 / LANES;
+    const int gtid = blockIdx.x * 64 + threadIdx.x;
+    const int sub = gtid & (LANES - 1);
+    const int k = gtid / LANES;
+    // whole lane groups past K leave together (64 is a multiple of LANES)
     if (k >= a.K) return;
     const size_t K = (size_t)a.K;
     const int N = a.N, S = a.S;
@@ -396,7 +473,8 @@ __global__ __launch_bounds__(64) void adjoint_backward(const RolloutArgs a, int 
     const float Jk = a.cost[k];
     const float *up = a.controls + k;
     if (!isfinite(Jk)) {
-        for (int e = 0; e < 2 * N; ++e) grad[(size_t)e * K + k] = 0.0f;
+        if (sub == 0)
+            for (int e = 0; e < 2 * N; ++e) grad[(size_t)e * K + k] = 0.0f;
         return;
     }
     // terminal cost Phi = w_g |(x, y) - goal| at the final state
@@ -413,9 +491,9 @@ __global__ __launch_bounds__(64) void adjoint_backward(const RolloutArgs a, int 
             lam[1] = wJ * a.w_g * gdy / dist;
         }
     }
-    Arm arms[4];
+    Arm arms[WPL];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) arms[q] = arm(a, q);
+    for (int q = 0; q < WPL; ++q) arms[q] = arm(a, sub * WPL + q);
 
     for (int seg = nseg - 1; seg >= 0; --seg) {
         const int n0 = seg * C;
@@ -436,7 +514,7 @@ __global__ __launch_bounds__(64) void adjoint_backward(const RolloutArgs a, int 
                 const float gdx = st[0] - a.goal_x, gdy = st[1] - a.goal_y;
                 const bool live = !(fmaf(gdx, gdx, gdy * gdy) <= a.goal_r2);
                 sl[(size_t)13 * K] = live ? 1.0f : 0.0f;
-                if (live) euler_step<1>(a, arms, st, Jdummy, dd, ax);
+                if (live) euler_step<LANES>(a, arms, st, Jdummy, dd, ax);
             }
         }
         // reverse through the segment
@@ -454,15 +532,17 @@ __global__ __launch_bounds__(64) void adjoint_backward(const RolloutArgs a, int 
 #pragma unroll
                 for (int q = 0; q < 13; ++q) sti[q] = sl[(size_t)q * K];
                 float g1, g2;
-                step_vjp(a, sti, dd, ax, wJ, lam, &g1, &g2);
+                step_vjp<LANES>(a, arms, sti, dd, ax, wJ, lam, &g1, &g2);
                 gdd += g1;
                 gax += g2;
             }
             // through the admissible-set clamps (identity branch inside)
             const bool in0 = !(u0 < -a.drate_max) && !(u0 > a.drate_max);
             const bool in1 = !(u1 < -1.0f) && !(u1 > 1.0f);
-            grad[(2 * (size_t)n) * K + k] = in0 ? gdd : 0.0f;
-            grad[(2 * (size_t)n + 1) * K + k] = in1 ? a.accel_max * gax : 0.0f;
+            if (sub == 0) {
+                grad[(2 * (size_t)n) * K + k] = in0 ? gdd : 0.0f;
+                grad[(2 * (size_t)n + 1) * K + k] = in1 ? a.accel_max * gax : 0.0f;
+            }
         }
     }
 }
@@ -470,10 +550,20 @@ __global__ __launch_bounds__(64) void adjoint_backward(const RolloutArgs a, int 
 }  // namespace
 
 hipError_t launch_adjoint_backward(const RolloutArgs &a, int C, const float *ckpt,
-                                   const float *weight, float *scratch, float *grad,
+                                   const float *weight, float *scratch, float *grad, int lanes,
                                    hipStream_t s) {
-    hipLaunchKernelGGL(adjoint_backward, dim3((a.K + 63) / 64), dim3(64), 0, s, a, C, ckpt, weight,
-                       scratch, grad);
+    const unsigned grid = (unsigned)(((long long)a.K * lanes + 63) / 64);
+    if (lanes == 1)
+        hipLaunchKernelGGL(adjoint_backward<1>, dim3(grid), dim3(64), 0, s, a, C, ckpt, weight,
+                           scratch, grad);
+    else if (lanes == 2)
+        hipLaunchKernelGGL(adjoint_backward<2>, dim3(grid), dim3(64), 0, s, a, C, ckpt, weight,
+                           scratch, grad);
+    else if (lanes == 4)
+        hipLaunchKernelGGL(adjoint_backward<4>, dim3(grid), dim3(64), 0, s, a, C, ckpt, weight,
+                           scratch, grad);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

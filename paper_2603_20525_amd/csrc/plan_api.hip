@@ -666,9 +666,8 @@ plan_status_t plan_rollout_grad(plan_ctx *c, const float state0[13], const float
     const int C = checkpoint_every < N ? checkpoint_every : N;
     const int nseg = (N + C - 1) / C;
     const size_t Kz = (size_t)K;
-    const size_t need = 13 * Kz                            // running state
-                        + (size_t)(nseg + 1) * 13 * Kz     // checkpoints
-                        + (size_t)C * c->integ.substeps * 14 * Kz;  // segment scratch
+    const size_t need = (size_t)(nseg + 1) * 13 * Kz                 // checkpoints
+                        + (size_t)C * c->integ.substeps * 14 * Kz;   // segment scratch
     HIP_TRY(c, hipSetDevice(c->device));
     if (need > c->gws_floats) {
         HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -682,34 +681,29 @@ plan_status_t plan_rollout_grad(plan_ctx *c, const float state0[13], const float
         }
         c->gws_floats = need;
     }
-    float *state = c->gws;
-    float *ckpt = state + 13 * Kz;
+    float *ckpt = c->gws;
     float *scratch = ckpt + (size_t)(nseg + 1) * 13 * Kz;
     RolloutArgs a;
     fill_args(c, a);
+    for (int q = 0; q < 13; ++q) a.s0[q] = state0[q];
     a.controls = controls_dev;
     a.K = K;
     a.N = N;
-    a.cost = cost_dev;
-    a.state = state;
-    HIP_TRY(c, plan::launch_init_state(state0, state, cost_dev, K, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(ckpt, state, sizeof(float) * 13 * Kz, hipMemcpyDeviceToDevice,
-                              c->stream));
-    // forward pass, one segment of C intervals at a time, checkpointing the
-    // state at every segment boundary
-    for (int seg = 0; seg < nseg; ++seg) {
-        a.n0 = seg * C;
-        a.n1 = (seg + 1) * C < N ? (seg + 1) * C : N;
-        a.finalize = a.n1 == N;
-        plan_status_t st = launch(c, a, Kind::chunk);
-        if (st != PLAN_OK) return st;
-        HIP_TRY(c, hipMemcpyAsync(ckpt + (size_t)(seg + 1) * 13 * Kz, state,
-                                  sizeof(float) * 13 * Kz, hipMemcpyDeviceToDevice, c->stream));
-    }
     a.n0 = 0;
     a.n1 = N;
     a.finalize = 1;
-    HIP_TRY(c, plan::launch_adjoint_backward(a, C, ckpt, weight_dev, scratch, grad_dev,
+    a.cost = cost_dev;
+    a.final_state = nullptr;
+    a.ckpt = ckpt;
+    a.ckpt_every = C;
+    // forward pass in one launch, storing the state at every C-th interval
+    int lanes, block;
+    auto_launch(K, &lanes, &block);
+    if (c->lanes_opt) lanes = c->lanes_opt;
+    if (c->block_opt) block = c->block_opt;
+    HIP_TRY(c, plan::launch_rollout_ckpt(a, lanes, block, c->stream));
+    // the backward kernel splits the wheels over the same lanes
+    HIP_TRY(c, plan::launch_adjoint_backward(a, C, ckpt, weight_dev, scratch, grad_dev, lanes,
                                              c->stream));
     return PLAN_OK;
 }

@@ -60,6 +60,10 @@ struct RolloutArgs {
     float *final_state;            // full: [13][K] or nullptr
     float *state;                  // chunk: [13][K], read and written
     SampleArgs smp;                // sampled launches: the candidate generator
+    // checkpointing launches (adjoint forward): ckpt [nseg+1][13][K] receives
+    // the state at intervals 0, C, 2C, ... and the final state
+    float *ckpt;
+    int ckpt_every;
     // fused argmin epilogue: packed-key slot (all ones between launches),
     // arrival ticket (zero between launches), plan [N][2], result copies
     unsigned long long *sel_key;
@@ -94,6 +98,10 @@ struct SlotList {
 // they continue from a.state / a.cost. Both run the same step code.
 hipError_t launch_rollout(const RolloutArgs &a, int lanes, int block, bool chunk, hipStream_t s);
 
+// Full-horizon rollout that also stores every candidate's state at each
+// checkpoint (a.ckpt, a.ckpt_every): the adjoint's forward pass in one launch.
+hipError_t launch_rollout_ckpt(const RolloutArgs &a, int lanes, int block, hipStream_t s);
+
 // Full-horizon rollout whose last workgroup to finish also selects the argmin
 // (a.sel_* and a.plan), with controls read (sampled = false) or drawn.
 hipError_t launch_rollout_argmin(const RolloutArgs &a, int lanes, int block, bool sampled,
@@ -114,8 +122,9 @@ hipError_t launch_rollout_est(const RolloutArgs &a, int block, hipStream_t s);
 hipError_t launch_rollout_slots(const RolloutArgs *slots, const TickTable &t, int lanes,
                                 int block, hipStream_t s);
 
+// lanes: 1, 2 or 4 lanes per candidate (wheels split as in the forward).
 hipError_t launch_adjoint_backward(const RolloutArgs &a, int C, const float *ckpt,
-                                   const float *weight, float *scratch, float *grad,
+                                   const float *weight, float *scratch, float *grad, int lanes,
                                    hipStream_t s);
 
 hipError_t launch_init_state(const float *s0, float *state, float *cost, int K, hipStream_t s);

@@ -36,7 +36,7 @@ namespace {
 // generator block per four intervals, kept in registers) instead of reading
 // a.controls. Lanes with store == false run a duplicate candidate only to
 // keep their lane group complete.
-template <int LANES, bool CHUNK, bool SAMPLED = false, bool RK4 = false>
+template <int LANES, bool CHUNK, bool SAMPLED = false, bool RK4 = false, bool CKPT = false>
 __device__ __forceinline__ float simulate(const RolloutArgs &a, int k, int sub, bool store) {
     constexpr int WPL = 4 / LANES;  // wheels per lane
     const size_t K = (size_t)a.K;
@@ -62,6 +62,18 @@ __device__ __forceinline__ float simulate(const RolloutArgs &a, int k, int sub, 
     Arm arms[WPL];
 #pragma unroll
     for (int q = 0; q < WPL; ++q) arms[q] = arm(a, sub * WPL + q);
+
+    // CKPT: ckpt[b] = state at interval min(b C, N), the 13 stores spread over
+    // the lane group; a candidate past its goal exit keeps its frozen state
+    int ckpt_done = 0;
+    auto write_ckpt = [&](int b) {
+        if (!store) return;
+        float *c = a.ckpt + (size_t)b * 13 * K + k;
+#pragma unroll
+        for (int q = 0; q < 13; ++q)
+            if ((q & (LANES - 1)) == sub) c[(size_t)q * K] = st[q];
+    };
+    if constexpr (CKPT) write_ckpt(0);
 
     for (int n = a.n0; n < a.n1 && !done; ++n) {
         // zero-order hold: control n for the whole interval, restricted to the
@@ -94,6 +106,16 @@ __device__ __forceinline__ float simulate(const RolloutArgs &a, int k, int sub, 
             else
                 euler_step<LANES>(a, arms, st, J, dd, ax);
         }
+        if constexpr (CKPT) {
+            if ((n + 1) % a.ckpt_every == 0 && n + 1 < a.N) {
+                ckpt_done = (n + 1) / a.ckpt_every;
+                write_ckpt(ckpt_done);
+            }
+        }
+    }
+    if constexpr (CKPT) {
+        const int nseg = (a.N + a.ckpt_every - 1) / a.ckpt_every;
+        for (int b = ckpt_done + 1; b <= nseg; ++b) write_ckpt(b);
     }
 
     if (a.finalize) {
@@ -158,7 +180,7 @@ __device__ __forceinline__ void argmin_epilogue(const RolloutArgs &a, unsigned l
 }
 
 template <int LANES, int BLOCK, bool CHUNK, bool SAMPLED = false, bool FUSED = false,
-          bool RK4 = false>
+          bool RK4 = false, bool CKPT = false>
 __global__ __launch_bounds__(BLOCK) void rollout_srb(const RolloutArgs a) {
     const int gtid = blockIdx.x * BLOCK + threadIdx.x;
     const int sub = gtid & (LANES - 1);
@@ -168,7 +190,7 @@ __global__ __launch_bounds__(BLOCK) void rollout_srb(const RolloutArgs a) {
     // is complete for the DPP sums; they store nothing (and reach the fused
     // epilogue's barriers like every other lane).
     if (!store) k = a.K - 1;
-    const float J = simulate<LANES, CHUNK, SAMPLED, RK4>(a, k, sub, store);
+    const float J = simulate<LANES, CHUNK, SAMPLED, RK4, CKPT>(a, k, sub, store);
     if constexpr (FUSED)
         argmin_epilogue<BLOCK, SAMPLED>(a, (store && sub == 0) ? cost_key(J, k) : ~0ull);
 }
@@ -264,6 +286,25 @@ hipError_t launch_rollout_sampled(const RolloutArgs &a, int lanes, int block, hi
     if (lanes == L && block == B) {                                                      \
         hipLaunchKernelGGL((rollout_srb<L, B, false, true>), dim3(grid), dim3(B), 0, s, a); \
         return hipGetLastError();                                                        \
+    }
+    PLAN_LAUNCH(1, 64)
+    PLAN_LAUNCH(2, 64)
+    PLAN_LAUNCH(4, 64)
+    PLAN_LAUNCH(1, 256)
+    PLAN_LAUNCH(2, 256)
+    PLAN_LAUNCH(4, 256)
+#undef PLAN_LAUNCH
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_rollout_ckpt(const RolloutArgs &a, int lanes, int block, hipStream_t s) {
+    const long long threads = (long long)a.K * lanes;
+    const unsigned grid = (unsigned)((threads + block - 1) / block);
+#define PLAN_LAUNCH(L, B)                                                                      \
+    if (lanes == L && block == B) {                                                            \
+        hipLaunchKernelGGL((rollout_srb<L, B, false, false, false, false, true>), dim3(grid),  \
+                           dim3(B), 0, s, a);                                                  \
+        return hipGetLastError();                                                              \
     }
     PLAN_LAUNCH(1, 64)
     PLAN_LAUNCH(2, 64)

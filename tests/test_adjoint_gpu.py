@@ -105,6 +105,21 @@ def test_checkpoint_interval_does_not_change_the_gradient():
         np.testing.assert_array_equal(g, ref[1])
 
 
+def test_lanes_per_candidate_do_not_change_the_gradient():
+    """The backward kernel splits each candidate's wheels over 1, 2 or 4 lanes
+    and sums their adjoints in the forward's fixed order: identical bits."""
+    w = inputs.c2(K=333)
+    pl, _ = setup(w)
+    pl.set_launch(1, 64)
+    ref = gpu_grad(pl, w, w.controls, ckpt=10)
+    for lanes in (2, 4):
+        pl.set_launch(lanes, 64)
+        J, g = gpu_grad(pl, w, w.controls, ckpt=10)
+        np.testing.assert_array_equal(J, ref[0])
+        np.testing.assert_array_equal(g, ref[1])
+    pl.set_launch(0, 0)
+
+
 def test_weights_scale_the_gradient_and_autograd_matches():
     from paper_2603_20525_amd.autograd import RolloutCost
     w = inputs.c1(K=32)
