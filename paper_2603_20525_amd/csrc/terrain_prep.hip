@@ -14,35 +14,55 @@
 namespace plan {
 namespace {
 
-constexpr int ROW_TILE = 256;  // outputs per workgroup in the row pass
-constexpr int COL_W = 32;      // columns per workgroup in the column pass
-constexpr int COL_T = 64;      // rows per workgroup in the column pass
+constexpr int ROW_OUT = 4;                      // outputs per thread, row pass
+constexpr int ROW_TILE = 256 * ROW_OUT;         // outputs per workgroup, row pass
+constexpr int COL_W = 32;                       // columns per workgroup, column pass
+constexpr int COL_RUN = 8;                      // consecutive rows per thread, column pass
+constexpr int COL_T = (256 / COL_W) * COL_RUN;  // rows per workgroup, column pass (64)
 
-// Row pass: tmp[j][i] = sum_k w[k] h[j][clamp(i + k - r)].
-__global__ __launch_bounds__(ROW_TILE) void smooth_rows(const float *__restrict__ h, int W, int H,
-                                                        const SmoothTaps taps,
-                                                        float *__restrict__ tmp) {
+// Row pass: tmp[j][i] = sum_k w[k] h[j][clamp(i + k - r)], k = 0 .. 2r in
+// order. Each thread produces ROW_OUT neighbouring outputs from one sliding
+// window of the LDS row tile.
+__global__ __launch_bounds__(256) void smooth_rows(const float *__restrict__ h, int W, int H,
+                                                   const SmoothTaps taps,
+                                                   float *__restrict__ tmp) {
     __shared__ float tile[ROW_TILE + 2 * MAX_SMOOTH_RADIUS];
     const int r = taps.r;
     const int j = blockIdx.y;
     const int i0 = blockIdx.x * ROW_TILE;
     const float *row = h + (size_t)j * W;
-    for (int q = threadIdx.x; q < ROW_TILE + 2 * r; q += ROW_TILE) {
+    for (int q = threadIdx.x; q < ROW_TILE + 2 * r; q += 256) {
         const int i = min(max(i0 + q - r, 0), W - 1);
         tile[q] = row[i];
     }
     __syncthreads();
-    const int i = i0 + threadIdx.x;
-    if (i >= W) return;
-    float acc = 0.0f;
-    for (int k = 0; k <= 2 * r; ++k) acc = fmaf(taps.w[k], tile[threadIdx.x + k], acc);
-    tmp[(size_t)j * W + i] = acc;
+    const int base = threadIdx.x * ROW_OUT;  // first output of this thread in the tile
+    float acc[ROW_OUT];
+#pragma unroll
+    for (int o = 0; o < ROW_OUT; ++o) acc[o] = 0.0f;
+    float win[ROW_OUT];
+#pragma unroll
+    for (int o = 0; o < ROW_OUT - 1; ++o) win[o + 1] = tile[base + o];
+    for (int k = 0; k <= 2 * r; ++k) {
+        // window = tile[base + k .. base + k + ROW_OUT - 1]
+#pragma unroll
+        for (int o = 0; o < ROW_OUT - 1; ++o) win[o] = win[o + 1];
+        win[ROW_OUT - 1] = tile[base + k + ROW_OUT - 1];
+        const float w = taps.w[k];
+#pragma unroll
+        for (int o = 0; o < ROW_OUT; ++o) acc[o] = fmaf(w, win[o], acc[o]);
+    }
+    float *dst = tmp + (size_t)j * W + i0 + base;
+#pragma unroll
+    for (int o = 0; o < ROW_OUT; ++o)
+        if (i0 + base + o < W) dst[o] = acc[o];
 }
 
 // Column pass: out[j][i] = sum_k w[k] tmp[clamp(j + k - r)][i]; a tile of
-// COL_T rows x COL_W columns plus the vertical halo is staged in LDS
-// (at most 318 x 32 floats, 40.7 KB). Thread t owns column t % 32 and rows
-// t / 32, t / 32 + 8, ...
+// COL_T rows x COL_W columns plus the vertical halo is staged in LDS (at most
+// 318 x 32 floats, 40.7 KB). Thread t owns column t % COL_W and the COL_RUN
+// consecutive rows starting at (t / COL_W) * COL_RUN, swept with a sliding
+// window of the column.
 __global__ __launch_bounds__(256) void smooth_cols(const float *__restrict__ tmp, int W, int H,
                                                    const SmoothTaps taps,
                                                    float *__restrict__ out) {
@@ -58,12 +78,25 @@ __global__ __launch_bounds__(256) void smooth_cols(const float *__restrict__ tmp
     }
     __syncthreads();
     if (i0 + c >= W) return;
-    for (int t = threadIdx.x / COL_W; t < COL_T; t += 256 / COL_W) {
-        const int j = j0 + t;
-        if (j >= H) break;
-        float acc = 0.0f;
-        for (int k = 0; k <= 2 * r; ++k) acc = fmaf(taps.w[k], tile[(t + k) * COL_W + c], acc);
-        out[(size_t)j * W + i0 + c] = acc;
+    const int t0 = (threadIdx.x / COL_W) * COL_RUN;  // first output row in the tile
+    float acc[COL_RUN];
+#pragma unroll
+    for (int o = 0; o < COL_RUN; ++o) acc[o] = 0.0f;
+    float win[COL_RUN];
+#pragma unroll
+    for (int o = 0; o < COL_RUN - 1; ++o) win[o + 1] = tile[(t0 + o) * COL_W + c];
+    for (int k = 0; k <= 2 * r; ++k) {
+#pragma unroll
+        for (int o = 0; o < COL_RUN - 1; ++o) win[o] = win[o + 1];
+        win[COL_RUN - 1] = tile[(t0 + k + COL_RUN - 1) * COL_W + c];
+        const float w = taps.w[k];
+#pragma unroll
+        for (int o = 0; o < COL_RUN; ++o) acc[o] = fmaf(w, win[o], acc[o]);
+    }
+#pragma unroll
+    for (int o = 0; o < COL_RUN; ++o) {
+        const int j = j0 + t0 + o;
+        if (j < H) out[(size_t)j * W + i0 + c] = acc[o];
     }
 }
 
@@ -117,8 +150,8 @@ __global__ __launch_bounds__(256) void costmap_polygons(const float2 *__restrict
 
 hipError_t launch_smooth(const float *h, int W, int H, const SmoothTaps &taps, float *tmp,
                          float *out, hipStream_t s) {
-    hipLaunchKernelGGL(smooth_rows, dim3((W + ROW_TILE - 1) / ROW_TILE, H), dim3(ROW_TILE), 0, s,
-                       h, W, H, taps, tmp);
+    hipLaunchKernelGGL(smooth_rows, dim3((W + ROW_TILE - 1) / ROW_TILE, H), dim3(256), 0, s, h, W,
+                       H, taps, tmp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(smooth_cols, dim3((W + COL_W - 1) / COL_W, (H + COL_T - 1) / COL_T),
