@@ -449,6 +449,7 @@ def main():
             "trace": "64 requests, Poisson arrivals at 200 req/s, K in {512,1024,2048,4096,8192}, "
                      "N in 40..160, dt 0.02 s, own 256x256 terrain and start each",
             "at_200_req_s": serving_leg(1.0),
+            "at_2000_req_s": serving_leg(0.1),
             "burst_all_at_once": serving_leg(0.0),
         }
     if args.rows:

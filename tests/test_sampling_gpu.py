@@ -207,3 +207,39 @@ def test_sampling_errors(c1big):
     lib = P.lib()
     assert lib.plan_sample_controls(c1big.planner.ctx, None, 8, 4,
                                     P.C.c_void_p(u.data_ptr())) == P.PLAN_EINVAL
+
+
+def test_paper_shape_full_size_one_launch_sampled_outputs():
+    """The paper's configuration at full size in the launch the bench times
+    (K = 204 288 candidates drawn in the kernel, 16 x 0.25 s at 50 Euler
+    substeps, argmin epilogue): sampled candidates' costs against the oracle's
+    own draws and rollouts, and the selection against the cost array."""
+    T = inputs.fbm_berm_terrain(2000)
+    w = inputs.paper_shape(K=8, terrain=T)
+    K, N = 204288, 16
+    pl = P.Planner(w.vehicle, w.cost, w.integ, K, N, T.W, T.H)
+    pl.set_terrain(dev(T.height), T.x0, T.y0, T.res)
+    spec = P.sample_spec(U, 6000, 0, (1.0, 0.0))
+    J = torch.empty(K, device="cuda")
+    fs = torch.empty(13, K, device="cuda")
+    plan = torch.empty(N, 2, device="cuda")
+    bk, bc = pl.rollout_sampled_argmin(w.state0, spec, N, J, plan, fs)
+    torch.cuda.synchronize()
+    Jg = J.cpu().numpy()
+    # selection: lowest index of the minimal finite cost, its controls regenerated
+    fin = np.isfinite(Jg)
+    assert bk == int(np.flatnonzero(Jg == Jg[fin].min())[0]) and bc == Jg[bk]
+    u_best = oracle.sample_controls(U, 6000, 0, [1.0, 0.0], K, N)[:, :, bk]
+    expect = np.stack([np.clip(u_best[:, 0], -1.0, 1.0), np.clip(u_best[:, 1], -1.0, 1.0)], 1)
+    assert np.array_equal(plan.cpu().numpy(), expect.astype(np.float32))
+    # sampled candidates, including the winner, against the oracle
+    idx = np.unique(np.concatenate([np.arange(0, K, 797), [bk]]))
+    u_all = oracle.sample_controls(U, 6000, 0, [1.0, 0.0], K, N).astype(np.float32)
+    u_s = np.ascontiguousarray(u_all[:, :, idx])
+    o = oracle.Oracle(w.vehicle, w.cost, w.integ)
+    o.set_terrain(T.height, T.x0, T.y0, T.res)
+    mc, ms, ex = assert_screened_parity(Jg[idx], fs.cpu().numpy()[:, idx], o, w.state0, u_s,
+                                        "paper shape full size, one launch")
+    print(f"paper shape K=204288 one launch: {len(idx)} sampled, costs within 1e-4 {mc:.1%}, "
+          f"states {ms:.1%}")
+    pl.close()
