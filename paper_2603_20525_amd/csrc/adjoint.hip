@@ -19,6 +19,8 @@
 // [C*S][14][M] scratch (13 state components plus an executed flag) and runs
 // the step adjoints in reverse. One lane per candidate (LANES = 1 step code,
 // the same arithmetic as the forward kernel).
+#include <type_traits>
+
 #include "plan_internal.h"
 #include "rollout_step.h"
 
@@ -79,10 +81,10 @@ __device__ __forceinline__ WheelAdj adj_group_sum(WheelAdj v) {
 // holds `arms`). In: lam = dJ/d(next state), wJ = dJ/d(running cost). Out:
 // lam = dJ/d(this state), *g_dd, *g_ax = dJ/d(dd), dJ/d(ax) through this
 // step; identical in every lane of the group.
-template <int LANES>
+template <int LANES, class Hook = NoHook>
 __device__ void step_vjp(const RolloutArgs &a, const Arm (&arms)[4 / LANES],
                          const float (&st)[13], float dd, float ax, float wJ, float (&lam)[13],
-                         float *g_dd, float *g_ax) {
+                         float *g_dd, float *g_ax, const Hook &hook = Hook()) {
     constexpr int WPL = 4 / LANES;
     const float h = a.h;
     const float half_pi = 1.57079632679489662f;
@@ -118,6 +120,15 @@ __device__ void step_vjp(const RolloutArgs &a, const Arm (&arms)[4 / LANES],
         chid[WPL];
     float Fkr[WPL], Fk[WPL], Fb[WPL], Fz[WPL], rr[WPL], alpha[WPL], Ca[WPL], qq[WPL], Fyv[WPL];
     bool guard[WPL], fb_first[WPL];
+    // texel requests of this lane's wheels first; the hook's loads are
+    // issued after them
+    Gather G[WPL];
+#pragma unroll
+    for (int i = 0; i < WPL; ++i) G[i] = gather(a, A, x, y, z, arms[i]);
+    if constexpr (!std::is_same<Hook, NoHook>::value) {
+        __builtin_amdgcn_sched_barrier(0);
+        hook();
+    }
 #pragma unroll
     for (int i = 0; i < WPL; ++i) {
         const Arm r = arms[i];
@@ -128,7 +139,7 @@ __device__ void step_vjp(const RolloutArgs &a, const Arm (&arms)[4 / LANES],
         const float vr = (P_y[i] - a.y0) * a.inv_res;
         cl_u[i] = (ur > 0.0f && ur < a.umax) ? 1.0f : 0.0f;  // NaN: clamped
         cl_v[i] = (vr > 0.0f && vr < a.vmax) ? 1.0f : 0.0f;
-        const Gather g = gather(a, A, x, y, z, r);
+        const Gather &g = G[i];
         txv[i] = g.tx;
         tyv[i] = g.ty;
         T00[i] = g.t00;
@@ -495,6 +506,10 @@ __global__ __launch_bounds__(64) void adjoint_backward(const RolloutArgs a, int 
 #pragma unroll
     for (int q = 0; q < WPL; ++q) arms[q] = arm(a, sub * WPL + q);
 
+    // Loads are issued one step ahead from inside the step (after its texel
+    // requests): the next interval's controls in the recomputation, the
+    // previous step's recomputed state and controls in the reverse sweep.
+    // Indices are clamped to the segment, so every load stays in bounds.
     for (int seg = nseg - 1; seg >= 0; --seg) {
         const int n0 = seg * C;
         const int n1 = min(N, n0 + C);
@@ -504,9 +519,11 @@ __global__ __launch_bounds__(64) void adjoint_backward(const RolloutArgs a, int 
         for (int q = 0; q < 13; ++q) st[q] = ckpt[((size_t)seg * 13 + q) * K + k];
         float Jdummy = 0.0f;
         int idx = 0;
+        float nu0 = up[(2 * (size_t)n0) * K], nu1 = up[(2 * (size_t)n0 + 1) * K];
         for (int n = n0; n < n1; ++n) {
-            const float dd = clampf_nan(up[(2 * (size_t)n) * K], -a.drate_max, a.drate_max);
-            const float ax = a.accel_max * clampf_nan(up[(2 * (size_t)n + 1) * K], -1.0f, 1.0f);
+            const float dd = clampf_nan(nu0, -a.drate_max, a.drate_max);
+            const float ax = a.accel_max * clampf_nan(nu1, -1.0f, 1.0f);
+            const size_t nn = (size_t)min(n + 1, n1 - 1);
             for (int s = 0; s < S; ++s, ++idx) {
                 float *sl = scratch + ((size_t)idx * 14) * K + k;
 #pragma unroll
@@ -514,35 +531,68 @@ __global__ __launch_bounds__(64) void adjoint_backward(const RolloutArgs a, int 
                 const float gdx = st[0] - a.goal_x, gdy = st[1] - a.goal_y;
                 const bool live = !(fmaf(gdx, gdx, gdy * gdy) <= a.goal_r2);
                 sl[(size_t)13 * K] = live ? 1.0f : 0.0f;
-                if (live) euler_step<LANES>(a, arms, st, Jdummy, dd, ax);
+                // a step that is not live leaves the state frozen, so no later
+                // step of this candidate is live and the stale controls are
+                // never applied
+                if (live)
+                    euler_step<LANES>(a, arms, st, Jdummy, dd, ax, [&]() {
+                        nu0 = up[(2 * nn) * K];
+                        nu1 = up[(2 * nn + 1) * K];
+                    });
             }
         }
-        // reverse through the segment
-        for (int n = n1 - 1; n >= n0; --n) {
-            const float u0 = up[(2 * (size_t)n) * K];
-            const float u1 = up[(2 * (size_t)n + 1) * K];
+        // reverse through the segment, one step at a time (flat index i)
+        const int cnt = (n1 - n0) * S;
+        float cur[14];
+        {
+            const float *sl = scratch + ((size_t)(cnt - 1) * 14) * K + k;
+#pragma unroll
+            for (int q = 0; q < 14; ++q) cur[q] = sl[(size_t)q * K];
+        }
+        float cu0 = up[(2 * (size_t)(n1 - 1)) * K], cu1 = up[(2 * (size_t)(n1 - 1) + 1) * K];
+        float gdd = 0.0f, gax = 0.0f;
+        for (int i = cnt - 1; i >= 0; --i) {
+            const int n = n0 + i / S;
+            const float u0 = cu0, u1 = cu1;
             const float dd = clampf_nan(u0, -a.drate_max, a.drate_max);
             const float ax = a.accel_max * clampf_nan(u1, -1.0f, 1.0f);
-            float gdd = 0.0f, gax = 0.0f;
-            for (int s = S - 1; s >= 0; --s) {
-                const int i = (n - n0) * S + s;
-                const float *sl = scratch + ((size_t)i * 14) * K + k;
-                if (sl[(size_t)13 * K] == 0.0f) continue;  // after the goal exit
+            const int ip = max(i - 1, 0);
+            const size_t np = (size_t)(n0 + ip / S);
+            const float *slp = scratch + ((size_t)ip * 14) * K + k;
+            float nxt[14], nu0, nu1;
+            auto prefetch = [&]() {
+#pragma unroll
+                for (int q = 0; q < 14; ++q) nxt[q] = slp[(size_t)q * K];
+                nu0 = up[(2 * np) * K];
+                nu1 = up[(2 * np + 1) * K];
+            };
+            if (cur[13] != 0.0f) {  // executed (not after the goal exit)
                 float sti[13];
 #pragma unroll
-                for (int q = 0; q < 13; ++q) sti[q] = sl[(size_t)q * K];
+                for (int q = 0; q < 13; ++q) sti[q] = cur[q];
                 float g1, g2;
-                step_vjp<LANES>(a, arms, sti, dd, ax, wJ, lam, &g1, &g2);
+                step_vjp<LANES>(a, arms, sti, dd, ax, wJ, lam, &g1, &g2, prefetch);
                 gdd += g1;
                 gax += g2;
+            } else {
+                prefetch();
             }
-            // through the admissible-set clamps (identity branch inside)
-            const bool in0 = !(u0 < -a.drate_max) && !(u0 > a.drate_max);
-            const bool in1 = !(u1 < -1.0f) && !(u1 > 1.0f);
-            if (sub == 0) {
-                grad[(2 * (size_t)n) * K + k] = in0 ? gdd : 0.0f;
-                grad[(2 * (size_t)n + 1) * K + k] = in1 ? a.accel_max * gax : 0.0f;
+            if (i == (n - n0) * S) {
+                // first substep of interval n: its gradient is complete;
+                // through the admissible-set clamps (identity branch inside)
+                const bool in0 = !(u0 < -a.drate_max) && !(u0 > a.drate_max);
+                const bool in1 = !(u1 < -1.0f) && !(u1 > 1.0f);
+                if (sub == 0) {
+                    grad[(2 * (size_t)n) * K + k] = in0 ? gdd : 0.0f;
+                    grad[(2 * (size_t)n + 1) * K + k] = in1 ? a.accel_max * gax : 0.0f;
+                }
+                gdd = 0.0f;
+                gax = 0.0f;
             }
+#pragma unroll
+            for (int q = 0; q < 14; ++q) cur[q] = nxt[q];
+            cu0 = nu0;
+            cu1 = nu1;
         }
     }
 }

@@ -41,7 +41,19 @@ __device__ __forceinline__ float simulate(const RolloutArgs &a, int k, int sub, 
     float (&st)[13] = st0;
     bool done = false;
 
+    // materialised controls are read one interval ahead (the index is clamped
+    // to [n0, n1)). The Euler step requests the next pair right after its
+    // texel gathers, so waiting for the texels does not wait for it and the
+    // load stays in flight for the rest of the step; RK4 requests it at the
+    // start of the interval.
     const float *up = a.controls + k;
+    float nu0 = 0.0f, nu1 = 0.0f;
+    if constexpr (!SAMPLED) {
+        if (a.n0 < a.n1) {
+            nu0 = up[(2 * (size_t)a.n0) * K];
+            nu1 = up[(2 * (size_t)a.n0 + 1) * K];
+        }
+    }
     PhiloxBlock blk{};
     int blk_n = -1;
 
@@ -72,8 +84,14 @@ __device__ __forceinline__ float simulate(const RolloutArgs &a, int k, int sub, 
             }
             draw_controls(a.smp, block_word(blk, n & 3), k, n, u0, u1);
         } else {
-            u0 = up[(2 * (size_t)n) * K];
-            u1 = up[(2 * (size_t)n + 1) * K];
+            u0 = nu0;
+            u1 = nu1;
+            if constexpr (RK4) {
+                if (n + 1 < a.n1) {
+                    nu0 = up[(2 * (size_t)n + 2) * K];
+                    nu1 = up[(2 * (size_t)n + 3) * K];
+                }
+            }
         }
         const float dd = clampf_nan(u0, -a.drate_max, a.drate_max);
         const float ax = a.accel_max * clampf_nan(u1, -1.0f, 1.0f);
@@ -87,10 +105,17 @@ __device__ __forceinline__ float simulate(const RolloutArgs &a, int k, int sub, 
                     break;
                 }
             }
-            if constexpr (RK4)
+            if constexpr (RK4) {
                 rk4_step<LANES>(a, arms, st, J, dd, ax);
-            else
+            } else if constexpr (SAMPLED) {
                 euler_step<LANES>(a, arms, st, J, dd, ax);
+            } else {
+                const size_t nn = (size_t)min(n + 1, a.n1 - 1);
+                euler_step<LANES>(a, arms, st, J, dd, ax, [&]() {
+                    nu0 = up[(2 * nn) * K];
+                    nu1 = up[(2 * nn + 1) * K];
+                });
+            }
         }
         if constexpr (CKPT) {
             if ((n + 1) % a.ckpt_every == 0 && n + 1 < a.N) {

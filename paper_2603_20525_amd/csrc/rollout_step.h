@@ -5,6 +5,8 @@
 // floating-point contraction and every fused multiply-add is an explicit fmaf.
 #pragma once
 
+#include <type_traits>
+
 #include "plan_internal.h"
 
 namespace plan {
@@ -196,13 +198,21 @@ __device__ __forceinline__ WheelOut wadd(const WheelOut &p, const WheelOut &q) {
     return WheelOut{p.Fy + q.Fy, p.Fz + q.Fz, p.Mx + q.Mx, p.My + q.My, p.Mz + q.Mz, p.c + q.c};
 }
 
+// Work a caller issues inside the step right after the texel gathers (a
+// load whose latency should overlap the rest of the step).
+struct NoHook {
+    __device__ __forceinline__ void operator()() const {}
+};
+
 // Right-hand side of the model for one candidate (this lane's wheels, group
 // sums over the candidate's lanes): xd receives the state derivative and the
-// return value is the running cost rate L at the state.
-template <int LANES>
+// return value is the running cost rate L at the state. A hook other than
+// NoHook runs after the gathers are issued, behind a scheduling barrier so
+// that its loads stay after them.
+template <int LANES, class Hook = NoHook>
 __device__ __forceinline__ float srb_rhs(const RolloutArgs &a, const Arm (&arms)[4 / LANES],
                                          const float (&st)[13], float dd, float ax,
-                                         float (&xd)[13]) {
+                                         float (&xd)[13], const Hook &hook = Hook()) {
     constexpr int WPL = 4 / LANES;  // wheels per lane
     const float half_pi = 1.57079632679489662f;
     float x = st[0], y = st[1], z = st[2];
@@ -216,6 +226,10 @@ __device__ __forceinline__ float srb_rhs(const RolloutArgs &a, const Arm (&arms)
     Gather G[WPL];
 #pragma unroll
     for (int q = 0; q < WPL; ++q) G[q] = gather(a, A, x, y, z, arms[q]);
+    if constexpr (!std::is_same<Hook, NoHook>::value) {
+        __builtin_amdgcn_sched_barrier(0);
+        hook();
+    }
 
     // kinematics: world velocity, Euler-angle rates, gravity in the
     // body frame, rear longitudinal constraint force
@@ -307,11 +321,12 @@ __device__ __forceinline__ void apply_limits(const RolloutArgs &a, float (&st)[1
 
 // One forward-Euler step (the paper's integrator): the running cost at the
 // node is added to J (left Riemann sum) and the state advanced in place.
-template <int LANES>
+template <int LANES, class Hook = NoHook>
 __device__ __forceinline__ void euler_step(const RolloutArgs &a, const Arm (&arms)[4 / LANES],
-                                           float (&st)[13], float &J, float dd, float ax) {
+                                           float (&st)[13], float &J, float dd, float ax,
+                                           const Hook &hook = Hook()) {
     float xd[13];
-    const float L = srb_rhs<LANES>(a, arms, st, dd, ax, xd);
+    const float L = srb_rhs<LANES>(a, arms, st, dd, ax, xd, hook);
     J = fmaf(a.h, L, J);
 #pragma unroll
     for (int q = 0; q < 13; ++q) st[q] = fmaf(a.h, xd[q], st[q]);
