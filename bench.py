@@ -40,7 +40,7 @@ ALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
 # by what the same counters read for a 256 MiB device copy (fetch x2.0,
 # write x1.0); profiles/rollout_srb_c2_hbm_counters.md has the commands. Valid
 # for the kernel as profiled; None for other workloads.
-C2_TRAFFIC_BYTES = (3749.94 * 262144.0 / 131084.4 + 32.91) * 1024
+C2_TRAFFIC_BYTES = (3750.93 * 262144.0 / 131084.6 + 32.91) * 1024
 
 
 def workload(name):
@@ -263,10 +263,11 @@ def serving_leg(scale=1.0, chunk=16, slots=64):
         return srv.submit(h, w.terrain.x0, w.terrain.y0, w.terrain.res, w.state0, u, w.cost,
                           w.integ, plan)
 
-    for item in R[:4]:  # warm both paths (code objects, first-touch)
+    for item in R:  # warm both paths (code objects, first-touch, every slot)
         plain_one(*item)
         submit(*item)
     srv.drain()
+    srv.completions(len(R))
     torch.cuda.synchronize()
     # plain path
     lat, done = [], []
@@ -284,22 +285,20 @@ def serving_leg(scale=1.0, chunk=16, slots=64):
     pl.close()
     # continuous batching
     ts0 = srv.now() + 0.01
-    ids, lat, done = {}, {}, []
+    index, lat, done = {}, {}, []
     i = 0
     while len(lat) < len(R):
         now = srv.now()
         while i < len(R) and ts0 + R[i][0].arrival * scale <= now:
-            ids[i] = submit(*R[i])
+            index[submit(*R[i])] = i
             i += 1
         srv.step()
-        for j, rid in ids.items():
-            if j in lat:
-                continue
+        for rid in srv.completions(len(R)):
+            j = index[rid]
             res = srv.result(rid)
-            if res["status"] != 0:
-                assert res["status"] == 1, res
-                lat[j] = res["t_done"] - (ts0 + R[j][0].arrival * scale)
-                done.append(res["t_done"])
+            assert res["status"] == 1, res
+            lat[j] = res["t_done"] - (ts0 + R[j][0].arrival * scale)
+            done.append(res["t_done"])
     serving = _summ(list(lat.values()), ts0, max(done), steps, len(R))
     srv.close()
     return {"plain": plain, "serving": serving}

@@ -101,6 +101,14 @@ plan_status_t plan_server_stats(const plan_server *s, int *active, int *queued,
 /* Copy the state of request id into *out. */
 plan_status_t plan_server_result(const plan_server *s, int id, plan_result_t *out);
 
+/* Completion queue: move up to capacity ids of requests that finished (done
+ * or failed) since the previous call into ids[], in the order the host
+ * observed them (plan_server_step and plan_server_drain observe them);
+ * *count receives how many were moved. Ids not moved stay queued for the
+ * next call. Errors: PLAN_EINVAL for NULL s or count, NULL ids with
+ * capacity > 0, or capacity < 0. */
+plan_status_t plan_server_completions(plan_server *s, int *ids, int capacity, int *count);
+
 /* Seconds on the server's monotonic clock (the clock of the timestamps). */
 double plan_server_now(const plan_server *s);
 

@@ -76,6 +76,33 @@ struct RolloutArgs {
 // intervals, and which blocks of the launch belong to each slot.
 constexpr int MAX_TICK_SLOTS = 128;
 
+// Texel (i, j) of the packed terrain: height, slopes by central differences
+// (one-sided on the border) and the costmap's rate. Returns false if the
+// node's height or cost is not finite.
+__device__ __forceinline__ bool pack_texel(const float *__restrict__ hgt,
+                                           const float *__restrict__ cm, int W, int H,
+                                           float inv_res, int i, int j,
+                                           float4 *__restrict__ tex) {
+    const size_t q = (size_t)j * W + i;
+    const float hc = hgt[q];
+    float fx, fy;
+    if (i == 0)
+        fx = (hgt[q + 1] - hc) * inv_res;
+    else if (i == W - 1)
+        fx = (hc - hgt[q - 1]) * inv_res;
+    else
+        fx = (hgt[q + 1] - hgt[q - 1]) * (0.5f * inv_res);
+    if (j == 0)
+        fy = (hgt[q + W] - hc) * inv_res;
+    else if (j == H - 1)
+        fy = (hc - hgt[q - W]) * inv_res;
+    else
+        fy = (hgt[q + W] - hgt[q - W]) * (0.5f * inv_res);
+    const float cc = cm ? cm[q] : 0.0f;
+    tex[q] = make_float4(hc, fx, fy, cc);
+    return isfinite(hc) && isfinite(cc);
+}
+
 struct TickEntry {
     int slot;
     int block_start;
@@ -132,7 +159,7 @@ hipError_t launch_init_state(const float *s0, float *state, float *cost, int K, 
 hipError_t launch_pack_terrain(const float *h, const float *c, int W, int H, float inv_res,
                                float4 *tex, int *bad, hipStream_t s);
 
-hipError_t launch_select_slots(const RolloutArgs *slots, float *const *plans, const int *bad,
+hipError_t launch_select_slots(const RolloutArgs *slots, float *const *plans, int *bad,
                                SelectOut *out, SelectOut *out_host, const SlotList &l,
                                hipStream_t s);
 

@@ -30,24 +30,7 @@ __global__ __launch_bounds__(256) void pack_terrain(const float *__restrict__ hg
     const int i = blockIdx.x * 16 + (threadIdx.x & 15);
     const int j = blockIdx.y * 16 + (threadIdx.x >> 4);
     if (i >= W || j >= H) return;
-    const size_t q = (size_t)j * W + i;
-    const float hc = hgt[q];
-    float fx, fy;
-    if (i == 0)
-        fx = (hgt[q + 1] - hc) * inv_res;
-    else if (i == W - 1)
-        fx = (hc - hgt[q - 1]) * inv_res;
-    else
-        fx = (hgt[q + 1] - hgt[q - 1]) * (0.5f * inv_res);
-    if (j == 0)
-        fy = (hgt[q + W] - hc) * inv_res;
-    else if (j == H - 1)
-        fy = (hc - hgt[q - W]) * inv_res;
-    else
-        fy = (hgt[q + W] - hgt[q - W]) * (0.5f * inv_res);
-    const float cc = cm ? cm[q] : 0.0f;
-    if (!isfinite(hc) || !isfinite(cc)) atomicOr(bad, 1);
-    tex[q] = make_float4(hc, fx, fy, cc);
+    if (!pack_texel(hgt, cm, W, H, inv_res, i, j, tex)) atomicOr(bad, 1);
 }
 
 // ---------------------------------------------------------------- argmin ----
@@ -200,7 +183,7 @@ constexpr int SLOT_SEL_BLOCK = 1024;
 
 __global__ __launch_bounds__(SLOT_SEL_BLOCK) void select_slots(
     const RolloutArgs *__restrict__ slots, float *const *__restrict__ plans,
-    const int *__restrict__ bad, SelectOut *__restrict__ out, SelectOut *out_host,
+    int *__restrict__ bad, SelectOut *__restrict__ out, SelectOut *out_host,
     const SlotList l) {
     __shared__ unsigned long long red[SLOT_SEL_BLOCK / 64];
     __shared__ unsigned long long best_sh;
@@ -224,6 +207,7 @@ __global__ __launch_bounds__(SLOT_SEL_BLOCK) void select_slots(
         o.best_k = (m == ~0ull) ? -1 : (int)(unsigned int)(m & 0xffffffffu);
         o.best_cost = (m == ~0ull) ? __builtin_inff() : key_cost(m);
         o.pad[0] = bad[s] ? (uint32_t)(int32_t)PLAN_EINVAL : 0u;
+        bad[s] = 0;  // the slot's next request starts with a clear flag
         o.pad[1] = 0;
         out[s] = o;
         out_host[s] = o;  // pinned ring entry the host polls
@@ -238,7 +222,7 @@ __global__ __launch_bounds__(SLOT_SEL_BLOCK) void select_slots(
 
 }  // namespace
 
-hipError_t launch_select_slots(const RolloutArgs *slots, float *const *plans, const int *bad,
+hipError_t launch_select_slots(const RolloutArgs *slots, float *const *plans, int *bad,
                                SelectOut *out, SelectOut *out_host, const SlotList &l,
                                hipStream_t s) {
     if (l.count < 1) return hipSuccess;

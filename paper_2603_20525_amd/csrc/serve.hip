@@ -31,24 +31,43 @@ namespace {
 constexpr int RING = 4;          // pinned result buffers (> steps in flight)
 constexpr int MAX_INFLIGHT = 2;  // steps the host may run ahead of the GPU
 
-// Admission of one request into a slot: its launch arguments (passed by value,
-// so no host staging buffer can change under a pending copy), its plan
-// pointer, a cleared terrain flag, and every candidate's initial state with
-// zero running cost.
-__global__ __launch_bounds__(256) void admit_slot(RolloutArgs args, int slot,
-                                                  RolloutArgs *__restrict__ slot_args,
-                                                  float *plan, float **__restrict__ plans,
-                                                  int *__restrict__ bad) {
-    const int k = blockIdx.x * 256 + threadIdx.x;
-    if (k == 0) {
-        slot_args[slot] = args;
-        plans[slot] = plan;
-        bad[slot] = 0;
+// One request admitted in this step: its launch arguments (state and cost
+// pointing at its slot's blocks), plan pointer and terrain.
+struct AdmitEntry {
+    RolloutArgs args;
+    const float *height;
+    const float *costmap;
+    float *plan;
+    float4 *tex;
+    int slot, W, H;
+    float inv_res;
+};
+
+// Admission of every request a step admits, in one launch: blockIdx.y picks
+// the request; thread t writes candidate t's initial state and zero running
+// cost and packs texel t of its terrain; thread 0 publishes the launch
+// arguments and plan pointer. The slot's bad-terrain flag was cleared by the
+// select that finished its previous request (or at server creation).
+__global__ __launch_bounds__(256) void admit_batch(const AdmitEntry *__restrict__ ents,
+                                                   RolloutArgs *__restrict__ slot_args,
+                                                   float **__restrict__ plans,
+                                                   int *__restrict__ bad) {
+    const AdmitEntry &e = ents[blockIdx.y];
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t == 0) {
+        slot_args[e.slot] = e.args;
+        plans[e.slot] = e.plan;
     }
-    if (k < args.K) {
+    const int K = e.args.K;
+    if (t < K) {
 #pragma unroll
-        for (int q = 0; q < 13; ++q) args.state[(size_t)q * args.K + k] = args.s0[q];
-        args.cost[k] = 0.0f;
+        for (int q = 0; q < 13; ++q) e.args.state[(size_t)q * K + t] = e.args.s0[q];
+        e.args.cost[t] = 0.0f;
+    }
+    if (t < e.W * e.H) {
+        const int i = t % e.W, j = t / e.W;
+        if (!plan::pack_texel(e.height, e.costmap, e.W, e.H, e.inv_res, i, j, e.tex))
+            atomicOr(bad + e.slot, 1);
     }
 }
 
@@ -88,11 +107,16 @@ struct plan_server {
     SelectOut *sel = nullptr;
     SelectOut *ring_host[RING] = {};
     int ring_next = 0;
+    // admission staging: pinned entries per ring position (reused only after
+    // the step that copied them has completed) and their device copy
+    AdmitEntry *admit_host[RING] = {};
+    AdmitEntry *admit_dev = nullptr;
     // host bookkeeping
     std::vector<Req> reqs;
     std::deque<int> queue;
     std::vector<Slot> slots;
     std::deque<Step> inflight;
+    std::deque<int> completed;  // finished request ids not yet collected
     std::vector<hipEvent_t> ev_pool;
     std::string err;
 };
@@ -136,8 +160,11 @@ static void server_release(plan_server *s) {
     (void)hipFree(s->plans);
     (void)hipFree(s->bad);
     (void)hipFree(s->sel);
-    for (int i = 0; i < RING; ++i)
+    (void)hipFree(s->admit_dev);
+    for (int i = 0; i < RING; ++i) {
         if (s->ring_host[i]) (void)hipHostFree(s->ring_host[i]);
+        if (s->admit_host[i]) (void)hipHostFree(s->admit_host[i]);
+    }
     for (auto &st : s->inflight) (void)hipEventDestroy(st.ev);
     for (auto e : s->ev_pool) (void)hipEventDestroy(e);
 }
@@ -155,6 +182,7 @@ static void retire_front(plan_server *s) {
         q.res.best_cost = o.best_cost;
         q.res.status = o.pad[0] ? (int)(int32_t)o.pad[0] : 1;
         q.res.t_done = t;
+        s->completed.push_back(fr.second);
     }
     s->ev_pool.push_back(st.ev);
 }
@@ -177,7 +205,14 @@ static plan_status_t poll(plan_server *s, bool block_until_below) {
     return PLAN_OK;
 }
 
+// Admit queued requests (FIFO) while a slot is free and the byte budget
+// allows. The step's admissions go out as one staging copy and one launch;
+// the staging entries belong to the ring position of the step about to be
+// launched, whose event covers the copy.
 static plan_status_t admit(plan_server *s) {
+    AdmitEntry *stage = s->admit_host[s->ring_next];
+    int count = 0;
+    long long extent = 0;
     while (!s->queue.empty()) {
         const int id = s->queue.front();
         Req &q = s->reqs[id];
@@ -191,9 +226,11 @@ static plan_status_t admit(plan_server *s) {
         if (slot < 0) break;
         s->queue.pop_front();
         const plan_request_t &r = q.r;
-        float4 *tex = s->tex + (size_t)slot * s->max_W * s->max_H;
-        RolloutArgs a;
-        plan::fill_rollout_args(a, s->veh, r.cost, r.integ, tex, r.W, r.H, r.x0, r.y0, r.res);
+        AdmitEntry &e = stage[count++];
+        memset(&e, 0, sizeof e);
+        e.tex = s->tex + (size_t)slot * s->max_W * s->max_H;
+        RolloutArgs &a = e.args;
+        plan::fill_rollout_args(a, s->veh, r.cost, r.integ, e.tex, r.W, r.H, r.x0, r.y0, r.res);
         for (int j = 0; j < 13; ++j) a.s0[j] = r.state0[j];
         a.controls = r.controls_dev;
         a.K = r.K;
@@ -201,17 +238,28 @@ static plan_status_t admit(plan_server *s) {
         a.state = s->state + (size_t)slot * 13 * s->max_K;
         a.cost = s->cost + (size_t)slot * s->max_K;
         a.final_state = nullptr;
-        hipLaunchKernelGGL(admit_slot, dim3((r.K + 255) / 256), dim3(256), 0, s->stream, a, slot,
-                           s->slot_args, r.plan_dev, s->plans, s->bad);
-        SHIP(s, hipGetLastError());
-        SHIP(s, plan::launch_pack_terrain(r.height_dev, r.costmap_dev, r.W, r.H, 1.0f / r.res, tex,
-                                          s->bad + slot, s->stream));
+        e.height = r.height_dev;
+        e.costmap = r.costmap_dev;
+        e.plan = r.plan_dev;
+        e.slot = slot;
+        e.W = r.W;
+        e.H = r.H;
+        e.inv_res = 1.0f / r.res;
+        const long long work = (long long)r.W * r.H > r.K ? (long long)r.W * r.H : r.K;
+        extent = work > extent ? work : extent;
         s->slots[slot].req = id;
         s->slots[slot].progress = 0;
         s->used += q.footprint;
         q.res.slot = slot;
         q.res.t_admit = now_of(s);
     }
+    if (count == 0) return PLAN_OK;
+    SHIP(s, hipMemcpyAsync(s->admit_dev, stage, sizeof(AdmitEntry) * count,
+                           hipMemcpyHostToDevice, s->stream));
+    const dim3 grid((unsigned)((extent + 255) / 256), (unsigned)count);
+    hipLaunchKernelGGL(admit_batch, grid, dim3(256), 0, s->stream, s->admit_dev, s->slot_args,
+                       s->plans, s->bad);
+    SHIP(s, hipGetLastError());
     return PLAN_OK;
 }
 
@@ -315,8 +363,12 @@ plan_status_t plan_server_create(plan_server **out, const plan_vehicle_t *veh, i
     if (e == hipSuccess) e = hipMalloc(&s->plans, sizeof(float *) * S);
     if (e == hipSuccess) e = hipMalloc(&s->bad, sizeof(int) * S);
     if (e == hipSuccess) e = hipMalloc(&s->sel, sizeof(SelectOut) * S);
+    if (e == hipSuccess) e = hipMalloc(&s->admit_dev, sizeof(AdmitEntry) * S);
     for (int i = 0; i < RING && e == hipSuccess; ++i)
         e = hipHostMalloc(&s->ring_host[i], sizeof(SelectOut) * S, hipHostMallocDefault);
+    for (int i = 0; i < RING && e == hipSuccess; ++i)
+        e = hipHostMalloc(&s->admit_host[i], sizeof(AdmitEntry) * S, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMemset(s->bad, 0, sizeof(int) * S);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         shipfail(nullptr, "plan_server_create", e);
@@ -399,6 +451,19 @@ plan_status_t plan_server_drain(plan_server *s) {
             return PLAN_OK;
         }
     }
+}
+
+plan_status_t plan_server_completions(plan_server *s, int *ids, int capacity, int *count) {
+    if (!s) return PLAN_EINVAL;
+    if (!count || capacity < 0 || (!ids && capacity > 0))
+        return sfail(s, PLAN_EINVAL, "invalid completion buffer");
+    int n = 0;
+    while (n < capacity && !s->completed.empty()) {
+        ids[n++] = s->completed.front();
+        s->completed.pop_front();
+    }
+    *count = n;
+    return PLAN_OK;
 }
 
 plan_status_t plan_server_stats(const plan_server *s, int *active, int *queued,

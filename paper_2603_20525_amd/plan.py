@@ -470,8 +470,9 @@ class Result(C.Structure):
 
 
 SERVER_EXPORTS = ("plan_server_create", "plan_server_submit", "plan_server_step",
-                  "plan_server_drain", "plan_server_stats", "plan_server_result", "plan_server_now",
-                  "plan_server_destroy", "plan_server_last_error")
+                  "plan_server_drain", "plan_server_stats", "plan_server_result",
+                  "plan_server_completions", "plan_server_now", "plan_server_destroy",
+                  "plan_server_last_error")
 
 _server_bound = False
 
@@ -488,6 +489,7 @@ def _bind_server():
         L.plan_server_drain.argtypes = [vp]
         L.plan_server_result.argtypes = [vp, C.c_int, C.POINTER(Result)]
         L.plan_server_stats.argtypes = [vp, ip, ip, C.POINTER(C.c_ulonglong)]
+        L.plan_server_completions.argtypes = [vp, ip, C.c_int, ip]
         L.plan_server_now.argtypes = [vp]
         L.plan_server_now.restype = C.c_double
         L.plan_server_destroy.argtypes = [vp]
@@ -495,7 +497,8 @@ def _bind_server():
         L.plan_server_last_error.argtypes = [vp]
         L.plan_server_last_error.restype = C.c_char_p
         for n in ("plan_server_create", "plan_server_submit", "plan_server_step",
-                  "plan_server_drain", "plan_server_stats", "plan_server_result"):
+                  "plan_server_drain", "plan_server_stats", "plan_server_result",
+                  "plan_server_completions"):
             getattr(L, n).restype = C.c_int
         _server_bound = True
     return L
@@ -564,6 +567,15 @@ class Server:
         if out["status"] != 0:
             self._keep.pop(rid, None)
         return out
+
+    def completions(self, capacity=128) -> list:
+        """Ids of requests finished since the previous call, in the order
+        the host observed them."""
+        buf = (C.c_int * capacity)()
+        n = C.c_int(0)
+        _scheck("plan_server_completions", _bind_server().plan_server_completions(
+            self.h, buf, capacity, C.byref(n)), self.h)
+        return list(buf[:n.value])
 
     def now(self) -> float:
         return _bind_server().plan_server_now(self.h)

@@ -101,6 +101,8 @@ def test_server_create_and_submit_reject_invalid_arguments(lib):
     assert lib.plan_server_submit(None, None, C.byref(rid)) == P.PLAN_EINVAL
     assert lib.plan_server_step(None, None, None) == P.PLAN_EINVAL
     assert lib.plan_server_drain(None) == P.PLAN_EINVAL
+    n = C.c_int(-1)
+    assert lib.plan_server_completions(None, None, 0, C.byref(n)) == P.PLAN_EINVAL
     lib.plan_server_destroy(None)
 
 

@@ -159,6 +159,40 @@ def test_bad_terrain_request_fails_alone(trace):
     srv.close()
 
 
+def test_bad_terrain_flag_cleared_for_next_request(trace):
+    # one slot: the request after the bad one reuses its slot, and must not
+    # inherit the non-finite-terrain flag
+    srv = _server(trace, slots=1)
+    bad = trace[1]
+    h = bad.w.terrain.height.copy()
+    h[3, 7] = np.inf
+    T = bad.w.terrain
+    id_bad = srv.submit(dev(h), T.x0, T.y0, T.res, bad.w.state0, bad.u, bad.w.cost,
+                        bad.w.integ, bad.plan)
+    ids = [r.submit(srv) for r in trace[2:4]]
+    srv.drain()
+    assert srv.result(id_bad)["status"] == P.PLAN_EINVAL
+    assert srv.result(id_bad)["slot"] == srv.result(ids[0])["slot"] == 0
+    _check(srv, trace[2:4], ids)
+    srv.close()
+
+
+def test_completion_queue(trace):
+    srv = _server(trace, slots=4)
+    ids = [r.submit(srv) for r in trace[:6]]
+    assert srv.completions() == []
+    srv.drain()
+    first = srv.completions(capacity=4)
+    rest = srv.completions()
+    assert len(first) == 4 and sorted(first + rest) == sorted(ids)
+    assert srv.completions() == []
+    # in the order observed: non-decreasing completion times
+    t = [srv.result(i)["t_done"] for i in first + rest]
+    assert t == sorted(t)
+    _check(srv, trace[:6], ids)
+    srv.close()
+
+
 def test_submit_validation(trace):
     srv = _server(trace)
     r = trace[0]
