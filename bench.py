@@ -89,9 +89,26 @@ def cpu_baseline(w, seconds):
         el = time.perf_counter() - t0
         if el >= seconds or runs >= 1000:
             break
-    return {"value": steps_per_run * runs / el, "unit": "rollout-steps/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{sample} repeated {runs}x in {el:.1f} s (FP64 C, OpenMP over candidates)"}
+    out = {"value": steps_per_run * runs / el, "unit": "rollout-steps/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"{sample} repeated {runs}x in {el:.1f} s (FP64 C, OpenMP over candidates)"}
+    # the same oracle on one core (OpenMP team of one; a quarter of the time budget)
+    import ctypes
+    gomp = ctypes.CDLL("libgomp.so.1")
+    gomp.omp_set_num_threads(1)
+    try:
+        runs1, t1 = 0, time.perf_counter()
+        while True:
+            o.rollout(w.state0, u)
+            runs1 += 1
+            el1 = time.perf_counter() - t1
+            if el1 >= seconds / 4 or runs1 >= 1000:
+                break
+    finally:
+        gomp.omp_set_num_threads(threads)
+    out["single_thread"] = {"value": steps_per_run * runs1 / el1, "cores": 1,
+                            "sample": f"{sample} repeated {runs1}x in {el1:.1f} s"}
+    return out
 
 
 def _summ(lat, t_first, t_last, steps, n):
