@@ -8,8 +8,9 @@
  * interface batches them: every admitted request occupies a device-resident
  * slot (its terrain texels, candidate states and running costs stay in HBM
  * between launches); each scheduling step launches ONE rollout kernel that
- * advances the candidates of every active slot by a few control intervals,
- * then selects the plans of the slots that finished. Requests arriving while
+ * advances the candidates of every active slot by a few control intervals
+ * and, in the same launch, selects the plans of the slots that finish.
+ * Requests arriving while
  * others run join at the next step, as slots and the memory budget allow.
  * Each request's result is bit-identical to plan_rollout + plan_select on the
  * same inputs (same kernels, same arithmetic).

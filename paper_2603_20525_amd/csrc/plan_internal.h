@@ -72,10 +72,6 @@ struct RolloutArgs {
     SelectOut *sel_out, *sel_out_host;
 };
 
-// One tick of the serving loop: which slots advance through which control
-// intervals, and which blocks of the launch belong to each slot.
-constexpr int MAX_TICK_SLOTS = 128;
-
 // Texel (i, j) of the packed terrain: height, slopes by central differences
 // (one-sided on the border) and the costmap's rate. Returns false if the
 // node's height or cost is not finite.
@@ -103,6 +99,10 @@ __device__ __forceinline__ bool pack_texel(const float *__restrict__ hgt,
     return isfinite(hc) && isfinite(cc);
 }
 
+// One tick of the serving loop: which slots advance through which control
+// intervals, and which blocks of the launch belong to each slot.
+constexpr int MAX_TICK_SLOTS = 128;
+
 struct TickEntry {
     int slot;
     int block_start;
@@ -114,11 +114,6 @@ struct TickTable {
     int count;
     int total_blocks;
     TickEntry e[MAX_TICK_SLOTS];
-};
-
-struct SlotList {
-    int count;
-    int slot[MAX_TICK_SLOTS];
 };
 
 // chunk = false: candidates start from s0 with zero cost. chunk = true:
@@ -146,8 +141,11 @@ hipError_t launch_sample_controls(const SampleArgs &sa, int K, int N, float *con
 // delta, v_x): full horizon from a.s0[0..6]; a.final_state is [7][K].
 hipError_t launch_rollout_est(const RolloutArgs &a, int block, hipStream_t s);
 
-hipError_t launch_rollout_slots(const RolloutArgs *slots, const TickTable &t, int lanes,
-                                int block, hipStream_t s);
+// Slots whose entry finalizes also select their plan in the same launch
+// (fused argmin per slot): result and status to ring[slot], plan to the slot's
+// plan buffer; bad[slot] (non-finite terrain) is reported and cleared.
+hipError_t launch_rollout_slots(const RolloutArgs *slots, const TickTable &t, int *bad,
+                                SelectOut *ring, int lanes, int block, hipStream_t s);
 
 // lanes: 1, 2 or 4 lanes per candidate (wheels split as in the forward).
 hipError_t launch_adjoint_backward(const RolloutArgs &a, int C, const float *ckpt,
@@ -158,10 +156,6 @@ hipError_t launch_init_state(const float *s0, float *state, float *cost, int K, 
 
 hipError_t launch_pack_terrain(const float *h, const float *c, int W, int H, float inv_res,
                                float4 *tex, int *bad, hipStream_t s);
-
-hipError_t launch_select_slots(const RolloutArgs *slots, float *const *plans, int *bad,
-                               SelectOut *out, SelectOut *out_host, const SlotList &l,
-                               hipStream_t s);
 
 // Terrain preparation. Gaussian taps w[0 .. 2r] (normalised, FP32) of the
 // separable level-of-detail kernel; r <= MAX_SMOOTH_RADIUS.

@@ -155,11 +155,15 @@ __device__ __forceinline__ float simulate(const RolloutArgs &a, int k, int sub, 
 
 // Fused argmin: every workgroup reduces its candidates' packed keys and
 // folds the result into a.sel_key with an atomic minimum (order-independent,
-// so the winner is the same as the separate selection kernel's); the last
-// workgroup to arrive publishes (k*, J*), writes the plan and resets the key
-// and the ticket for the next launch.
+// so the winner is the same as the separate selection kernel's); the last of
+// the nblocks workgroups to arrive publishes (k*, J*) to a.sel_out and
+// out_host, writes the plan and resets the key and the ticket for the next
+// launch. bad (optional) is a flag to report in the result's status and
+// clear.
 template <int BLOCK, bool SAMPLED>
-__device__ __forceinline__ void argmin_epilogue(const RolloutArgs &a, unsigned long long key) {
+__device__ __forceinline__ void argmin_epilogue(const RolloutArgs &a, unsigned long long key,
+                                                unsigned int nblocks, SelectOut *out_host,
+                                                int *bad) {
     __shared__ unsigned long long red[BLOCK / 64];
     __shared__ int last_sh;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -170,7 +174,7 @@ __device__ __forceinline__ void argmin_epilogue(const RolloutArgs &a, unsigned l
         unsigned long long b = red[0];
 #pragma unroll
         for (int q = 1; q < BLOCK / 64; ++q) b = red[q] < b ? red[q] : b;
-        last_sh = fold_key_and_take_ticket(a.sel_key, a.sel_ticket, b, gridDim.x);
+        last_sh = fold_key_and_take_ticket(a.sel_key, a.sel_ticket, b, nblocks);
     }
     __syncthreads();
     if (!last_sh) return;
@@ -180,9 +184,11 @@ __device__ __forceinline__ void argmin_epilogue(const RolloutArgs &a, unsigned l
         SelectOut o;
         o.best_k = (m == ~0ull) ? -1 : (int)(unsigned int)(m & 0xffffffffu);
         o.best_cost = (m == ~0ull) ? __builtin_inff() : key_cost(m);
-        o.pad[0] = o.pad[1] = 0;
+        o.pad[0] = (bad && *bad) ? (uint32_t)(int32_t)PLAN_EINVAL : 0u;
+        o.pad[1] = 0;
+        if (bad) *bad = 0;  // the slot's next request starts with a clear flag
         *a.sel_out = o;
-        if (a.sel_out_host) *a.sel_out_host = o;
+        if (out_host) *out_host = o;
     }
     __syncthreads();
     const unsigned long long m = red[0];
@@ -203,16 +209,21 @@ __global__ __launch_bounds__(BLOCK) void rollout_srb(const RolloutArgs a) {
     if (!store) k = a.K - 1;
     const float J = simulate<LANES, CHUNK, SAMPLED, RK4, CKPT>(a, k, sub, store);
     if constexpr (FUSED)
-        argmin_epilogue<BLOCK, SAMPLED>(a, (store && sub == 0) ? cost_key(J, k) : ~0ull);
+        argmin_epilogue<BLOCK, SAMPLED>(a, (store && sub == 0) ? cost_key(J, k) : ~0ull,
+                                        gridDim.x, a.sel_out_host, nullptr);
 }
 
 // Several independent plans in one launch (the serving loop's tick). Entry e
 // of the table owns blocks [e.block_start, next block_start) and advances
 // slot e.slot through intervals [e.n0, e.n1); every block belongs to exactly
-// one slot, so the per-slot arguments are wave-uniform.
+// one slot, so the per-slot arguments are wave-uniform. An entry that ends
+// its request's horizon also selects the request's plan: the entry's blocks
+// run the fused argmin epilogue on the slot's own key and ticket, and the
+// last of them writes the result to ring[slot] and the plan.
 template <int LANES, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void rollout_slots(const RolloutArgs *__restrict__ slots,
-                                                       const TickTable t) {
+                                                       const TickTable t, int *bad,
+                                                       SelectOut *ring) {
     int lo = 0, hi = t.count - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -222,6 +233,7 @@ __global__ __launch_bounds__(BLOCK) void rollout_slots(const RolloutArgs *__rest
             hi = mid - 1;
     }
     const TickEntry te = t.e[lo];
+    const int block_end = lo + 1 < t.count ? t.e[lo + 1].block_start : t.total_blocks;
     RolloutArgs a = slots[te.slot];
     a.n0 = te.n0;
     a.n1 = te.n1;
@@ -231,7 +243,11 @@ __global__ __launch_bounds__(BLOCK) void rollout_slots(const RolloutArgs *__rest
     int k = gtid / LANES;
     const bool store = k < a.K;
     if (!store) k = a.K - 1;
-    simulate<LANES, true>(a, k, sub, store);
+    const float J = simulate<LANES, true>(a, k, sub, store);
+    if (te.finalize)
+        argmin_epilogue<BLOCK, false>(a, (store && sub == 0) ? cost_key(J, k) : ~0ull,
+                                      (unsigned int)(block_end - te.block_start),
+                                      ring + te.slot, bad + te.slot);
 }
 
 // Launch dispatch for one lane count L (block 64 or 256).
@@ -305,12 +321,15 @@ __forceinline__ hipError_t launch_argmin_lanes(const RolloutArgs &a, int block, 
 
 template <int L>
 __forceinline__ hipError_t launch_slots_lanes(const RolloutArgs *slots, const TickTable &t,
-                                              int block, hipStream_t s) {
+                                              int *bad, SelectOut *ring, int block,
+                                              hipStream_t s) {
     const unsigned grid = (unsigned)t.total_blocks;
     if (block == 64)
-        hipLaunchKernelGGL((rollout_slots<L, 64>), dim3(grid), dim3(64), 0, s, slots, t);
+        hipLaunchKernelGGL((rollout_slots<L, 64>), dim3(grid), dim3(64), 0, s, slots, t, bad,
+                           ring);
     else if (block == 256)
-        hipLaunchKernelGGL((rollout_slots<L, 256>), dim3(grid), dim3(256), 0, s, slots, t);
+        hipLaunchKernelGGL((rollout_slots<L, 256>), dim3(grid), dim3(256), 0, s, slots, t, bad,
+                           ring);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -325,7 +344,7 @@ hipError_t launch_sampled_multi(const RolloutArgs &a, int lanes, int block, hipS
 hipError_t launch_ckpt_multi(const RolloutArgs &a, int lanes, int block, hipStream_t s);
 hipError_t launch_argmin_multi(const RolloutArgs &a, int lanes, int block, bool sampled,
                                hipStream_t s);
-hipError_t launch_slots_multi(const RolloutArgs *slots, const TickTable &t, int lanes, int block,
-                              hipStream_t s);
+hipError_t launch_slots_multi(const RolloutArgs *slots, const TickTable &t, int *bad,
+                              SelectOut *ring, int lanes, int block, hipStream_t s);
 
 }  // namespace plan

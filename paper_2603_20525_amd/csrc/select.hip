@@ -177,59 +177,7 @@ __global__ __launch_bounds__(SEL_BLOCK) void select_softmin(
     if (tid == 0) *ticket = 0u;
 }
 
-// Argmin and plan gather for the slots that finished in a serving tick: one
-// block per slot, any K (strided), same keys and tie rule as select_argmin.
-constexpr int SLOT_SEL_BLOCK = 1024;
-
-__global__ __launch_bounds__(SLOT_SEL_BLOCK) void select_slots(
-    const RolloutArgs *__restrict__ slots, float *const *__restrict__ plans,
-    int *__restrict__ bad, SelectOut *__restrict__ out, SelectOut *out_host,
-    const SlotList l) {
-    __shared__ unsigned long long red[SLOT_SEL_BLOCK / 64];
-    __shared__ unsigned long long best_sh;
-    const int s = l.slot[blockIdx.x];
-    const RolloutArgs &a = slots[s];
-    const int K = a.K, N = a.N;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    unsigned long long key = ~0ull;
-    for (int k = tid; k < K; k += SLOT_SEL_BLOCK) {
-        const unsigned long long kk = cost_key(a.cost[k], k);
-        key = kk < key ? kk : key;
-    }
-    key = wave_min(key);
-    if (lane == 0) red[wv] = key;
-    __syncthreads();
-    if (tid == 0) {
-        unsigned long long m = red[0];
-        for (int q = 1; q < SLOT_SEL_BLOCK / 64; ++q) m = red[q] < m ? red[q] : m;
-        best_sh = m;
-        SelectOut o;
-        o.best_k = (m == ~0ull) ? -1 : (int)(unsigned int)(m & 0xffffffffu);
-        o.best_cost = (m == ~0ull) ? __builtin_inff() : key_cost(m);
-        o.pad[0] = bad[s] ? (uint32_t)(int32_t)PLAN_EINVAL : 0u;
-        bad[s] = 0;  // the slot's next request starts with a clear flag
-        o.pad[1] = 0;
-        out[s] = o;
-        out_host[s] = o;  // pinned ring entry the host polls
-    }
-    __syncthreads();
-    const unsigned long long m = best_sh;
-    const int kb = (m == ~0ull) ? -1 : (int)(unsigned int)(m & 0xffffffffu);
-    float *plan = plans[s];
-    for (int e = tid; e < 2 * N; e += SLOT_SEL_BLOCK)
-        plan[e] = (kb < 0) ? 0.0f : clamp_ctrl(a.controls[(size_t)e * K + kb], e, a.drate_max);
-}
-
 }  // namespace
-
-hipError_t launch_select_slots(const RolloutArgs *slots, float *const *plans, int *bad,
-                               SelectOut *out, SelectOut *out_host, const SlotList &l,
-                               hipStream_t s) {
-    if (l.count < 1) return hipSuccess;
-    hipLaunchKernelGGL(select_slots, dim3(l.count), dim3(SLOT_SEL_BLOCK), 0, s, slots, plans, bad,
-                       out, out_host, l);
-    return hipGetLastError();
-}
 
 int select_blocks(int K) { return (K + SEL_CHUNK - 1) / SEL_CHUNK; }
 int softmin_chunks(int K) { return (K + SM_CHUNK - 1) / SM_CHUNK; }

@@ -4,8 +4,9 @@
 // and a [max_K] running-cost block for the whole life of the server; a
 // request's controls and plan output stay in the caller's buffers. A step
 // launches one rollout over all resident requests (rollout_slots: each
-// workgroup belongs to one slot, so per-slot arguments are wave-uniform),
-// then one select over the requests that finished in it. The host runs at
+// workgroup belongs to one slot, so per-slot arguments are wave-uniform);
+// the requests that end in it select their plans in the same launch (fused
+// per-slot argmin). The host runs at
 // most two steps ahead of the GPU and learns of finished requests through
 // one event per step; per-step result copies go to their own pinned buffer so
 // nothing is overwritten before it is read.
@@ -37,7 +38,6 @@ struct AdmitEntry {
     RolloutArgs args;
     const float *height;
     const float *costmap;
-    float *plan;
     float4 *tex;
     int slot, W, H;
     float inv_res;
@@ -46,18 +46,14 @@ struct AdmitEntry {
 // Admission of every request a step admits, in one launch: blockIdx.y picks
 // the request; thread t writes candidate t's initial state and zero running
 // cost and packs texel t of its terrain; thread 0 publishes the launch
-// arguments and plan pointer. The slot's bad-terrain flag was cleared by the
-// select that finished its previous request (or at server creation).
+// arguments. The slot's bad-terrain flag was cleared by the rollout that
+// finished its previous request (or at server creation).
 __global__ __launch_bounds__(256) void admit_batch(const AdmitEntry *__restrict__ ents,
                                                    RolloutArgs *__restrict__ slot_args,
-                                                   float **__restrict__ plans,
                                                    int *__restrict__ bad) {
     const AdmitEntry &e = ents[blockIdx.y];
     const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t == 0) {
-        slot_args[e.slot] = e.args;
-        plans[e.slot] = e.plan;
-    }
+    if (t == 0) slot_args[e.slot] = e.args;
     const int K = e.args.K;
     if (t < K) {
 #pragma unroll
@@ -102,9 +98,10 @@ struct plan_server {
     float *state = nullptr;
     float *cost = nullptr;
     RolloutArgs *slot_args = nullptr;
-    float **plans = nullptr;
     int *bad = nullptr;
     SelectOut *sel = nullptr;
+    unsigned long long *sel_key = nullptr;  // per-slot argmin key (all ones between uses)
+    unsigned int *sel_ticket = nullptr;     // per-slot arrival ticket (zero between uses)
     SelectOut *ring_host[RING] = {};
     int ring_next = 0;
     // admission staging: pinned entries per ring position (reused only after
@@ -157,7 +154,8 @@ static void server_release(plan_server *s) {
     (void)hipFree(s->state);
     (void)hipFree(s->cost);
     (void)hipFree(s->slot_args);
-    (void)hipFree(s->plans);
+    (void)hipFree(s->sel_key);
+    (void)hipFree(s->sel_ticket);
     (void)hipFree(s->bad);
     (void)hipFree(s->sel);
     (void)hipFree(s->admit_dev);
@@ -238,9 +236,13 @@ static plan_status_t admit(plan_server *s) {
         a.state = s->state + (size_t)slot * 13 * s->max_K;
         a.cost = s->cost + (size_t)slot * s->max_K;
         a.final_state = nullptr;
+        a.sel_key = s->sel_key + slot;
+        a.sel_ticket = s->sel_ticket + slot;
+        a.plan = r.plan_dev;
+        a.sel_out = s->sel + slot;
+        a.sel_out_host = nullptr;  // the step's ring entry, passed at launch
         e.height = r.height_dev;
         e.costmap = r.costmap_dev;
-        e.plan = r.plan_dev;
         e.slot = slot;
         e.W = r.W;
         e.H = r.H;
@@ -258,7 +260,7 @@ static plan_status_t admit(plan_server *s) {
                            hipMemcpyHostToDevice, s->stream));
     const dim3 grid((unsigned)((extent + 255) / 256), (unsigned)count);
     hipLaunchKernelGGL(admit_batch, grid, dim3(256), 0, s->stream, s->admit_dev, s->slot_args,
-                       s->plans, s->bad);
+                       s->bad);
     SHIP(s, hipGetLastError());
     return PLAN_OK;
 }
@@ -266,8 +268,6 @@ static plan_status_t admit(plan_server *s) {
 static plan_status_t launch_step(plan_server *s) {
     plan::TickTable t;
     memset(&t, 0, sizeof t);
-    plan::SlotList fin;
-    memset(&fin, 0, sizeof fin);
     long long total_K = 0;
     for (int i = 0; i < s->max_slots; ++i)
         if (s->slots[i].req >= 0) total_K += s->reqs[s->slots[i].req].r.K;
@@ -290,19 +290,15 @@ static plan_status_t launch_step(plan_server *s) {
         e.n1 = sl.progress + slice < r.N ? sl.progress + slice : r.N;
         e.finalize = e.n1 == r.N;
         blocks += (int)(((long long)r.K * lanes + block - 1) / block);
-        if (e.finalize) {
-            fin.slot[fin.count++] = i;
-            st.finished.emplace_back(i, sl.req);
-        }
+        if (e.finalize) st.finished.emplace_back(i, sl.req);
     }
     t.total_blocks = blocks;
-    SHIP(s, plan::launch_rollout_slots(s->slot_args, t, lanes, block, s->stream));
+    // the requests that end in this launch select their plans in it and
+    // write their results into this step's pinned ring entry
     st.ring = s->ring_next;
     s->ring_next = (s->ring_next + 1) % RING;
-    if (fin.count) {
-        SHIP(s, plan::launch_select_slots(s->slot_args, s->plans, s->bad, s->sel,
-                                          s->ring_host[st.ring], fin, s->stream));
-    }
+    SHIP(s, plan::launch_rollout_slots(s->slot_args, t, s->bad, s->ring_host[st.ring], lanes,
+                                       block, s->stream));
     if (s->ev_pool.empty()) {
         hipEvent_t e;
         SHIP(s, hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -360,7 +356,10 @@ plan_status_t plan_server_create(plan_server **out, const plan_vehicle_t *veh, i
     if (e == hipSuccess) e = hipMalloc(&s->state, sizeof(float) * S * 13 * max_K);
     if (e == hipSuccess) e = hipMalloc(&s->cost, sizeof(float) * S * max_K);
     if (e == hipSuccess) e = hipMalloc(&s->slot_args, sizeof(RolloutArgs) * S);
-    if (e == hipSuccess) e = hipMalloc(&s->plans, sizeof(float *) * S);
+    if (e == hipSuccess) e = hipMalloc(&s->sel_key, sizeof(unsigned long long) * S);
+    if (e == hipSuccess) e = hipMalloc(&s->sel_ticket, sizeof(unsigned int) * S);
+    if (e == hipSuccess) e = hipMemset(s->sel_key, 0xFF, sizeof(unsigned long long) * S);
+    if (e == hipSuccess) e = hipMemset(s->sel_ticket, 0, sizeof(unsigned int) * S);
     if (e == hipSuccess) e = hipMalloc(&s->bad, sizeof(int) * S);
     if (e == hipSuccess) e = hipMalloc(&s->sel, sizeof(SelectOut) * S);
     if (e == hipSuccess) e = hipMalloc(&s->admit_dev, sizeof(AdmitEntry) * S);
