@@ -32,8 +32,9 @@ namespace {
 constexpr int RING = 4;          // pinned result buffers (> steps in flight)
 constexpr int MAX_INFLIGHT = 2;  // steps the host may run ahead of the GPU
 
-// One request admitted in this step: its launch arguments (state and cost
-// pointing at its slot's blocks), plan pointer and terrain.
+// One request admitted in this step: its launch arguments (state, cost and
+// argmin key and ticket pointing at its slot's storage; the caller's plan
+// buffer) and its terrain.
 struct AdmitEntry {
     RolloutArgs args;
     const float *height;
