@@ -29,6 +29,7 @@ __global__ __launch_bounds__(256) void smooth_rows(const float *__restrict__ h, 
     __shared__ float tile[ROW_TILE + 2 * MAX_SMOOTH_RADIUS];
     const int r = taps.r;
     const int j = blockIdx.y;
+    if (j >= H) return;  // whole workgroup (grid rows = H)
     const int i0 = blockIdx.x * ROW_TILE;
     const float *row = h + (size_t)j * W;
     for (int q = threadIdx.x; q < ROW_TILE + 2 * r; q += 256) {
