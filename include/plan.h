@@ -259,7 +259,11 @@ plan_status_t plan_init_state(plan_ctx *ctx, const float state0[13], float *stat
  * If no cost is finite, best_k = -1, best_cost = +inf, plan_dev is zeroed and
  * the status is still PLAN_OK.
  * best_k and best_cost are host pointers; if either is non-NULL the call
- * synchronises the stream to fill them. Pass both NULL to stay asynchronous.
+ * waits until the kernel has published them into pinned host memory (it
+ * polls that memory briefly, then synchronises the stream). The device
+ * outputs (plan_dev) are ordered on the context's stream like every other
+ * launch: read them through that stream, or synchronise it first. Pass both
+ * NULL to stay asynchronous.
  * Errors: PLAN_EINVAL (NULL ctx/controls/cost/plan, K or N out of range, bad
  * mode, lambda <= 0 for SOFTMIN); PLAN_EDEVICE. */
 plan_status_t plan_select(plan_ctx *ctx, int mode, float lambda,

@@ -5,6 +5,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <atomic>
+#include <chrono>
 #include <new>
 #include <string>
 
@@ -41,6 +43,7 @@ struct plan_ctx {
     float *wpart = nullptr;
     SelectOut *sel_dev = nullptr;
     SelectOut *sel_host = nullptr;  // pinned
+    uint32_t seq = 0;               // sequence number of the last published selection
     // launch shape
     int lanes_opt = 0, block_opt = 0;
     int last_lanes = 0, last_block = 0;
@@ -269,6 +272,7 @@ plan_status_t plan_create(plan_ctx **out, const plan_vehicle_t *veh, const plan_
     CREATE_TRY(hipMalloc(&c->wpart, sizeof(float) * wsz));
     CREATE_TRY(hipMalloc(&c->sel_dev, sizeof(SelectOut)));
     CREATE_TRY(hipHostMalloc(&c->sel_host, sizeof(SelectOut), hipHostMallocDefault));
+    memset(c->sel_host, 0, sizeof(SelectOut));  // no sequence number matches 0
     CREATE_TRY(hipEventCreate(&c->ev0));
     CREATE_TRY(hipEventCreate(&c->ev1));
     CREATE_TRY(hipDeviceSynchronize());
@@ -428,6 +432,57 @@ plan_status_t plan_rollout_sampled(plan_ctx *c, const float state0[13], const pl
     return launch(c, a, Kind::sampled);
 }
 
+// Sequence number for the next selection whose host copy is read: unique
+// in the process (until it wraps) and never 0, so neither a zeroed record nor
+// one left in recycled pinned memory by another context can match.
+static std::atomic<uint32_t> g_seq{0};
+
+static uint32_t next_seq(plan_ctx *c) {
+    uint32_t s = g_seq.fetch_add(1u, std::memory_order_relaxed) + 1u;
+    if (s == 0u) s = g_seq.fetch_add(1u, std::memory_order_relaxed) + 1u;
+    c->seq = s;
+    return s;
+}
+
+// Wait for the pinned copy of (k*, J*) published by selection `seq`: poll the
+// two 8-byte words that carry it (each also holds seq) for up to about a
+// millisecond, then fall back to a stream synchronisation, which also reports
+// a failed launch. Polling returns as soon as the result lands in host memory,
+// a few microseconds before the stream would report completion; the kernel
+// may still be writing the plan then, and device outputs stay ordered on the
+// context's stream.
+static plan_status_t wait_result(plan_ctx *c, uint32_t seq, int *best_k, float *best_cost) {
+    const uint64_t *w = reinterpret_cast<const uint64_t *>(c->sel_host);
+    uint64_t w0 = 0, w1 = 0;
+    bool seen = false;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (unsigned i = 1;; ++i) {
+        w0 = __atomic_load_n(&w[0], __ATOMIC_ACQUIRE);
+        w1 = __atomic_load_n(&w[1], __ATOMIC_ACQUIRE);
+        if ((uint32_t)(w0 >> 32) == seq && (uint32_t)(w1 >> 32) == seq) {
+            seen = true;
+            break;
+        }
+        if ((i & 1023u) == 0u &&
+            std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(1000))
+            break;
+        __builtin_ia32_pause();
+    }
+    if (!seen) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        w0 = __atomic_load_n(&w[0], __ATOMIC_ACQUIRE);
+        w1 = __atomic_load_n(&w[1], __ATOMIC_ACQUIRE);
+        if ((uint32_t)(w0 >> 32) != seq || (uint32_t)(w1 >> 32) != seq)
+            return fail(c, PLAN_EDEVICE, "selection result was not published");
+    }
+    if (best_k) *best_k = (int)(uint32_t)w0;
+    if (best_cost) {
+        const uint32_t bits = (uint32_t)w1;
+        memcpy(best_cost, &bits, sizeof bits);
+    }
+    return PLAN_OK;
+}
+
 plan_status_t plan_select_sampled(plan_ctx *c, const plan_sample_t *spec, const float *cost_dev,
                                   int K, int N, int *best_k, float *best_cost, float *plan_dev) {
     if (!c) return PLAN_EINVAL;
@@ -439,15 +494,11 @@ plan_status_t plan_select_sampled(plan_ctx *c, const plan_sample_t *spec, const 
     if (st != PLAN_OK) return st;
     HIP_TRY(c, hipSetDevice(c->device));
     const bool want = best_k || best_cost;
+    const uint32_t seq = want ? next_seq(c) : 0u;
     HIP_TRY(c, plan::launch_select_sampled(sa, cost_dev, K, N, c->veh.delta_rate_max, plan_dev,
                                            c->part_keys, c->counters, c->sel_dev,
-                                           want ? c->sel_host : nullptr, c->stream));
-    if (want) {
-        HIP_TRY(c, hipStreamSynchronize(c->stream));
-        if (best_k) *best_k = c->sel_host->best_k;
-        if (best_cost) *best_cost = c->sel_host->best_cost;
-    }
-    return PLAN_OK;
+                                           want ? c->sel_host : nullptr, seq, c->stream));
+    return want ? wait_result(c, seq, best_k, best_cost) : PLAN_OK;
 }
 
 plan_status_t plan_rollout_est(plan_ctx *c, const float state0[7], const float *controls_dev,
@@ -492,12 +543,10 @@ static plan_status_t fused_launch(plan_ctx *c, RolloutArgs &a, bool sampled, flo
     a.plan = plan_dev;
     a.sel_out = c->sel_dev;
     a.sel_out_host = want ? c->sel_host : nullptr;
+    a.sel_seq = want ? next_seq(c) : 0u;
     plan_status_t st = launch(c, a, sampled ? Kind::fused_sampled : Kind::fused);
     if (st != PLAN_OK || !want) return st;
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    if (best_k) *best_k = c->sel_host->best_k;
-    if (best_cost) *best_cost = c->sel_host->best_cost;
-    return PLAN_OK;
+    return wait_result(c, a.sel_seq, best_k, best_cost);
 }
 
 plan_status_t plan_rollout_argmin(plan_ctx *c, const float state0[13], const float *controls_dev,
@@ -720,16 +769,12 @@ plan_status_t plan_select(plan_ctx *c, int mode, float lambda, const float *cont
         return fail(c, PLAN_EINVAL, "softmin needs a finite lambda > 0");
     HIP_TRY(c, hipSetDevice(c->device));
     const bool want = best_k || best_cost;
+    const uint32_t seq = want ? next_seq(c) : 0u;
     HIP_TRY(c, plan::launch_select(mode, lambda, controls_dev, cost_dev, K, N,
                                    c->veh.delta_rate_max, plan_dev, c->part_keys, c->counters,
-                                   c->wpart, c->sel_dev, want ? c->sel_host : nullptr,
+                                   c->wpart, c->sel_dev, want ? c->sel_host : nullptr, seq,
                                    c->stream));
-    if (want) {
-        HIP_TRY(c, hipStreamSynchronize(c->stream));
-        if (best_k) *best_k = c->sel_host->best_k;
-        if (best_cost) *best_cost = c->sel_host->best_cost;
-    }
-    return PLAN_OK;
+    return want ? wait_result(c, seq, best_k, best_cost) : PLAN_OK;
 }
 
 plan_status_t plan_set_launch(plan_ctx *c, int lanes, int block) {

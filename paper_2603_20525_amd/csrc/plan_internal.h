@@ -10,9 +10,16 @@
 namespace plan {
 
 struct SelectOut {
+    // (k*, J*) of a selection. Each of the first two 8-byte words also holds
+    // the sequence number of the call that produced it, so a host polling
+    // the pinned copy knows both halves are that call's (a naturally aligned
+    // 8-byte store is never torn).
     int best_k;
+    uint32_t seq_k;
     float best_cost;
-    uint32_t pad[2];  // pad[0]: status of the request (0 or a plan_status_t)
+    uint32_t seq_cost;
+    int32_t status;  // serving: 0, or the plan_status_t of the request
+    uint32_t pad[3];
 };
 
 // Everything one rollout needs, passed by value as the kernel argument
@@ -70,6 +77,7 @@ struct RolloutArgs {
     unsigned int *sel_ticket;
     float *plan;
     SelectOut *sel_out, *sel_out_host;
+    uint32_t sel_seq;  // sequence number published with the host copy
 };
 
 // Texel (i, j) of the packed terrain: height, slopes by central differences
@@ -192,13 +200,15 @@ int softmin_row_groups(int N);
 hipError_t launch_select(int mode, float lambda, const float *controls, const float *cost,
                          int K, int N, float drate_max, float *plan_out,
                          unsigned long long *part_keys, unsigned int *counters,
-                         float *wpart, SelectOut *out, SelectOut *out_host, hipStream_t s);
+                         float *wpart, SelectOut *out, SelectOut *out_host, uint32_t seq,
+                         hipStream_t s);
 
 // Argmin whose plan is the winner's sequence regenerated from the sampler.
 hipError_t launch_select_sampled(const SampleArgs &sa, const float *cost, int K, int N,
                                  float drate_max, float *plan_out,
                                  unsigned long long *part_keys, unsigned int *counters,
-                                 SelectOut *out, SelectOut *out_host, hipStream_t s);
+                                 SelectOut *out, SelectOut *out_host, uint32_t seq,
+                                 hipStream_t s);
 
 // Host helpers shared by the plan and server entry points.
 void fill_rollout_args(RolloutArgs &a, const plan_vehicle_t &v, const plan_cost_t &co,

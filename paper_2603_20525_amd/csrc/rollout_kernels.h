@@ -181,14 +181,9 @@ __device__ __forceinline__ void argmin_epilogue(const RolloutArgs &a, unsigned l
     if (tid == 0) {
         const unsigned long long m = take_key_and_reset(a.sel_key, a.sel_ticket);
         red[0] = m;
-        SelectOut o;
-        o.best_k = (m == ~0ull) ? -1 : (int)(unsigned int)(m & 0xffffffffu);
-        o.best_cost = (m == ~0ull) ? __builtin_inff() : key_cost(m);
-        o.pad[0] = (bad && *bad) ? (uint32_t)(int32_t)PLAN_EINVAL : 0u;
-        o.pad[1] = 0;
+        const int32_t status = (bad && *bad) ? (int32_t)PLAN_EINVAL : 0;
         if (bad) *bad = 0;  // the slot's next request starts with a clear flag
-        *a.sel_out = o;
-        if (out_host) *out_host = o;
+        publish_result(a.sel_out, out_host, m, a.sel_seq, status);
     }
     __syncthreads();
     const unsigned long long m = red[0];

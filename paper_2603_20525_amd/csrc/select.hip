@@ -54,7 +54,7 @@ __global__ __launch_bounds__(SEL_BLOCK) void select_argmin(
     const float *__restrict__ cost, int K, const float *__restrict__ controls, int N,
     float drate_max, int gather, float *__restrict__ plan,
     unsigned long long *__restrict__ part, unsigned int *__restrict__ ticket,
-    SelectOut *__restrict__ out, SelectOut *out_host, const SampleArgs smp) {
+    SelectOut *__restrict__ out, SelectOut *out_host, uint32_t seq, const SampleArgs smp) {
     __shared__ unsigned long long red[SEL_BLOCK / 64];
     __shared__ int last_sh;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -81,17 +81,8 @@ __global__ __launch_bounds__(SEL_BLOCK) void select_argmin(
     if (tid == 0) {
         const unsigned long long m = take_key_and_reset(part, ticket);
         red[0] = m;
-        SelectOut o;
-        if (m == ~0ull) {
-            o.best_k = -1;
-            o.best_cost = __builtin_inff();
-        } else {
-            o.best_k = (int)(unsigned int)(m & 0xffffffffu);
-            o.best_cost = key_cost(m);
-        }
-        o.pad[0] = o.pad[1] = 0;
-        *out = o;
-        if (out_host) *out_host = o;  // pinned host copy: no readback copy needed
+        // pinned host copy: no readback copy needed
+        publish_result(out, out_host, m, seq, 0);
     }
     __syncthreads();
     if (gather) {
@@ -193,11 +184,11 @@ hipError_t launch_pack_terrain(const float *h, const float *c, int W, int H, flo
 hipError_t launch_select(int mode, float lambda, const float *controls, const float *cost,
                          int K, int N, float drate_max, float *plan_out,
                          unsigned long long *part_keys, unsigned int *counters, float *wpart,
-                         SelectOut *out, SelectOut *out_host, hipStream_t s) {
+                         SelectOut *out, SelectOut *out_host, uint32_t seq, hipStream_t s) {
     const int nb = select_blocks(K);
     hipLaunchKernelGGL(select_argmin<false>, dim3(nb), dim3(SEL_BLOCK), 0, s, cost, K, controls,
                        N, drate_max, mode == 0 ? 1 : 0, plan_out, part_keys, counters + 0, out,
-                       out_host, SampleArgs{});
+                       out_host, seq, SampleArgs{});
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || mode == 0) return e;
     dim3 grid(softmin_chunks(K), softmin_row_groups(N));
@@ -210,10 +201,11 @@ hipError_t launch_select(int mode, float lambda, const float *controls, const fl
 hipError_t launch_select_sampled(const SampleArgs &sa, const float *cost, int K, int N,
                                  float drate_max, float *plan_out,
                                  unsigned long long *part_keys, unsigned int *counters,
-                                 SelectOut *out, SelectOut *out_host, hipStream_t s) {
+                                 SelectOut *out, SelectOut *out_host, uint32_t seq,
+                                 hipStream_t s) {
     const int nb = select_blocks(K);
     hipLaunchKernelGGL(select_argmin<true>, dim3(nb), dim3(SEL_BLOCK), 0, s, cost, K, nullptr, N,
-                       drate_max, 1, plan_out, part_keys, counters + 0, out, out_host, sa);
+                       drate_max, 1, plan_out, part_keys, counters + 0, out, out_host, seq, sa);
     return hipGetLastError();
 }
 

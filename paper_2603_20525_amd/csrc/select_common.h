@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "plan_internal.h"
 #include "sample.h"
 
 namespace plan {
@@ -35,6 +36,25 @@ __device__ __forceinline__ unsigned long long wave_min(unsigned long long v) {
         v = o < v ? o : v;
     }
     return v;
+}
+
+// The selection result: a device copy, and (optional) the pinned host copy
+// written as two 16-byte stores, the first holding (k*, seq, J*, seq).
+__device__ __forceinline__ void publish_result(SelectOut *out, SelectOut *out_host,
+                                               unsigned long long m, uint32_t seq,
+                                               int32_t status) {
+    SelectOut o;
+    o.best_k = (m == ~0ull) ? -1 : (int)(unsigned int)(m & 0xffffffffu);
+    o.best_cost = (m == ~0ull) ? __builtin_inff() : key_cost(m);
+    o.seq_k = o.seq_cost = seq;
+    o.status = status;
+    o.pad[0] = o.pad[1] = o.pad[2] = 0u;
+    *out = o;
+    if (out_host) {
+        uint4 *h = reinterpret_cast<uint4 *>(out_host);
+        h[0] = make_uint4((unsigned int)o.best_k, seq, __float_as_uint(o.best_cost), seq);
+        h[1] = make_uint4((unsigned int)status, 0u, 0u, 0u);
+    }
 }
 
 // Admissible-set clamp of plan row `row` ([N][2] flattened: even rows are

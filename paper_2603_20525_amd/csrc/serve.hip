@@ -179,7 +179,7 @@ static void retire_front(plan_server *s) {
         const SelectOut &o = res[fr.first];
         q.res.best_k = o.best_k;
         q.res.best_cost = o.best_cost;
-        q.res.status = o.pad[0] ? (int)(int32_t)o.pad[0] : 1;
+        q.res.status = o.status ? (int)o.status : 1;
         q.res.t_done = t;
         s->completed.push_back(fr.second);
     }

@@ -127,6 +127,27 @@ def test_sampled_fused_equals_sampled_two_call(lanes, block):
     assert r1 == r2 and torch.equal(J1, J2) and torch.equal(p1, p2)
 
 
+def test_host_results_never_stale_across_contexts():
+    # each context's pinned result record may reuse memory a destroyed context
+    # published into; the reported (k*, J*) must be this call's
+    for seed in (11, 12, 13, 14, 15, 16):
+        w = inputs.c1(seed=seed)
+        T = w.terrain
+        pl = P.Planner(w.vehicle, w.cost, w.integ, w.K, w.N, T.W, T.H)
+        pl.set_terrain(dev(T.height), T.x0, T.y0, T.res)
+        u = dev(w.controls)
+        J = torch.empty(w.K, device="cuda")
+        plan = torch.empty(w.N, 2, device="cuda")
+        for _ in range(seed % 3 + 1):
+            k, jb = pl.rollout_argmin(w.state0, u, J, plan)
+            torch.cuda.synchronize()
+            Jh = J.cpu().numpy()
+            assert k == int(np.argmin(Jh)) and np.float32(jb) == Jh[k]
+        k2, jb2 = pl.select(u, J, plan)
+        assert (k2, jb2) == (k, jb)
+        pl.close()
+
+
 def test_fused_argument_errors(c2case):
     u = dev(c2case.w.controls)
     N, _, K = u.shape
