@@ -54,7 +54,10 @@ typedef struct {
 
 /* State of one request. Times are seconds on the server's monotonic clock
  * (plan_server_now). t_done is when plan_server_step first observed the
- * result on the host. */
+ * result on the host: the kernel publishes (k*, J*) into pinned memory, and
+ * the host sees it there before the launch has completed. The request's
+ * plan_dev is written by that same launch, so read it through the server's
+ * stream (or after plan_server_drain, which completes all device work). */
 typedef struct {
     int status;       /* 0 pending, 1 done, < 0: plan_status_t of a failure */
     int best_k;       /* as plan_select; -1 if no candidate is finite */
@@ -91,7 +94,8 @@ plan_status_t plan_server_submit(plan_server *s, const plan_request_t *req, int 
  * resident and waiting requests after the step. */
 plan_status_t plan_server_step(plan_server *s, int *active, int *queued);
 
-/* Step until every submitted request is done. */
+/* Step until every submitted request is done, then wait for the server's
+ * stream, so every plan buffer is written on return. */
 plan_status_t plan_server_drain(plan_server *s);
 
 /* Resident requests, queued requests and bytes of budget in use (their summed

@@ -150,10 +150,12 @@ hipError_t launch_sample_controls(const SampleArgs &sa, int K, int N, float *con
 hipError_t launch_rollout_est(const RolloutArgs &a, int block, hipStream_t s);
 
 // Slots whose entry finalizes also select their plan in the same launch
-// (fused argmin per slot): result and status to ring[slot], plan to the slot's
-// plan buffer; bad[slot] (non-finite terrain) is reported and cleared.
+// (fused argmin per slot): result, status and sequence number seq to
+// ring[slot], plan to the slot's plan buffer; bad[slot] (non-finite terrain)
+// is reported and cleared.
 hipError_t launch_rollout_slots(const RolloutArgs *slots, const TickTable &t, int *bad,
-                                SelectOut *ring, int lanes, int block, hipStream_t s);
+                                SelectOut *ring, uint32_t seq, int lanes, int block,
+                                hipStream_t s);
 
 // lanes: 1, 2 or 4 lanes per candidate (wheels split as in the forward).
 hipError_t launch_adjoint_backward(const RolloutArgs &a, int C, const float *ckpt,

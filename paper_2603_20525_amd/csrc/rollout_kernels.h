@@ -218,7 +218,7 @@ __global__ __launch_bounds__(BLOCK) void rollout_srb(const RolloutArgs a) {
 template <int LANES, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void rollout_slots(const RolloutArgs *__restrict__ slots,
                                                        const TickTable t, int *bad,
-                                                       SelectOut *ring) {
+                                                       SelectOut *ring, uint32_t seq) {
     int lo = 0, hi = t.count - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -233,6 +233,7 @@ __global__ __launch_bounds__(BLOCK) void rollout_slots(const RolloutArgs *__rest
     a.n0 = te.n0;
     a.n1 = te.n1;
     a.finalize = te.finalize;
+    a.sel_seq = seq;
     const int gtid = ((int)blockIdx.x - te.block_start) * BLOCK + threadIdx.x;
     const int sub = gtid & (LANES - 1);
     int k = gtid / LANES;
@@ -316,15 +317,15 @@ __forceinline__ hipError_t launch_argmin_lanes(const RolloutArgs &a, int block, 
 
 template <int L>
 __forceinline__ hipError_t launch_slots_lanes(const RolloutArgs *slots, const TickTable &t,
-                                              int *bad, SelectOut *ring, int block,
-                                              hipStream_t s) {
+                                              int *bad, SelectOut *ring, uint32_t seq,
+                                              int block, hipStream_t s) {
     const unsigned grid = (unsigned)t.total_blocks;
     if (block == 64)
         hipLaunchKernelGGL((rollout_slots<L, 64>), dim3(grid), dim3(64), 0, s, slots, t, bad,
-                           ring);
+                           ring, seq);
     else if (block == 256)
         hipLaunchKernelGGL((rollout_slots<L, 256>), dim3(grid), dim3(256), 0, s, slots, t, bad,
-                           ring);
+                           ring, seq);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -340,6 +341,7 @@ hipError_t launch_ckpt_multi(const RolloutArgs &a, int lanes, int block, hipStre
 hipError_t launch_argmin_multi(const RolloutArgs &a, int lanes, int block, bool sampled,
                                hipStream_t s);
 hipError_t launch_slots_multi(const RolloutArgs *slots, const TickTable &t, int *bad,
-                              SelectOut *ring, int lanes, int block, hipStream_t s);
+                              SelectOut *ring, uint32_t seq, int lanes, int block,
+                              hipStream_t s);
 
 }  // namespace plan

@@ -82,6 +82,7 @@ struct Slot {
 struct Step {
     hipEvent_t ev;
     int ring;
+    uint32_t seq;                               // published with each finished slot's result
     std::vector<std::pair<int, int>> finished;  // (slot, request)
 };
 
@@ -105,6 +106,7 @@ struct plan_server {
     unsigned int *sel_ticket = nullptr;     // per-slot arrival ticket (zero between uses)
     SelectOut *ring_host[RING] = {};
     int ring_next = 0;
+    uint32_t seq = 0;  // sequence number of the last launched step
     // admission staging: pinned entries per ring position (reused only after
     // the step that copied them has completed) and their device copy
     AdmitEntry *admit_host[RING] = {};
@@ -186,8 +188,30 @@ static void retire_front(plan_server *s) {
     s->ev_pool.push_back(st.ev);
 }
 
+// Whether every result of step st has landed in its pinned ring entry (each
+// finishing slot's record carries the step's sequence number in both of its
+// 8-byte words). A step that finishes no request has nothing to publish.
+static bool results_landed(const plan_server *s, const Step &st) {
+    if (st.finished.empty()) return false;
+    const SelectOut *res = s->ring_host[st.ring];
+    for (const auto &fr : st.finished) {
+        const uint64_t *w = reinterpret_cast<const uint64_t *>(&res[fr.first]);
+        const uint64_t w0 = __atomic_load_n(&w[0], __ATOMIC_ACQUIRE);
+        const uint64_t w1 = __atomic_load_n(&w[1], __ATOMIC_ACQUIRE);
+        if ((uint32_t)(w0 >> 32) != st.seq || (uint32_t)(w1 >> 32) != st.seq) return false;
+    }
+    return true;
+}
+
+// Retire completed steps from the front: a step is complete when its event
+// has fired or, sooner, when all its results have landed in host memory (its
+// kernel may still be writing plans then; they stay ordered on the stream).
 static plan_status_t poll(plan_server *s, bool block_until_below) {
     while (!s->inflight.empty()) {
+        if (results_landed(s, s->inflight.front())) {
+            retire_front(s);
+            continue;
+        }
         hipError_t q = hipEventQuery(s->inflight.front().ev);
         if (q == hipSuccess) {
             retire_front(s);
@@ -298,8 +322,10 @@ static plan_status_t launch_step(plan_server *s) {
     // write their results into this step's pinned ring entry
     st.ring = s->ring_next;
     s->ring_next = (s->ring_next + 1) % RING;
-    SHIP(s, plan::launch_rollout_slots(s->slot_args, t, s->bad, s->ring_host[st.ring], lanes,
-                                       block, s->stream));
+    s->seq = s->seq + 1u == 0u ? 1u : s->seq + 1u;
+    st.seq = s->seq;
+    SHIP(s, plan::launch_rollout_slots(s->slot_args, t, s->bad, s->ring_host[st.ring], st.seq,
+                                       lanes, block, s->stream));
     if (s->ev_pool.empty()) {
         hipEvent_t e;
         SHIP(s, hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -364,8 +390,10 @@ plan_status_t plan_server_create(plan_server **out, const plan_vehicle_t *veh, i
     if (e == hipSuccess) e = hipMalloc(&s->bad, sizeof(int) * S);
     if (e == hipSuccess) e = hipMalloc(&s->sel, sizeof(SelectOut) * S);
     if (e == hipSuccess) e = hipMalloc(&s->admit_dev, sizeof(AdmitEntry) * S);
-    for (int i = 0; i < RING && e == hipSuccess; ++i)
+    for (int i = 0; i < RING && e == hipSuccess; ++i) {
         e = hipHostMalloc(&s->ring_host[i], sizeof(SelectOut) * S, hipHostMallocDefault);
+        if (e == hipSuccess) memset(s->ring_host[i], 0, sizeof(SelectOut) * S);  // seq 0: none
+    }
     for (int i = 0; i < RING && e == hipSuccess; ++i)
         e = hipHostMalloc(&s->admit_host[i], sizeof(AdmitEntry) * S, hipHostMallocDefault);
     if (e == hipSuccess) e = hipMemset(s->bad, 0, sizeof(int) * S);
@@ -445,9 +473,12 @@ plan_status_t plan_server_drain(plan_server *s) {
         if (st != PLAN_OK) return st;
         if (active == 0 && queued == 0) {
             while (!s->inflight.empty()) {
-                SHIP(s, hipEventSynchronize(s->inflight.front().ev));
+                if (!results_landed(s, s->inflight.front()))
+                    SHIP(s, hipEventSynchronize(s->inflight.front().ev));
                 retire_front(s);
             }
+            // every plan buffer written before returning
+            SHIP(s, hipStreamSynchronize(s->stream));
             return PLAN_OK;
         }
     }
