@@ -341,8 +341,8 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(candidate sharding over GPUs is described in the design notes, not built)",
+        print(f"bench.py: libplan runs on one GPU; --gpus {args.gpus} is not supported "
+              "(sharding candidates over GPUs is designed, not implemented)",
               file=sys.stderr)
         sys.exit(2)
 
