@@ -29,8 +29,10 @@ if ROOT not in sys.path:
 METRIC = "candidate rollout-steps/sec and p50/p99 plan latency (serving vs plain)"
 
 # FP32 operations per rollout-step of the step definition, one lane per
-# candidate, transcendentals counted as one (the per-block count is tabulated
-# in the design notes); used for the algorithmic side of the ALU roofline.
+# candidate, transcendentals counted as one: goal test 5, attitude 21,
+# kinematics 26, four wheels of 101, wheel sums 18, right-hand side rows 17,
+# ESM and soft cost 12, running cost 5, Euler update and clamps 19, control
+# clamp 5 per interval. Used for the algorithmic side of the ALU roofline.
 OPS_PER_STEP = 532
 # MI355X vector ALU issue: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz, one
 # non-packed FP32 operation per lane per clock.
@@ -118,7 +120,11 @@ def _summ(lat, t_first, t_last, steps, n):
 
 
 # Algorithmic FP32 operations per step of the other rollout variants (same
-# counting rules as OPS_PER_STEP; tabulated in the design notes).
+# counting rules as OPS_PER_STEP). EST: one bilinear lookup of 3 channels with
+# its index arithmetic 40, angles from the normal 10, sincos psi, rotation and
+# world velocity 16, load transfer 6, two slip angles 10, tires 12, rows,
+# constraint and cost 20, Euler and limits 12, goal test 5. RK4: four
+# right-hand sides, the stage and combination updates, one set of limits.
 EST_OPS_PER_STEP = 130
 RK4_OPS_PER_STEP = 4 * (OPS_PER_STEP - 24) + 24 + 3 * 13 * 2 + 2 * 13
 HBM_PEAK_GBS = 8000.0

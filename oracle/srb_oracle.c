@@ -21,7 +21,7 @@
  *   - Optimiser: section "Real-Time Implementation" (empirical argmin; MPPI
  *     weighted average as the lambda > 0 variant; forward Euler).
  *
- * Readings where the paper is silent or ambiguous (listed in the design notes):
+ * Readings where the paper is silent or ambiguous (the kernels take the same):
  *   - terrain normal taken as (-f_x, -f_y, 1), the upward normal of z=f(x,y);
  *   - ESM sign: negative once |phi| + phi_bar exceeds pi/2 (CoM past the
  *     wheel line);
