@@ -9,8 +9,9 @@ Tolerances (FP32 GPU arithmetic against FP64 on identical float32 inputs):
     less than the cost tolerance (a tie at FP32 resolution);
   * plan entries: 1e-4 relative to max(|oracle|, 0.1).
 The state bound is the one the planner's accuracy needs (1e-4 of a metre on
-a trajectory of tens of metres). A single FP32 step errs by about 1e-7
-relative, so the step map is compared element by element; over a whole
+a trajectory of tens of metres). One control interval computed in FP32
+from the same float32 state stays within it (worst about half of it on the
+single-plan workload), so the step map is compared element by element; over a whole
 horizon on berm terrain the model's discontinuities (damper switch at
 touchdown, slip-angle flip at v_x = 0) and the steep ESM soft cost amplify
 storage rounding beyond 1e-4 even between two FP64 runs whose inputs differ
