@@ -204,6 +204,24 @@ def rows_leg():
                               "alu_frac": alu(RK4_OPS_PER_STEP * steps, ms / 1e3)}
     pl.close()
 
+    # softmin selection on the single-plan workload: weights over all K
+    # costs, weighted mean of all K control sequences (HBM: the controls and
+    # costs read once, the plan written)
+    w = inputs.c2()
+    pl = P.Planner(w.vehicle, w.cost, w.integ, w.K, w.N, w.terrain.W, w.terrain.H)
+    pl.set_terrain(dev(w.terrain.height), w.terrain.x0, w.terrain.y0, w.terrain.res)
+    uc = dev(w.controls)
+    Jc = torch.empty(w.K, device="cuda")
+    pc = torch.empty(w.N, 2, device="cuda")
+    pl.rollout(w.state0, uc, Jc)
+    ms = _time_ms(lambda: pl.select(uc, Jc, pc, mode=P.PLAN_SOFTMIN, lam=10.0,
+                                    want_result=False), reps=20, warm=5)
+    nbytes = 4 * (2 * w.N * w.K + w.K + 2 * w.N)
+    out["softmin_select_single_plan"] = {"ms": ms, "bytes": nbytes,
+                                         "gb_per_s": nbytes / (ms / 1e3) / 1e9,
+                                         "hbm_frac": nbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+    pl.close()
+
     # adjoint: forward (checkpoints every 10 intervals) + backward, K = 1024
     # and the top-32 refinement set
     w = inputs.c4()

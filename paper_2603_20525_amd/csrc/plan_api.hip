@@ -38,9 +38,8 @@ struct plan_ctx {
     int *bad_host = nullptr;  // pinned
     // selection workspace
     unsigned long long *part_keys = nullptr;  // argmin slot, all ones between launches
-    unsigned int *counters = nullptr;  // tickets: [0] argmin, [1] softmin, [2] fused argmin
+    unsigned int *counters = nullptr;  // tickets: [0] argmin, [2] fused argmin
     unsigned long long *fused_key = nullptr;  // fused argmin slot, all ones between launches
-    float *wpart = nullptr;
     SelectOut *sel_dev = nullptr;
     SelectOut *sel_host = nullptr;  // pinned
     uint32_t seq = 0;               // sequence number of the last published selection
@@ -95,7 +94,6 @@ static void release(plan_ctx *c) {
     (void)hipFree(c->part_keys);
     (void)hipFree(c->counters);
     (void)hipFree(c->fused_key);
-    (void)hipFree(c->wpart);
     (void)hipFree(c->sel_dev);
     (void)hipFree(c->gws);
     (void)hipFree(c->smooth_tmp);
@@ -268,8 +266,6 @@ plan_status_t plan_create(plan_ctx **out, const plan_vehicle_t *veh, const plan_
     CREATE_TRY(hipMemset(c->counters, 0, sizeof(unsigned int) * 4));
     CREATE_TRY(hipMalloc(&c->fused_key, sizeof(unsigned long long)));
     CREATE_TRY(hipMemset(c->fused_key, 0xFF, sizeof(unsigned long long)));
-    const size_t wsz = (size_t)plan::softmin_chunks(max_K) * (2 * (size_t)max_N + 1);
-    CREATE_TRY(hipMalloc(&c->wpart, sizeof(float) * wsz));
     CREATE_TRY(hipMalloc(&c->sel_dev, sizeof(SelectOut)));
     CREATE_TRY(hipHostMalloc(&c->sel_host, sizeof(SelectOut), hipHostMallocDefault));
     memset(c->sel_host, 0, sizeof(SelectOut));  // no sequence number matches 0
@@ -772,7 +768,7 @@ plan_status_t plan_select(plan_ctx *c, int mode, float lambda, const float *cont
     const uint32_t seq = want ? next_seq(c) : 0u;
     HIP_TRY(c, plan::launch_select(mode, lambda, controls_dev, cost_dev, K, N,
                                    c->veh.delta_rate_max, plan_dev, c->part_keys, c->counters,
-                                   c->wpart, c->sel_dev, want ? c->sel_host : nullptr, seq,
+                                   c->sel_dev, want ? c->sel_host : nullptr, seq,
                                    c->stream));
     return want ? wait_result(c, seq, best_k, best_cost) : PLAN_OK;
 }

@@ -196,14 +196,11 @@ hipError_t launch_costmap_polygons(const float *verts, const PolygonSet &ps, int
 
 // Selection workspace sizes for a given maximum K / N.
 int select_blocks(int K);
-int softmin_chunks(int K);
-int softmin_row_groups(int N);
 
 hipError_t launch_select(int mode, float lambda, const float *controls, const float *cost,
                          int K, int N, float drate_max, float *plan_out,
                          unsigned long long *part_keys, unsigned int *counters,
-                         float *wpart, SelectOut *out, SelectOut *out_host, uint32_t seq,
-                         hipStream_t s);
+                         SelectOut *out, SelectOut *out_host, uint32_t seq, hipStream_t s);
 
 // Argmin whose plan is the winner's sequence regenerated from the sampler.
 hipError_t launch_select_sampled(const SampleArgs &sa, const float *cost, int K, int N,

@@ -17,8 +17,9 @@ namespace {
 constexpr int SEL_BLOCK = 256;
 constexpr int SEL_ITEMS = 16;                      // candidates per thread
 constexpr int SEL_CHUNK = SEL_BLOCK * SEL_ITEMS;   // candidates per block
-constexpr int SM_CHUNK = 2048;                     // softmin: candidates per block
-constexpr int SM_ROWS = 8;                         // softmin: plan entries per block
+constexpr int SM_ROWS = 4;                         // softmin: plan entries per block
+constexpr int SM_UNROLL = 8;                       // softmin: candidates in flight per thread
+constexpr int SM_BLOCK = 1024;                     // softmin: threads per block
 
 // --------------------------------------------------------------- terrain ----
 // Node slopes by central differences (one-sided on the border), merged with
@@ -38,11 +39,6 @@ __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
-}
-
-// Coherent read of a partial written by another block of the same launch.
-__device__ __forceinline__ float load_partial(const float *p) {
-    return __uint_as_float(__atomic_load_n((const unsigned int *)p, __ATOMIC_RELAXED));
 }
 
 // One block per SEL_CHUNK candidates; each folds its minimum key into the
@@ -92,87 +88,87 @@ __global__ __launch_bounds__(SEL_BLOCK) void select_argmin(
     }
 }
 
-// Softmin partial sums. Block (c, g) handles candidates [c*SM_CHUNK, ...) and
-// plan rows [g*SM_ROWS, ...); row 2N is the weight sum. The last block to
-// finish adds the chunk partials in chunk order and divides.
-__global__ __launch_bounds__(SEL_BLOCK) void select_softmin(
+// MPPI-style softmin in one launch with no traffic between workgroups.
+// Workgroup g owns plan entries [g*SM_ROWS, (g+1)*SM_ROWS) of the 2N. Every
+// workgroup takes the minimum key over all K itself (the costs are a few KB,
+// served from L2), weighs each finite candidate w_k = exp(-(J_k - J_min) /
+// lambda), and forms its entries' weighted sums of the clamped controls and
+// the weight sum, each thread over a fixed stride of candidates and then in
+// a fixed reduction tree, so the result does not depend on scheduling.
+// Workgroup 0 publishes (k*, J*).
+__global__ __launch_bounds__(SM_BLOCK) void select_softmin(
     const float *__restrict__ cost, int K, const float *__restrict__ controls, int N,
-    float drate_max, float inv_lambda, float *__restrict__ plan,
-    float *__restrict__ wpart, unsigned int *__restrict__ ticket,
-    const SelectOut *__restrict__ best) {
-    __shared__ float w_sh[SM_CHUNK];
-    __shared__ float red[SEL_BLOCK / 64][SM_ROWS + 1];
-    __shared__ int last_sh;
+    float drate_max, float inv_lambda, float *__restrict__ plan, SelectOut *__restrict__ out,
+    SelectOut *out_host, uint32_t seq) {
+    __shared__ unsigned long long kred[SM_BLOCK / 64];
+    __shared__ float fred[SM_BLOCK / 64][SM_ROWS + 1];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int chunk = blockIdx.x, grp = blockIdx.y;
-    const int nchunks = gridDim.x;
-    const int rows = 2 * N + 1;
-    const int k0 = chunk * SM_CHUNK;
-    const int kn = min(SM_CHUNK, K - k0);
-    const SelectOut bo = *best;
-    const float jmin = bo.best_cost;
-    const bool any = bo.best_k >= 0;
-    for (int q = tid; q < SM_CHUNK; q += SEL_BLOCK) {
-        float w = 0.0f;
-        if (any && q < kn) {
-            const float J = cost[k0 + q];
-            if (isfinite(J)) w = __expf(-(J - jmin) * inv_lambda);
-        }
-        w_sh[q] = w;
+    unsigned long long key = ~0ull;
+    for (int k = tid; k < K; k += SM_BLOCK) {
+        const unsigned long long kk = cost_key(cost[k], k);
+        key = kk < key ? kk : key;
     }
+    key = wave_min(key);
+    if (lane == 0) kred[wv] = key;
     __syncthreads();
-    const int r0 = grp * SM_ROWS;
-    for (int rr = 0; rr < SM_ROWS; ++rr) {
-        const int r = r0 + rr;
-        float acc = 0.0f;
-        if (r < rows) {
-            if (r == 2 * N) {
-                for (int q = tid; q < kn; q += SEL_BLOCK) acc += w_sh[q];
-            } else {
-                const float *row = controls + (size_t)r * K + k0;
-                for (int q = tid; q < kn; q += SEL_BLOCK)
-                    acc += w_sh[q] * clamp_ctrl(row[q], r, drate_max);
+    unsigned long long m = kred[0];
+#pragma unroll
+    for (int q = 1; q < SM_BLOCK / 64; ++q) m = kred[q] < m ? kred[q] : m;
+    if (blockIdx.x == 0 && tid == 0) publish_result(out, out_host, m, seq, 0);
+    const bool any = m != ~0ull;
+    const float jmin = any ? key_cost(m) : 0.0f;
+    const int rows = 2 * N;
+    const int r0 = blockIdx.x * SM_ROWS;
+    float acc[SM_ROWS + 1];
+#pragma unroll
+    for (int j = 0; j <= SM_ROWS; ++j) acc[j] = 0.0f;
+    if (any) {
+        // SM_UNROLL candidates per thread per pass, all loads issued before
+        // any is used; candidates still accumulate in the order k = tid,
+        // tid + SM_BLOCK, ... for every thread
+        for (int kb = tid; kb < K; kb += SM_BLOCK * SM_UNROLL) {
+            float w[SM_UNROLL];
+            float u[SM_ROWS][SM_UNROLL];
+#pragma unroll
+            for (int q = 0; q < SM_UNROLL; ++q) {
+                const int k = kb + q * SM_BLOCK;
+                const float J = k < K ? cost[k] : __builtin_inff();
+#pragma unroll
+                for (int j = 0; j < SM_ROWS; ++j) {
+                    const int r = r0 + j;
+                    u[j][q] = (k < K && r < rows) ? controls[(size_t)r * K + k] : 0.0f;
+                }
+                w[q] = isfinite(J) ? __expf(-(J - jmin) * inv_lambda) : 0.0f;
+            }
+#pragma unroll
+            for (int q = 0; q < SM_UNROLL; ++q) {
+                acc[SM_ROWS] += w[q];
+#pragma unroll
+                for (int j = 0; j < SM_ROWS; ++j)
+                    acc[j] += w[q] * clamp_ctrl(u[j][q], r0 + j, drate_max);
             }
         }
-        acc = wave_sum(acc);
-        if (lane == 0) red[wv][rr] = acc;
+    }
+#pragma unroll
+    for (int j = 0; j <= SM_ROWS; ++j) {
+        const float v = wave_sum(acc[j]);
+        if (lane == 0) fred[wv][j] = v;
     }
     __syncthreads();
-    if (tid < SM_ROWS) {
-        const int r = r0 + tid;
-        if (r < rows) {
-            float s = 0.0f;
-            for (int q = 0; q < SEL_BLOCK / 64; ++q) s += red[q][tid];
-            wpart[(size_t)r * nchunks + chunk] = s;
+    if (tid < SM_ROWS && r0 + tid < rows) {
+        float num = fred[0][tid], den = fred[0][SM_ROWS];
+#pragma unroll
+        for (int q = 1; q < SM_BLOCK / 64; ++q) {
+            num += fred[q][tid];
+            den += fred[q][SM_ROWS];
         }
+        plan[r0 + tid] = any ? num / den : 0.0f;
     }
-    __syncthreads();
-    if (tid == 0) {
-        __threadfence();
-        const unsigned int t = atomicAdd(ticket, 1u);
-        last_sh = (t == gridDim.x * gridDim.y - 1);
-    }
-    __syncthreads();
-    if (!last_sh) return;
-    __threadfence();
-    // last block: fixed-order sum over chunks, then divide by the weight sum
-    float den = 0.0f;
-    for (int c = 0; c < nchunks; ++c)
-        den += load_partial(&wpart[(size_t)(2 * N) * nchunks + c]);
-    for (int r = tid; r < 2 * N; r += SEL_BLOCK) {
-        float num = 0.0f;
-        for (int c = 0; c < nchunks; ++c)
-            num += load_partial(&wpart[(size_t)r * nchunks + c]);
-        plan[r] = any ? num / den : 0.0f;
-    }
-    if (tid == 0) *ticket = 0u;
 }
 
 }  // namespace
 
 int select_blocks(int K) { return (K + SEL_CHUNK - 1) / SEL_CHUNK; }
-int softmin_chunks(int K) { return (K + SM_CHUNK - 1) / SM_CHUNK; }
-int softmin_row_groups(int N) { return (2 * N + 1 + SM_ROWS - 1) / SM_ROWS; }
 
 hipError_t launch_pack_terrain(const float *h, const float *c, int W, int H, float inv_res,
                                float4 *tex, int *bad, hipStream_t s) {
@@ -183,18 +179,17 @@ hipError_t launch_pack_terrain(const float *h, const float *c, int W, int H, flo
 
 hipError_t launch_select(int mode, float lambda, const float *controls, const float *cost,
                          int K, int N, float drate_max, float *plan_out,
-                         unsigned long long *part_keys, unsigned int *counters, float *wpart,
+                         unsigned long long *part_keys, unsigned int *counters,
                          SelectOut *out, SelectOut *out_host, uint32_t seq, hipStream_t s) {
-    const int nb = select_blocks(K);
-    hipLaunchKernelGGL(select_argmin<false>, dim3(nb), dim3(SEL_BLOCK), 0, s, cost, K, controls,
-                       N, drate_max, mode == 0 ? 1 : 0, plan_out, part_keys, counters + 0, out,
-                       out_host, seq, SampleArgs{});
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || mode == 0) return e;
-    dim3 grid(softmin_chunks(K), softmin_row_groups(N));
-    hipLaunchKernelGGL(select_softmin, grid, dim3(SEL_BLOCK), 0, s, cost, K, controls, N,
-                       drate_max, 1.0f / lambda, plan_out, wpart, counters + 1,
-                       (const SelectOut *)out);
+    if (mode == 0) {
+        hipLaunchKernelGGL(select_argmin<false>, dim3(select_blocks(K)), dim3(SEL_BLOCK), 0, s,
+                           cost, K, controls, N, drate_max, 1, plan_out, part_keys,
+                           counters + 0, out, out_host, seq, SampleArgs{});
+    } else {
+        const unsigned groups = (unsigned)((2 * N + SM_ROWS - 1) / SM_ROWS);
+        hipLaunchKernelGGL(select_softmin, dim3(groups), dim3(SM_BLOCK), 0, s, cost, K,
+                           controls, N, drate_max, 1.0f / lambda, plan_out, out, out_host, seq);
+    }
     return hipGetLastError();
 }
 
