@@ -117,15 +117,22 @@ def _check(fn: str, st: int, ctx=None):
         raise PlanError(fn, st, detail.decode() if detail else "")
 
 
+_F32 = None
+
+
 def _dptr(t, name, numel=None):
-    """Device address of a contiguous float32 CUDA tensor (None -> NULL)."""
+    """Device address (int) of a contiguous float32 CUDA tensor (None -> NULL)."""
+    global _F32
     if t is None:
         return None
-    if not t.is_cuda or t.dtype.__str__() != "torch.float32" or not t.is_contiguous():
+    if _F32 is None:
+        import torch
+        _F32 = torch.float32
+    if not t.is_cuda or t.dtype is not _F32 or not t.is_contiguous():
         raise ValueError(f"{name} must be a contiguous float32 GPU tensor")
     if numel is not None and t.numel() != numel:
         raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
-    return C.c_void_p(t.data_ptr())
+    return t.data_ptr()
 
 
 def _struct(cls, d):
@@ -281,14 +288,19 @@ def plan_select_sampled(ctx, spec: Sample, cost, plan, want_result: bool = True)
 
 
 def plan_rollout_argmin(ctx, state0, controls, cost, plan, final_state=None,
-                        want_result: bool = True):
+                        want_result: bool = True, _bufs=None):
     """Rollout and argmin in one launch; returns (best_k, best_cost) when
-    want_result (waits), else None."""
+    want_result (waits), else None. _bufs: reusable (state0 array, int,
+    float) ctypes objects of the caller."""
     N, two, K = controls.shape
     if two != 2:
         raise ValueError("controls must be [N][2][K]")
-    s0 = (C.c_float * 13)(*[float(v) for v in state0])
-    bk, bc = C.c_int(0), C.c_float(0)
+    if _bufs is None:
+        s0 = (C.c_float * 13)(*[float(v) for v in state0])
+        bk, bc = C.c_int(0), C.c_float(0)
+    else:
+        s0, bk, bc = _bufs
+        s0[:] = state0
     st = lib().plan_rollout_argmin(ctx, s0, _dptr(controls, "controls"), K, N,
                                    _dptr(cost, "cost", K),
                                    _dptr(final_state, "final_state", 13 * K),
@@ -377,6 +389,7 @@ class Planner:
     def __init__(self, vehicle, cost, integ, max_K, max_N, max_W, max_H, stream=None):
         import torch
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._bufs = None  # reusable ctypes arguments of the one-launch plan call
         self.ctx = plan_create(vehicle, cost, integ, max_K, max_N, max_W, max_H, self.stream)
 
     def close(self):
@@ -424,8 +437,10 @@ class Planner:
         return plan_select_sampled(self.ctx, spec, cost, plan, want_result)
 
     def rollout_argmin(self, state0, controls, cost, plan, final_state=None, want_result=True):
+        if self._bufs is None:
+            self._bufs = ((C.c_float * 13)(), C.c_int(0), C.c_float(0))
         return plan_rollout_argmin(self.ctx, state0, controls, cost, plan, final_state,
-                                   want_result)
+                                   want_result, self._bufs)
 
     def rollout_sampled_argmin(self, state0, spec, N, cost, plan, final_state=None,
                                want_result=True):
@@ -531,13 +546,13 @@ class Server:
         """All tensors are kept referenced until the request is read back."""
         H, W = height.shape
         N, two, K = controls.shape
-        r = Request(height_dev=_dptr(height, "height").value, W=W, H=H, x0=float(x0),
+        r = Request(height_dev=_dptr(height, "height"), W=W, H=H, x0=float(x0),
                     y0=float(y0), res=float(res),
-                    costmap_dev=None if costmap is None else _dptr(costmap, "costmap", H * W).value,
+                    costmap_dev=None if costmap is None else _dptr(costmap, "costmap", H * W),
                     state0=(C.c_float * 13)(*[float(v) for v in state0]),
-                    controls_dev=_dptr(controls, "controls").value, K=K, N=N,
+                    controls_dev=_dptr(controls, "controls"), K=K, N=N,
                     cost=_struct(Cost, cost), integ=_struct(Integ, integ),
-                    plan_dev=_dptr(plan, "plan", 2 * N).value)
+                    plan_dev=_dptr(plan, "plan", 2 * N))
         rid = C.c_int(-1)
         _scheck("plan_server_submit", _bind_server().plan_server_submit(self.h, C.byref(r),
                                                                          C.byref(rid)), self.h)
