@@ -531,6 +531,11 @@ class Server:
     def __init__(self, vehicle, max_slots, max_K, max_N, max_W, max_H, budget_bytes,
                  chunk_intervals=16, stream=None):
         import torch
+        self._req = Request()
+        self._rid = C.c_int(-1)
+        self._params = {}
+        self._cbuf = {}
+        self._cn, self._sa, self._sq = C.c_int(0), C.c_int(0), C.c_int(0)
         L = _bind_server()
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = C.c_void_p()
@@ -546,21 +551,40 @@ class Server:
         """All tensors are kept referenced until the request is read back."""
         H, W = height.shape
         N, two, K = controls.shape
-        r = Request(height_dev=_dptr(height, "height"), W=W, H=H, x0=float(x0),
-                    y0=float(y0), res=float(res),
-                    costmap_dev=None if costmap is None else _dptr(costmap, "costmap", H * W),
-                    state0=(C.c_float * 13)(*[float(v) for v in state0]),
-                    controls_dev=_dptr(controls, "controls"), K=K, N=N,
-                    cost=_struct(Cost, cost), integ=_struct(Integ, integ),
-                    plan_dev=_dptr(plan, "plan", 2 * N))
-        rid = C.c_int(-1)
+        # the library copies the request, so one Request object is reused
+        r = self._req
+        r.height_dev = _dptr(height, "height")
+        r.W, r.H = W, H
+        r.x0, r.y0, r.res = float(x0), float(y0), float(res)
+        r.costmap_dev = None if costmap is None else _dptr(costmap, "costmap", H * W)
+        r.state0[:] = state0
+        r.controls_dev = _dptr(controls, "controls")
+        r.K, r.N = K, N
+        r.cost = self._param(Cost, cost)
+        r.integ = self._param(Integ, integ)
+        r.plan_dev = _dptr(plan, "plan", 2 * N)
+        rid = self._rid
         _scheck("plan_server_submit", _bind_server().plan_server_submit(self.h, C.byref(r),
                                                                          C.byref(rid)), self.h)
         self._keep[rid.value] = (height, controls, plan, costmap)
         return rid.value
 
+    def _param(self, cls, d):
+        """ctypes copy of a parameter dict, reused while the dict's values are
+        unchanged (requests usually share their cost and integration dicts)."""
+        key = (cls, id(d))
+        snap = tuple(d.values())
+        hit = self._params.get(key)
+        if hit is not None and hit[0] is d and hit[1] == snap:
+            return hit[2]
+        st = _struct(cls, d)
+        if len(self._params) > 256:
+            self._params.clear()
+        self._params[key] = (d, snap, st)
+        return st
+
     def step(self):
-        a, q = C.c_int(0), C.c_int(0)
+        a, q = self._sa, self._sq
         _scheck("plan_server_step", _bind_server().plan_server_step(self.h, C.byref(a),
                                                                      C.byref(q)), self.h)
         return a.value, q.value
@@ -586,11 +610,13 @@ class Server:
     def completions(self, capacity=128) -> list:
         """Ids of requests finished since the previous call, in the order
         the host observed them."""
-        buf = (C.c_int * capacity)()
-        n = C.c_int(0)
+        buf = self._cbuf.get(capacity)
+        if buf is None:
+            buf = self._cbuf[capacity] = (C.c_int * capacity)()
+        n = self._cn
         _scheck("plan_server_completions", _bind_server().plan_server_completions(
             self.h, buf, capacity, C.byref(n)), self.h)
-        return list(buf[:n.value])
+        return buf[:n.value] if n.value else []
 
     def now(self) -> float:
         return _bind_server().plan_server_now(self.h)
