@@ -178,9 +178,13 @@ def rows_leg():
         "rollout_steps_per_s": steps * 1e3 / ms, "alu_frac": alu(OPS_PER_STEP * steps, ms / 1e3),
         "paper_context": "11e6 samples/s (80 Hz) on an RTX 5000 Ada Mobile; about 21e6 on an "
                          "RTX 6000 Ada (other hardware, scanned terrain)"}
-    # extended single-track formulation at the same shape (materialised samples)
+    # materialised samples of the same shape (generator only: 2 N K floats written)
     u = torch.empty(N, 2, K, device="cuda")
-    pl.sample_controls(spec, u)
+    ms = _time_ms(lambda: pl.sample_controls(spec, u))
+    nbytes = 8 * N * K
+    out["sample_controls_paper_shape"] = {"ms": ms, "gb_per_s": nbytes / ms / 1e6,
+                                          "hbm_frac": nbytes / ms / 1e6 / HBM_PEAK_GBS}
+    # extended single-track formulation at the same shape (materialised samples)
     s13 = w.state0
     s7 = [s13[0], s13[1], s13[3], s13[7], s13[11], s13[12], s13[6]]
     ms_est = _time_ms(lambda: pl.rollout_est(s7, u, J))
@@ -265,6 +269,12 @@ def rows_leg():
     out["costmap_2048"] = {"ms": ms, "polygons": len(polys), "edges": edges,
                            "node_edge_tests_per_s": T.W * T.H * edges * 1e3 / ms,
                            "alu_frac": alu(25 * T.W * T.H * edges, ms / 1e3)}
+    # terrain pack (plan_set_terrain: slopes and texels, with its non-finite
+    # check and the host wait for it): heights and costmap read, texels written
+    ms = _time_ms(lambda: pl.set_terrain(h, T.x0, T.y0, T.res, cm))
+    nbytes = (4 + 4 + 16) * T.W * T.H
+    out["terrain_pack_2048"] = {"ms": ms, "gb_per_s": nbytes / ms / 1e6,
+                                "hbm_frac": nbytes / ms / 1e6 / HBM_PEAK_GBS}
     pl.close()
     return out
 
