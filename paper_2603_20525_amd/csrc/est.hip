@@ -136,15 +136,14 @@ __global__ __launch_bounds__(BLOCK) void rollout_est(const RolloutArgs a) {
     float J = 0.0f;
     bool done = false;
     const float *up = a.controls + k;
-    for (int n = 0; n < a.N && !done; ++n) {
+    // uniform trip counts: a candidate that reaches the goal stays frozen
+    for (int n = 0; n < a.N; ++n) {
         const float dd = clampf_nan(up[(2 * (size_t)n) * K], -a.drate_max, a.drate_max);
         const float ax = a.accel_max * clampf_nan(up[(2 * (size_t)n + 1) * K], -1.0f, 1.0f);
         for (int s = 0; s < a.S; ++s) {
             const float gdx = st[0] - a.goal_x, gdy = st[1] - a.goal_y;
-            if (fmaf(gdx, gdx, gdy * gdy) <= a.goal_r2) {
-                done = true;
-                break;
-            }
+            done = done || fmaf(gdx, gdx, gdy * gdy) <= a.goal_r2;
+            if (done) continue;
             est_step(a, st, J, dd, ax);
         }
     }

@@ -73,7 +73,10 @@ __device__ __forceinline__ float simulate(const RolloutArgs &a, int k, int sub, 
     };
     if constexpr (CKPT) write_ckpt(0);
 
-    for (int n = a.n0; n < a.n1 && !done; ++n) {
+    // uniform trip counts: a candidate that reaches the goal stays in the
+    // loop frozen (its lanes skip the steps), so the loops carry no
+    // per-lane exit bookkeeping
+    for (int n = a.n0; n < a.n1; ++n) {
         // zero-order hold: control n for the whole interval, restricted to the
         // admissible set (|delta_dot| <= limit, throttle in [-1, 1])
         float u0, u1;
@@ -100,11 +103,9 @@ __device__ __forceinline__ float simulate(const RolloutArgs &a, int k, int sub, 
             // goal test at the Euler node, before the step
             {
                 const float gdx = st[0] - a.goal_x, gdy = st[1] - a.goal_y;
-                if (fmaf(gdx, gdx, gdy * gdy) <= a.goal_r2) {
-                    done = true;
-                    break;
-                }
+                done = done || fmaf(gdx, gdx, gdy * gdy) <= a.goal_r2;
             }
+            if (done) continue;
             if constexpr (RK4) {
                 rk4_step<LANES>(a, arms, st, J, dd, ax);
             } else if constexpr (SAMPLED) {
