@@ -152,9 +152,9 @@ hipError_t launch_rollout_est(const RolloutArgs &a, int block, hipStream_t s);
 // Slots whose entry finalizes also select their plan in the same launch
 // (fused argmin per slot): result, status and sequence number seq to
 // ring[slot], plan to the slot's plan buffer; bad[slot] (non-finite terrain)
-// is reported and cleared.
+// is reported and cleared. s1: every slot has one substep per interval.
 hipError_t launch_rollout_slots(const RolloutArgs *slots, const TickTable &t, int *bad,
-                                SelectOut *ring, uint32_t seq, int lanes, int block,
+                                SelectOut *ring, uint32_t seq, bool s1, int lanes, int block,
                                 hipStream_t s);
 
 // lanes: 1, 2 or 4 lanes per candidate (wheels split as in the forward).

@@ -77,11 +77,11 @@ hipError_t launch_rollout_argmin(const RolloutArgs &a, int lanes, int block, boo
 }
 
 hipError_t launch_rollout_slots(const RolloutArgs *slots, const TickTable &t, int *bad,
-                                SelectOut *ring, uint32_t seq, int lanes, int block,
+                                SelectOut *ring, uint32_t seq, bool s1, int lanes, int block,
                                 hipStream_t s) {
     if (t.count < 1) return hipSuccess;
-    return lanes == 1 ? launch_slots_lanes<1>(slots, t, bad, ring, seq, block, s)
-                      : launch_slots_multi(slots, t, bad, ring, seq, lanes, block, s);
+    return lanes == 1 ? launch_slots_lanes<1>(slots, t, bad, ring, seq, s1, block, s)
+                      : launch_slots_multi(slots, t, bad, ring, seq, s1, lanes, block, s);
 }
 
 hipError_t launch_sample_controls(const SampleArgs &sa, int K, int N, float *controls,

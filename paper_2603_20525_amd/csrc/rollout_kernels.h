@@ -22,7 +22,8 @@ namespace {
 // generator block per four intervals, kept in registers) instead of reading
 // a.controls. Lanes with store == false run a duplicate candidate only to
 // keep their lane group complete.
-template <int LANES, bool CHUNK, bool SAMPLED = false, bool RK4 = false, bool CKPT = false>
+template <int LANES, bool CHUNK, bool SAMPLED = false, bool RK4 = false, bool CKPT = false,
+          bool S1 = false>
 __device__ __forceinline__ float simulate(const RolloutArgs &a, int k, int sub, bool store) {
     constexpr int WPL = 4 / LANES;  // wheels per lane
     const size_t K = (size_t)a.K;
@@ -48,6 +49,8 @@ __device__ __forceinline__ float simulate(const RolloutArgs &a, int k, int sub, 
     // start of the interval.
     const float *up = a.controls + k;
     float nu0 = 0.0f, nu1 = 0.0f;
+    // the pair requested during interval n: interval min(n + 1, n1 - 1)
+    const float *unext = up + 2 * (size_t)max(min(a.n0 + 1, a.n1 - 1), 0) * K;
     if constexpr (!SAMPLED) {
         if (a.n0 < a.n1) {
             nu0 = up[(2 * (size_t)a.n0) * K];
@@ -99,7 +102,9 @@ __device__ __forceinline__ float simulate(const RolloutArgs &a, int k, int sub, 
         const float dd = clampf_nan(u0, -a.drate_max, a.drate_max);
         const float ax = a.accel_max * clampf_nan(u1, -1.0f, 1.0f);
 
-        for (int s = 0; s < a.S; ++s) {
+        // S1: one Euler substep per interval, no substep loop
+        const int S = S1 ? 1 : a.S;
+        for (int s = 0; s < S; ++s) {
             // goal test at the Euler node, before the step
             {
                 const float gdx = st[0] - a.goal_x, gdy = st[1] - a.goal_y;
@@ -111,13 +116,13 @@ __device__ __forceinline__ float simulate(const RolloutArgs &a, int k, int sub, 
             } else if constexpr (SAMPLED) {
                 euler_step<LANES>(a, arms, st, J, dd, ax);
             } else {
-                const size_t nn = (size_t)min(n + 1, a.n1 - 1);
                 euler_step<LANES>(a, arms, st, J, dd, ax, [&]() {
-                    nu0 = up[(2 * nn) * K];
-                    nu1 = up[(2 * nn + 1) * K];
+                    nu0 = unext[0];
+                    nu1 = unext[K];
                 });
             }
         }
+        if (n + 2 < a.n1) unext += 2 * K;
         if constexpr (CKPT) {
             if ((n + 1) % a.ckpt_every == 0 && n + 1 < a.N) {
                 ckpt_done = (n + 1) / a.ckpt_every;
@@ -193,7 +198,7 @@ __device__ __forceinline__ void argmin_epilogue(const RolloutArgs &a, unsigned l
 }
 
 template <int LANES, int BLOCK, bool CHUNK, bool SAMPLED = false, bool FUSED = false,
-          bool RK4 = false, bool CKPT = false>
+          bool RK4 = false, bool CKPT = false, bool S1 = false>
 __global__ __launch_bounds__(BLOCK) void rollout_srb(const RolloutArgs a) {
     const int gtid = blockIdx.x * BLOCK + threadIdx.x;
     const int sub = gtid & (LANES - 1);
@@ -203,7 +208,7 @@ __global__ __launch_bounds__(BLOCK) void rollout_srb(const RolloutArgs a) {
     // is complete for the DPP sums; they store nothing (and reach the fused
     // epilogue's barriers like every other lane).
     if (!store) k = a.K - 1;
-    const float J = simulate<LANES, CHUNK, SAMPLED, RK4, CKPT>(a, k, sub, store);
+    const float J = simulate<LANES, CHUNK, SAMPLED, RK4, CKPT, S1>(a, k, sub, store);
     if constexpr (FUSED)
         argmin_epilogue<BLOCK, SAMPLED>(a, (store && sub == 0) ? cost_key(J, k) : ~0ull,
                                         gridDim.x, a.sel_out_host, nullptr);
@@ -216,7 +221,7 @@ __global__ __launch_bounds__(BLOCK) void rollout_srb(const RolloutArgs a) {
 // its request's horizon also selects the request's plan: the entry's blocks
 // run the fused argmin epilogue on the slot's own key and ticket, and the
 // last of them writes the result to ring[slot] and the plan.
-template <int LANES, int BLOCK>
+template <int LANES, int BLOCK, bool S1>
 __global__ __launch_bounds__(BLOCK) void rollout_slots(const RolloutArgs *__restrict__ slots,
                                                        const TickTable t, int *bad,
                                                        SelectOut *ring, uint32_t seq) {
@@ -240,14 +245,16 @@ __global__ __launch_bounds__(BLOCK) void rollout_slots(const RolloutArgs *__rest
     int k = gtid / LANES;
     const bool store = k < a.K;
     if (!store) k = a.K - 1;
-    const float J = simulate<LANES, true>(a, k, sub, store);
+    const float J = simulate<LANES, true, false, false, false, S1>(a, k, sub, store);
     if (te.finalize)
         argmin_epilogue<BLOCK, false>(a, (store && sub == 0) ? cost_key(J, k) : ~0ull,
                                       (unsigned int)(block_end - te.block_start),
                                       ring + te.slot, bad + te.slot);
 }
 
-// Launch dispatch for one lane count L (block 64 or 256).
+// Launch dispatch for one lane count L (block 64 or 256). Euler launches
+// with one substep per interval (a.S == 1) use the S1 instantiations, which
+// carry no substep loop.
 template <int L>
 __forceinline__ hipError_t launch_rollout_lanes(const RolloutArgs &a, int block, bool chunk,
                                                 hipStream_t s) {
@@ -258,6 +265,9 @@ __forceinline__ hipError_t launch_rollout_lanes(const RolloutArgs &a, int block,
         if (a.method == 1)                                                                      \
             hipLaunchKernelGGL((rollout_srb<L, B, C, false, false, true>), dim3(grid), dim3(B),  \
                                0, s, a);                                                        \
+        else if (a.S == 1)                                                                      \
+            hipLaunchKernelGGL((rollout_srb<L, B, C, false, false, false, false, true>),         \
+                               dim3(grid), dim3(B), 0, s, a);                                   \
         else                                                                                    \
             hipLaunchKernelGGL((rollout_srb<L, B, C>), dim3(grid), dim3(B), 0, s, a);           \
         return hipGetLastError();                                                               \
@@ -287,15 +297,20 @@ template <int L>
 __forceinline__ hipError_t launch_ckpt_lanes(const RolloutArgs &a, int block, hipStream_t s) {
     const long long threads = (long long)a.K * L;
     const unsigned grid = (unsigned)((threads + block - 1) / block);
-    if (block == 64)
-        hipLaunchKernelGGL((rollout_srb<L, 64, false, false, false, false, true>), dim3(grid),
-                           dim3(64), 0, s, a);
-    else if (block == 256)
-        hipLaunchKernelGGL((rollout_srb<L, 256, false, false, false, false, true>), dim3(grid),
-                           dim3(256), 0, s, a);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+#define PLAN_LAUNCH(B)                                                                          \
+    if (block == B) {                                                                           \
+        if (a.S == 1)                                                                           \
+            hipLaunchKernelGGL((rollout_srb<L, B, false, false, false, false, true, true>),      \
+                               dim3(grid), dim3(B), 0, s, a);                                   \
+        else                                                                                    \
+            hipLaunchKernelGGL((rollout_srb<L, B, false, false, false, false, true>),            \
+                               dim3(grid), dim3(B), 0, s, a);                                   \
+        return hipGetLastError();                                                               \
+    }
+    PLAN_LAUNCH(64)
+    PLAN_LAUNCH(256)
+#undef PLAN_LAUNCH
+    return hipErrorInvalidValue;
 }
 
 template <int L>
@@ -303,33 +318,45 @@ __forceinline__ hipError_t launch_argmin_lanes(const RolloutArgs &a, int block, 
                                                hipStream_t s) {
     const long long threads = (long long)a.K * L;
     const unsigned grid = (unsigned)((threads + block - 1) / block);
-#define PLAN_LAUNCH(B, SMP)                                                                  \
-    if (block == B && sampled == SMP) {                                                      \
-        hipLaunchKernelGGL((rollout_srb<L, B, false, SMP, true>), dim3(grid), dim3(B), 0, s, a); \
-        return hipGetLastError();                                                            \
+#define PLAN_LAUNCH(B)                                                                          \
+    if (block == B) {                                                                           \
+        if (sampled)                                                                            \
+            hipLaunchKernelGGL((rollout_srb<L, B, false, true, true>), dim3(grid), dim3(B), 0,   \
+                               s, a);                                                           \
+        else if (a.S == 1)                                                                      \
+            hipLaunchKernelGGL((rollout_srb<L, B, false, false, true, false, false, true>),      \
+                               dim3(grid), dim3(B), 0, s, a);                                   \
+        else                                                                                    \
+            hipLaunchKernelGGL((rollout_srb<L, B, false, false, true>), dim3(grid), dim3(B), 0,  \
+                               s, a);                                                           \
+        return hipGetLastError();                                                               \
     }
-    PLAN_LAUNCH(64, false)
-    PLAN_LAUNCH(256, false)
-    PLAN_LAUNCH(64, true)
-    PLAN_LAUNCH(256, true)
+    PLAN_LAUNCH(64)
+    PLAN_LAUNCH(256)
 #undef PLAN_LAUNCH
     return hipErrorInvalidValue;
 }
 
+// s1: every slot of the tick integrates with one substep per interval.
 template <int L>
 __forceinline__ hipError_t launch_slots_lanes(const RolloutArgs *slots, const TickTable &t,
-                                              int *bad, SelectOut *ring, uint32_t seq,
+                                              int *bad, SelectOut *ring, uint32_t seq, bool s1,
                                               int block, hipStream_t s) {
     const unsigned grid = (unsigned)t.total_blocks;
-    if (block == 64)
-        hipLaunchKernelGGL((rollout_slots<L, 64>), dim3(grid), dim3(64), 0, s, slots, t, bad,
-                           ring, seq);
-    else if (block == 256)
-        hipLaunchKernelGGL((rollout_slots<L, 256>), dim3(grid), dim3(256), 0, s, slots, t, bad,
-                           ring, seq);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+#define PLAN_LAUNCH(B)                                                                          \
+    if (block == B) {                                                                           \
+        if (s1)                                                                                 \
+            hipLaunchKernelGGL((rollout_slots<L, B, true>), dim3(grid), dim3(B), 0, s, slots,    \
+                               t, bad, ring, seq);                                              \
+        else                                                                                    \
+            hipLaunchKernelGGL((rollout_slots<L, B, false>), dim3(grid), dim3(B), 0, s, slots,   \
+                               t, bad, ring, seq);                                              \
+        return hipGetLastError();                                                               \
+    }
+    PLAN_LAUNCH(64)
+    PLAN_LAUNCH(256)
+#undef PLAN_LAUNCH
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -342,7 +369,7 @@ hipError_t launch_ckpt_multi(const RolloutArgs &a, int lanes, int block, hipStre
 hipError_t launch_argmin_multi(const RolloutArgs &a, int lanes, int block, bool sampled,
                                hipStream_t s);
 hipError_t launch_slots_multi(const RolloutArgs *slots, const TickTable &t, int *bad,
-                              SelectOut *ring, uint32_t seq, int lanes, int block,
+                              SelectOut *ring, uint32_t seq, bool s1, int lanes, int block,
                               hipStream_t s);
 
 }  // namespace plan

@@ -31,10 +31,10 @@ hipError_t launch_argmin_multi(const RolloutArgs &a, int lanes, int block, bool 
 }
 
 hipError_t launch_slots_multi(const RolloutArgs *slots, const TickTable &t, int *bad,
-                              SelectOut *ring, uint32_t seq, int lanes, int block,
+                              SelectOut *ring, uint32_t seq, bool s1, int lanes, int block,
                               hipStream_t s) {
-    if (lanes == 2) return launch_slots_lanes<2>(slots, t, bad, ring, seq, block, s);
-    if (lanes == 4) return launch_slots_lanes<4>(slots, t, bad, ring, seq, block, s);
+    if (lanes == 2) return launch_slots_lanes<2>(slots, t, bad, ring, seq, s1, block, s);
+    if (lanes == 4) return launch_slots_lanes<4>(slots, t, bad, ring, seq, s1, block, s);
     return hipErrorInvalidValue;
 }
 

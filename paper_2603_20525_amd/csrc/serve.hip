@@ -324,8 +324,11 @@ static plan_status_t launch_step(plan_server *s) {
     s->ring_next = (s->ring_next + 1) % RING;
     s->seq = s->seq + 1u == 0u ? 1u : s->seq + 1u;
     st.seq = s->seq;
+    bool s1 = true;
+    for (int j = 0; j < t.count; ++j)
+        s1 = s1 && s->reqs[s->slots[t.e[j].slot].req].r.integ.substeps == 1;
     SHIP(s, plan::launch_rollout_slots(s->slot_args, t, s->bad, s->ring_host[st.ring], st.seq,
-                                       lanes, block, s->stream));
+                                       s1, lanes, block, s->stream));
     if (s->ev_pool.empty()) {
         hipEvent_t e;
         SHIP(s, hipEventCreateWithFlags(&e, hipEventDisableTiming));
