@@ -134,7 +134,6 @@ __global__ __launch_bounds__(BLOCK) void rollout_est(const RolloutArgs a) {
 #pragma unroll
     for (int q = 0; q < 7; ++q) st[q] = a.s0[q];
     float J = 0.0f;
-    bool done = false;
     const float *up = a.controls + k;
     // uniform trip counts: a candidate that reaches the goal stays frozen
     for (int n = 0; n < a.N; ++n) {
@@ -142,8 +141,8 @@ __global__ __launch_bounds__(BLOCK) void rollout_est(const RolloutArgs a) {
         const float ax = a.accel_max * clampf_nan(up[(2 * (size_t)n + 1) * K], -1.0f, 1.0f);
         for (int s = 0; s < a.S; ++s) {
             const float gdx = st[0] - a.goal_x, gdy = st[1] - a.goal_y;
-            done = done || fmaf(gdx, gdx, gdy * gdy) <= a.goal_r2;
-            if (done) continue;
+            // a candidate at its goal is frozen, so the test stays true
+            if (fmaf(gdx, gdx, gdy * gdy) <= a.goal_r2) continue;
             est_step(a, st, J, dd, ax);
         }
     }

@@ -40,7 +40,6 @@ __device__ __forceinline__ float simulate(const RolloutArgs &a, int k, int sub, 
         J = 0.0f;
     }
     float (&st)[13] = st0;
-    bool done = false;
 
     // materialised controls are read one interval ahead (the index is clamped
     // to [n0, n1)). The Euler step requests the next pair right after its
@@ -78,7 +77,7 @@ __device__ __forceinline__ float simulate(const RolloutArgs &a, int k, int sub, 
 
     // uniform trip counts: a candidate that reaches the goal stays in the
     // loop frozen (its lanes skip the steps), so the loops carry no
-    // per-lane exit bookkeeping
+    // per-lane exit or done-flag bookkeeping
     for (int n = a.n0; n < a.n1; ++n) {
         // zero-order hold: control n for the whole interval, restricted to the
         // admissible set (|delta_dot| <= limit, throttle in [-1, 1])
@@ -105,12 +104,12 @@ __device__ __forceinline__ float simulate(const RolloutArgs &a, int k, int sub, 
         // S1: one Euler substep per interval, no substep loop
         const int S = S1 ? 1 : a.S;
         for (int s = 0; s < S; ++s) {
-            // goal test at the Euler node, before the step
+            // goal test at the Euler node, before the step; a candidate at
+            // its goal is frozen, so the test stays true for it from then on
             {
                 const float gdx = st[0] - a.goal_x, gdy = st[1] - a.goal_y;
-                done = done || fmaf(gdx, gdx, gdy * gdy) <= a.goal_r2;
+                if (fmaf(gdx, gdx, gdy * gdy) <= a.goal_r2) continue;
             }
-            if (done) continue;
             if constexpr (RK4) {
                 rk4_step<LANES>(a, arms, st, J, dd, ax);
             } else if constexpr (SAMPLED) {
