@@ -21,8 +21,8 @@ namespace {
 // Bilinear (h, f_x, f_y, cost) at (Px, Py), clamp-to-edge; a NaN coordinate
 // clamps to the grid origin, so every index is inside the grid.
 __device__ __forceinline__ float4 bilinear(const RolloutArgs &a, float Px, float Py) {
-    const float u = fminf(fmaxf((Px - a.x0) * a.inv_res, 0.0f), a.umax);
-    const float v = fminf(fmaxf((Py - a.y0) * a.inv_res, 0.0f), a.vmax);
+    const float u = __builtin_amdgcn_fmed3f((Px - a.x0) * a.inv_res, 0.0f, a.umax);
+    const float v = __builtin_amdgcn_fmed3f((Py - a.y0) * a.inv_res, 0.0f, a.vmax);
     const int i = min((int)u, a.W - 2);
     const int j = min((int)v, a.H - 2);
     const float tx = u - (float)i, ty = v - (float)j;

@@ -30,10 +30,12 @@ __device__ __forceinline__ float group_sum(float v) {
     return v;
 }
 
-// NaN-propagating clamps (a NaN input stays NaN, as in the reference
-// arithmetic; the candidate is then scored +inf at the end).
+// NaN-propagating clamp (a NaN input stays NaN, as in the reference
+// arithmetic; the candidate is then scored +inf at the end). v_med3 returns
+// the clamped value for every non-NaN input, -0.0 included.
 __device__ __forceinline__ float clampf_nan(float x, float lo, float hi) {
-    return x < lo ? lo : (x > hi ? hi : x);
+    const float m = __builtin_amdgcn_fmed3f(x, lo, hi);
+    return x != x ? x : m;
 }
 
 // Attitude terms of the 3-2-1 rotation W <- B.
@@ -93,10 +95,11 @@ __device__ __forceinline__ Gather gather(const RolloutArgs &a, const Attitude &A
     const float Py = fmaf(A.R21, r.rx, fmaf(A.R22, r.ry, fmaf(A.R23, r.rz, y)));
     Gather g;
     g.Pz = fmaf(A.R31, r.rx, fmaf(A.R32, r.ry, fmaf(A.R33, r.rz, z)));
-    // clamp-to-edge; a NaN coordinate clamps to 0 through fmaxf, so the
-    // indices are always inside the grid
-    const float u = fminf(fmaxf((Px - a.x0) * a.inv_res, 0.0f), a.umax);
-    const float v = fminf(fmaxf((Py - a.y0) * a.inv_res, 0.0f), a.vmax);
+    // clamp-to-edge with v_med3, which on gfx950 gives min(max(x, 0), umax)
+    // for every input and maps a NaN coordinate to 0, so the indices are
+    // always inside the grid
+    const float u = __builtin_amdgcn_fmed3f((Px - a.x0) * a.inv_res, 0.0f, a.umax);
+    const float v = __builtin_amdgcn_fmed3f((Py - a.y0) * a.inv_res, 0.0f, a.vmax);
     const int i = min((int)u, a.W - 2);
     const int j = min((int)v, a.H - 2);
     g.tx = u - (float)i;
