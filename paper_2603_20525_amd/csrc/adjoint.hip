@@ -551,13 +551,15 @@ __global__ __launch_bounds__(64) void adjoint_backward(const RolloutArgs a, int 
         }
         float cu0 = up[(2 * (size_t)(n1 - 1)) * K], cu1 = up[(2 * (size_t)(n1 - 1) + 1) * K];
         float gdd = 0.0f, gax = 0.0f;
+        // (n, s): interval and substep of flat index i, stepped down with i
+        // (no divisions in the loop)
+        int n = n1 - 1, s = S - 1;
         for (int i = cnt - 1; i >= 0; --i) {
-            const int n = n0 + i / S;
             const float u0 = cu0, u1 = cu1;
             const float dd = clampf_nan(u0, -a.drate_max, a.drate_max);
             const float ax = a.accel_max * clampf_nan(u1, -1.0f, 1.0f);
             const int ip = max(i - 1, 0);
-            const size_t np = (size_t)(n0 + ip / S);
+            const size_t np = (size_t)(i == 0 ? n0 : (s > 0 ? n : n - 1));
             const float *slp = scratch + ((size_t)ip * 14) * K + k;
             float nxt[14], nu0, nu1;
             auto prefetch = [&]() {
@@ -577,7 +579,7 @@ __global__ __launch_bounds__(64) void adjoint_backward(const RolloutArgs a, int 
             } else {
                 prefetch();
             }
-            if (i == (n - n0) * S) {
+            if (s == 0) {
                 // first substep of interval n: its gradient is complete;
                 // through the admissible-set clamps (identity branch inside)
                 const bool in0 = !(u0 < -a.drate_max) && !(u0 > a.drate_max);
@@ -593,6 +595,12 @@ __global__ __launch_bounds__(64) void adjoint_backward(const RolloutArgs a, int 
             for (int q = 0; q < 14; ++q) cur[q] = nxt[q];
             cu0 = nu0;
             cu1 = nu1;
+            if (s == 0) {
+                s = S - 1;
+                --n;
+            } else {
+                --s;
+            }
         }
     }
 }
