@@ -113,8 +113,22 @@ __device__ __forceinline__ void write_plan(int kb, int N, int K, const float *co
             plan[2 * n + 1] = u1;
         }
     } else {
-        for (int e = tid; e < 2 * N; e += nthreads)
-            plan[e] = (kb < 0) ? 0.0f : clamp_ctrl(controls[(size_t)e * K + kb], e, drate_max);
+        // the column gather is one scattered load per plan entry: each thread
+        // issues four before it stores any, so their latencies overlap
+        constexpr int B = 4;
+        for (int e0 = tid; e0 < 2 * N; e0 += B * nthreads) {
+            float v[B];
+#pragma unroll
+            for (int q = 0; q < B; ++q) {
+                const int e = e0 + q * nthreads;
+                v[q] = (kb >= 0 && e < 2 * N) ? controls[(size_t)e * K + kb] : 0.0f;
+            }
+#pragma unroll
+            for (int q = 0; q < B; ++q) {
+                const int e = e0 + q * nthreads;
+                if (e < 2 * N) plan[e] = (kb < 0) ? 0.0f : clamp_ctrl(v[q], e, drate_max);
+            }
+        }
     }
 }
 
