@@ -170,12 +170,19 @@ def rows_leg():
     spec = P.sample_spec(P.PLAN_SAMPLE_UNIFORM, 6000, 0, (1.0, 0.0))
     J = torch.empty(K, device="cuda")
     plan = torch.empty(N, 2, device="cuda")
-    ms = _time_ms(lambda: pl.rollout_sampled_argmin(w.state0, spec, N, J, plan,
-                                                    want_result=False))
+    plan_call = lambda: pl.rollout_sampled_argmin(w.state0, spec, N, J, plan,  # noqa: E731
+                                                   want_result=False)
+    # default: the candidates run in locality order (sorting included)
+    ms = _time_ms(plan_call)
+    ordered = pl.get_order()
+    pl.set_order(P.PLAN_ORDER_OFF)
+    ms_unordered = _time_ms(plan_call)
+    pl.set_order(P.PLAN_ORDER_AUTO)
     steps = K * N * S
     out["paper_shape_sampled_one_launch"] = {
         "ms_per_plan": ms, "plans_per_s": 1e3 / ms, "samples_per_s": K * 1e3 / ms,
         "rollout_steps_per_s": steps * 1e3 / ms, "alu_frac": alu(OPS_PER_STEP * steps, ms / 1e3),
+        "locality_order": ordered, "ms_per_plan_unordered": ms_unordered,
         "paper_context": "11e6 samples/s (80 Hz) on an RTX 5000 Ada Mobile; about 21e6 on an "
                          "RTX 6000 Ada (other hardware, scanned terrain)"}
     # materialised samples of the same shape (generator only: 2 N K floats written)
@@ -189,10 +196,15 @@ def rows_leg():
     s7 = [s13[0], s13[1], s13[3], s13[7], s13[11], s13[12], s13[6]]
     ms_est = _time_ms(lambda: pl.rollout_est(s7, u, J))
     ms_srb = _time_ms(lambda: pl.rollout(w.state0, u, J))
+    pl.set_order(P.PLAN_ORDER_OFF)
+    ms_est_u = _time_ms(lambda: pl.rollout_est(s7, u, J))
+    ms_srb_u = _time_ms(lambda: pl.rollout(w.state0, u, J))
+    pl.set_order(P.PLAN_ORDER_AUTO)
     out["est_paper_shape"] = {
         "ms": ms_est, "rollout_steps_per_s": steps * 1e3 / ms_est,
         "alu_frac": alu(EST_OPS_PER_STEP * steps, ms_est / 1e3),
-        "srb_ms_same_samples": ms_srb}
+        "srb_ms_same_samples": ms_srb, "ms_unordered": ms_est_u,
+        "srb_ms_same_samples_unordered": ms_srb_u}
     pl.close()
 
     # RK4 on the single-plan workload

@@ -359,6 +359,29 @@ plan_status_t plan_set_launch(plan_ctx *ctx, int lanes, int block);
 /* Launch shape chosen for the most recent rollout. */
 plan_status_t plan_get_launch(const plan_ctx *ctx, int *lanes, int *block);
 
+/* Candidate order of full-horizon rollouts (plan_rollout, plan_rollout_est,
+ * plan_rollout_sampled, plan_rollout_argmin, plan_rollout_sampled_argmin).
+ * Gather locality, not the paper: a wave of one-lane candidates gathers the
+ * texels under 64 different vehicles each step, and when the candidates are
+ * far apart the texture path rather than arithmetic limits the rollout. With
+ * ordering, the library first sorts the candidates by a kinematic proxy of
+ * their trajectories (single-track kinematics under the model's control
+ * limits and a friction-limited curvature; lateral offsets at four times of
+ * the horizon, Morton-interleaved, stable radix sort; fourteen small
+ * launches on the context's stream) and runs each wave on neighbouring candidates;
+ * materialised controls are first gathered into lane order (a buffer of
+ * 2 max_N max_K floats that the context allocates on first use). Only the
+ * assignment of candidates to lanes changes: every output is bit-identical
+ * with and without ordering. Modes: PLAN_ORDER_AUTO (default: one-lane
+ * launches of at least 196 608 candidates, three waves per SIMD of the
+ * 256-CU device), PLAN_ORDER_OFF,
+ * PLAN_ORDER_ON (every full-horizon launch). Errors: PLAN_EINVAL for another
+ * mode. plan_get_order reports whether the most recent full-horizon rollout
+ * was ordered (1) or not (0). */
+enum { PLAN_ORDER_AUTO = 0, PLAN_ORDER_OFF = 1, PLAN_ORDER_ON = 2 };
+plan_status_t plan_set_order(plan_ctx *ctx, int mode);
+plan_status_t plan_get_order(const plan_ctx *ctx, int *ordered);
+
 /* Kernel timing: when enabled, HIP events bracket each rollout kernel on the
  * context's stream; plan_last_rollout_ms waits for the end event and returns
  * the kernel's elapsed time in milliseconds. */

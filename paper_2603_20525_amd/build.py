@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libplan.so")
 SOURCES = ["rollout.hip", "rollout_multilane.hip", "est.hip", "select.hip", "plan_api.hip",
-           "serve.hip", "adjoint.hip", "terrain_prep.hip"]
+           "serve.hip", "adjoint.hip", "terrain_prep.hip", "order.hip"]
 
 # Per-source flags. The two- and four-lane rollout kernels are scheduled for
 # instruction-level parallelism: at small K each SIMD holds at most one wave,

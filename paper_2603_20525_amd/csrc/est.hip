@@ -127,14 +127,15 @@ __device__ __forceinline__ void est_step(const RolloutArgs &a, float (&st)[7], f
 
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void rollout_est(const RolloutArgs a) {
-    const int k = blockIdx.x * BLOCK + threadIdx.x;
-    if (k >= a.K) return;
+    const int slot = blockIdx.x * BLOCK + threadIdx.x;
+    if (slot >= a.K) return;
+    const int k = a.order ? min(max(a.order[slot], 0), a.K - 1) : slot;
     const size_t K = (size_t)a.K;
     float st[7];
 #pragma unroll
     for (int q = 0; q < 7; ++q) st[q] = a.s0[q];
     float J = 0.0f;
-    const float *up = a.controls + k;
+    const float *up = a.controls_lane ? a.controls_lane + slot : a.controls + k;
     // uniform trip counts: a candidate that reaches the goal stays frozen
     for (int n = 0; n < a.N; ++n) {
         const float dd = clampf_nan(up[(2 * (size_t)n) * K], -a.drate_max, a.drate_max);

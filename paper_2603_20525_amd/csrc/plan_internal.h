@@ -78,7 +78,43 @@ struct RolloutArgs {
     float *plan;
     SelectOut *sel_out, *sel_out_host;
     uint32_t sel_seq;  // sequence number published with the host copy
+    // full-horizon launches: lane group i simulates candidate order[i]
+    // (a permutation of 0..K-1), or candidate i if order is nullptr; with an
+    // order, controls_lane (if not nullptr) holds the controls [N][2][K] in
+    // lane order (column i = candidate order[i]), so the reads stay coalesced
+    const int *order;
+    const float *controls_lane;
 };
+
+// Locality order of a full-horizon rollout (order.hip): the candidates
+// sorted by a kinematic proxy of their trajectories, so that each wave
+// gathers texels from nearby cells.
+struct OrderArgs {
+    int K, N;
+    const float *controls;  // [N][2][K], or nullptr: drawn from smp
+    SampleArgs smp;
+    float dt, drate_max, delta_max, accel_max, vx_min;
+    float inv_wheelbase, mu_g;  // 1 / (L_f + L_r), mu g
+    float delta0, vx0;          // initial steering angle and forward speed
+    // workspace (sized for the context's max_K)
+    float *lat;                 // [4][lat_stride] proxy lateral offsets
+    int lat_stride;             // max_K
+    unsigned *range;            // [8] ordered-bits minimum (0..3) and maximum (4..7)
+    unsigned *keys[2];          // [max_K] each
+    int *vals[2];               // [max_K] each; vals[0] receives the order
+    unsigned *hist;             // [256][tiles of K] digit counts, then offsets
+    int nt_max;                 // order_tiles(max_K)
+};
+
+// Scatter tiles of the order's radix sort for K candidates.
+int order_tiles(int max_K);
+// Reset the range (once, after allocation; each order leaves it reset).
+hipError_t launch_order_reset(const OrderArgs &o, hipStream_t s);
+// Fourteen launches: proxy, keys, and four histogram + scan + scatter passes.
+hipError_t launch_locality_order(const OrderArgs &o, hipStream_t s);
+// out[n][c][i] = controls[n][c][order[i]] for the N intervals of K candidates.
+hipError_t launch_permute_controls(const float *controls, const int *order, int K, int N,
+                                   float *out, hipStream_t s);
 
 // Texel (i, j) of the packed terrain: height, slopes by central differences
 // (one-sided on the border) and the costmap's rate. Returns false if the

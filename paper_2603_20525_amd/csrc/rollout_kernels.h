@@ -24,7 +24,8 @@ namespace {
 // keep their lane group complete.
 template <int LANES, bool CHUNK, bool SAMPLED = false, bool RK4 = false, bool CKPT = false,
           bool S1 = false>
-__device__ __forceinline__ float simulate(const RolloutArgs &a, int k, int sub, bool store) {
+__device__ __forceinline__ float simulate(const RolloutArgs &a, int k, int sub, bool store,
+                                          const float *up) {
     constexpr int WPL = 4 / LANES;  // wheels per lane
     const size_t K = (size_t)a.K;
 
@@ -46,7 +47,7 @@ __device__ __forceinline__ float simulate(const RolloutArgs &a, int k, int sub, 
     // texel gathers, so waiting for the texels does not wait for it and the
     // load stays in flight for the rest of the step; RK4 requests it at the
     // start of the interval.
-    const float *up = a.controls + k;
+    // up: this candidate's control column (interval n at up[2 n K], up[(2 n + 1) K])
     float nu0 = 0.0f, nu1 = 0.0f;
     // the pair requested during interval n: interval min(n + 1, n1 - 1)
     const float *unext = up + 2 * (size_t)max(min(a.n0 + 1, a.n1 - 1), 0) * K;
@@ -201,13 +202,23 @@ template <int LANES, int BLOCK, bool CHUNK, bool SAMPLED = false, bool FUSED = f
 __global__ __launch_bounds__(BLOCK) void rollout_srb(const RolloutArgs a) {
     const int gtid = blockIdx.x * BLOCK + threadIdx.x;
     const int sub = gtid & (LANES - 1);
-    int k = gtid / LANES;
-    const bool store = k < a.K;
+    int slot = gtid / LANES;
+    const bool store = slot < a.K;
     // Lanes past K simulate the last candidate again so that every lane group
     // is complete for the DPP sums; they store nothing (and reach the fused
     // epilogue's barriers like every other lane).
-    if (!store) k = a.K - 1;
-    const float J = simulate<LANES, CHUNK, SAMPLED, RK4, CKPT, S1>(a, k, sub, store);
+    if (!store) slot = a.K - 1;
+    int k = slot;
+    const float *up = a.controls + slot;
+    if constexpr (!CHUNK && !CKPT) {
+        if (a.order) {
+            // clamped so that a malformed order can only misassign, never
+            // address outside the candidate arrays
+            k = min(max(a.order[slot], 0), a.K - 1);
+            up = a.controls_lane ? a.controls_lane + slot : a.controls + k;
+        }
+    }
+    const float J = simulate<LANES, CHUNK, SAMPLED, RK4, CKPT, S1>(a, k, sub, store, up);
     if constexpr (FUSED)
         argmin_epilogue<BLOCK, SAMPLED>(a, (store && sub == 0) ? cost_key(J, k) : ~0ull,
                                         gridDim.x, a.sel_out_host, nullptr);
@@ -244,7 +255,8 @@ __global__ __launch_bounds__(BLOCK) void rollout_slots(const RolloutArgs *__rest
     int k = gtid / LANES;
     const bool store = k < a.K;
     if (!store) k = a.K - 1;
-    const float J = simulate<LANES, true, false, false, false, S1>(a, k, sub, store);
+    const float J = simulate<LANES, true, false, false, false, S1>(a, k, sub, store,
+                                                                   a.controls + k);
     if (te.finalize)
         argmin_epilogue<BLOCK, false>(a, (store && sub == 0) ? cost_key(J, k) : ~0ull,
                                       (unsigned int)(block_end - te.block_start),

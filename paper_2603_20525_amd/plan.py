@@ -18,6 +18,7 @@ PLAN_OK, PLAN_EINVAL, PLAN_ENOMEM, PLAN_EDEVICE, PLAN_ENOTERRAIN = 0, -1, -2, -3
 PLAN_ARGMIN, PLAN_SOFTMIN = 0, 1
 PLAN_SAMPLE_UNIFORM, PLAN_SAMPLE_GAUSSIAN = 0, 1
 PLAN_EULER, PLAN_RK4 = 0, 1
+PLAN_ORDER_AUTO, PLAN_ORDER_OFF, PLAN_ORDER_ON = 0, 1, 2
 STATUS_NAMES = {0: "PLAN_OK", -1: "PLAN_EINVAL", -2: "PLAN_ENOMEM", -3: "PLAN_EDEVICE",
                 -4: "PLAN_ENOTERRAIN"}
 
@@ -57,7 +58,8 @@ EXPORTS = ("plan_create", "plan_set_stream", "plan_set_cost", "plan_set_terrain"
            "plan_select", "plan_sample_controls", "plan_rollout_sampled", "plan_select_sampled",
            "plan_rollout_argmin", "plan_rollout_sampled_argmin",
            "plan_smooth_terrain", "plan_costmap_polygons",
-           "plan_set_launch", "plan_get_launch", "plan_enable_timing", "plan_last_rollout_ms",
+           "plan_set_launch", "plan_get_launch", "plan_set_order", "plan_get_order",
+           "plan_enable_timing", "plan_last_rollout_ms",
            "plan_destroy", "plan_last_error")
 
 _lib = None
@@ -98,6 +100,8 @@ def lib():
                                             C.c_float, C.c_int, vp]
         L.plan_set_launch.argtypes = [vp, C.c_int, C.c_int]
         L.plan_get_launch.argtypes = [vp, ip, ip]
+        L.plan_set_order.argtypes = [vp, C.c_int]
+        L.plan_get_order.argtypes = [vp, ip]
         L.plan_enable_timing.argtypes = [vp, C.c_int]
         L.plan_last_rollout_ms.argtypes = [vp, fp]
         L.plan_destroy.argtypes = [vp]
@@ -361,6 +365,18 @@ def plan_get_launch(ctx):
     return l.value, b.value
 
 
+def plan_set_order(ctx, mode: int = 0):
+    """Candidate order for gather locality: PLAN_ORDER_AUTO, _OFF or _ON."""
+    _check("plan_set_order", lib().plan_set_order(ctx, int(mode)), ctx)
+
+
+def plan_get_order(ctx) -> bool:
+    """Whether the most recent full-horizon rollout ran in locality order."""
+    o = C.c_int(0)
+    _check("plan_get_order", lib().plan_get_order(ctx, C.byref(o)), ctx)
+    return bool(o.value)
+
+
 def plan_enable_timing(ctx, on: bool = True):
     _check("plan_enable_timing", lib().plan_enable_timing(ctx, int(bool(on))), ctx)
 
@@ -466,6 +482,12 @@ class Planner:
 
     def get_launch(self):
         return plan_get_launch(self.ctx)
+
+    def set_order(self, mode=0):
+        plan_set_order(self.ctx, mode)
+
+    def get_order(self):
+        return plan_get_order(self.ctx)
 
 
 # ----------------------------------------------------- serving (plan_serve.h)

@@ -73,6 +73,9 @@ def test_calls_on_null_context_are_rejected(lib):
     assert lib.plan_select(None, 0, 0.0, None, None, 1, 1, None, None, None) == P.PLAN_EINVAL
     assert lib.plan_set_terrain(None, None, 2, 2, 0.0, 0.0, 1.0, None) == P.PLAN_EINVAL
     assert lib.plan_set_launch(None, 4, 64) == P.PLAN_EINVAL
+    assert lib.plan_set_order(None, P.PLAN_ORDER_ON) == P.PLAN_EINVAL
+    o = C.c_int(7)
+    assert lib.plan_get_order(None, C.byref(o)) == P.PLAN_EINVAL and o.value == 7
     assert lib.plan_set_stream(None, None) == P.PLAN_EINVAL
     assert lib.plan_set_cost(None, None) == P.PLAN_EINVAL
     assert lib.plan_enable_timing(None, 1) == P.PLAN_EINVAL

@@ -1,0 +1,126 @@
+"""GPU tests of the locality order: running the candidates of a full-horizon
+rollout in proxy-trajectory order changes only which lane simulates which
+candidate, so every output must be bit-identical to the unordered launch,
+and every candidate must be written exactly once (outputs start as NaN)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2603_20525_amd import inputs  # noqa: E402
+from paper_2603_20525_amd import plan as P  # noqa: E402
+from tests.test_est_gpu import est_state0  # noqa: E402
+from tests.test_parity_gpu import dev  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    P.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+def nan(*shape):
+    return torch.full(shape, float("nan"), device="cuda")
+
+
+class Ctx:
+    def __init__(self, w, max_K):
+        T = w.terrain
+        self.w = w
+        self.pl = P.Planner(w.vehicle, w.cost, w.integ, max_K, w.N, T.W, T.H)
+        self.pl.set_terrain(dev(T.height), T.x0, T.y0, T.res)
+
+    def run(self, mode, u, K=None):
+        """Every full-horizon entry point under one order mode."""
+        pl, w = self.pl, self.w
+        u = u if K is None else u[:, :, :K].contiguous()
+        N, _, K = u.shape
+        pl.set_order(mode)
+        out = {}
+        J, fs = nan(K), nan(13, K)
+        pl.rollout(w.state0, u, J, fs)
+        out["rollout"] = (J, fs, pl.get_order())
+        J, fs, plan = nan(K), nan(13, K), nan(N, 2)
+        r = pl.rollout_argmin(w.state0, u, J, plan, fs)
+        out["argmin"] = (J, fs, plan, r)
+        spec = P.sample_spec(P.PLAN_SAMPLE_UNIFORM, 77, 3, (1.0, 0.5))
+        J, fs, plan = nan(K), nan(13, K), nan(N, 2)
+        r = pl.rollout_sampled_argmin(w.state0, spec, N, J, plan, fs)
+        out["sampled_argmin"] = (J, fs, plan, r)
+        J, fs = nan(K), nan(13, K)
+        pl.rollout_sampled(w.state0, spec, N, J, fs)
+        out["sampled"] = (J, fs)
+        J, fs = nan(K), nan(7, K)
+        pl.rollout_est(est_state0(w.state0), u, J, fs)
+        out["est"] = (J, fs, pl.get_order())
+        torch.cuda.synchronize()
+        return out
+
+
+def assert_same(a, b, label):
+    for key in a:
+        for x, y in zip(a[key], b[key]):
+            if isinstance(x, torch.Tensor):
+                xh, yh = x.cpu().numpy(), y.cpu().numpy()
+                assert not np.isnan(xh).any(), f"{label} {key}: a candidate was not written"
+                np.testing.assert_array_equal(xh, yh, err_msg=f"{label} {key}")
+            elif isinstance(x, tuple):
+                assert x == y, f"{label} {key}: {x} != {y}"
+
+
+def test_ordered_outputs_equal_unordered_bitwise_ragged_tiles():
+    # 5000 candidates: three sort tiles, the last ragged; forced on
+    w = inputs.c2(K=5000, N=24)
+    c = Ctx(w, 5000)
+    u = dev(w.controls)
+    off = c.run(P.PLAN_ORDER_OFF, u)
+    on = c.run(P.PLAN_ORDER_ON, u)
+    assert not off["rollout"][2] and on["rollout"][2] and on["est"][2]
+    assert_same(off, on, "c2 K=5000")
+    c.pl.close()
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 5])
+def test_ordered_outputs_with_fewer_intervals_than_proxy_samples(N):
+    w = inputs.c1(K=300, N=N)
+    c = Ctx(w, 300)
+    u = dev(w.controls)
+    assert_same(c.run(P.PLAN_ORDER_OFF, u), c.run(P.PLAN_ORDER_ON, u), f"c1 N={N}")
+    c.pl.close()
+
+
+def test_single_candidate_ordered():
+    w = inputs.c1(K=1, N=10)
+    c = Ctx(w, 1)
+    u = dev(w.controls)
+    assert_same(c.run(P.PLAN_ORDER_OFF, u), c.run(P.PLAN_ORDER_ON, u), "K=1")
+    c.pl.close()
+
+
+def test_auto_orders_large_one_lane_launches_and_k_can_change():
+    # paper-shape candidates (uniform steering rates, 50 substeps) on a short
+    # horizon; the automatic mode orders the one-lane launch at K >= 196 608,
+    # and alternating sizes on one context reuse the sort's workspace
+    w = inputs.paper_shape(K=200000)
+    w.controls = np.ascontiguousarray(w.controls[:4])
+    c = Ctx(w, 200000)
+    u = dev(w.controls)
+    off_big = c.run(P.PLAN_ORDER_OFF, u)
+    off_small = c.run(P.PLAN_ORDER_OFF, u, K=5000)
+    auto_big = c.run(P.PLAN_ORDER_AUTO, u)
+    assert auto_big["rollout"][2] and auto_big["est"][2]
+    assert c.pl.get_launch()[0] == 1
+    auto_small = c.run(P.PLAN_ORDER_AUTO, u, K=5000)
+    assert not auto_small["rollout"][2]
+    on_small = c.run(P.PLAN_ORDER_ON, u, K=5000)
+    auto_big2 = c.run(P.PLAN_ORDER_AUTO, u)
+    assert_same(off_big, auto_big, "K=200000 auto")
+    assert_same(off_small, auto_small, "K=5000 auto")
+    assert_same(off_small, on_small, "K=5000 on after 200000")
+    assert_same(off_big, auto_big2, "K=200000 auto again")
+    c.pl.close()
