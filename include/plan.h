@@ -101,7 +101,8 @@ enum { PLAN_ARGMIN = 0, PLAN_SOFTMIN = 1 };
 
 /* Create a context on the current HIP device. max_K, max_N, max_W, max_H bound
  * the sizes later calls may use; the library allocates its workspace for them
- * once here (terrain texels 16*max_W*max_H bytes plus selection scratch).
+ * once here (terrain texels 16*max_W*max_H bytes, the candidate-order
+ * workspace about 32*max_K bytes, plus selection scratch).
  * hip_stream is a hipStream_t, or NULL for the default stream.
  * Errors: PLAN_EINVAL for NULL pointers, non-positive sizes or invalid
  * parameters (M, J, Lf+Lr, e, hR, dt <= 0, substeps < 1, non-finite values);
@@ -368,8 +369,10 @@ plan_status_t plan_get_launch(const plan_ctx *ctx, int *lanes, int *block);
  * their trajectories (single-track kinematics under the model's control
  * limits and a friction-limited curvature; lateral offsets at four times of
  * the horizon, Morton-interleaved, stable radix sort; fourteen small
- * launches on the context's stream) and runs each wave on neighbouring candidates;
- * materialised controls are first gathered into lane order (a buffer of
+ * launches on the context's stream) and runs each wave on neighbouring
+ * candidates, one lane per candidate (plan_set_launch's lane count applies
+ * to unordered launches, its workgroup size to both); materialised
+ * controls are first gathered into lane order (a buffer of
  * 2 max_N max_K floats that the context allocates on first use). Only the
  * assignment of candidates to lanes changes: every output is bit-identical
  * with and without ordering. Modes: PLAN_ORDER_AUTO (default: one-lane

@@ -349,17 +349,17 @@ enum class Kind { plain, chunk, sampled, fused, fused_sampled };
 // is smaller and, with the sorting, not reliably positive.
 constexpr int ORDER_AUTO_MIN_K = 196608;
 
-// Sort the candidates of a full-horizon launch by their proxy trajectories
-// and point a.order at the result, if the context's mode asks for it.
-// delta0 and vx0: the initial steering angle and forward speed.
-static plan_status_t maybe_order(plan_ctx *c, RolloutArgs &a, int lanes, float delta0,
-                                 float vx0) {
-    a.order = nullptr;
-    a.controls_lane = nullptr;
-    c->last_ordered = false;
-    const bool on = c->order_mode == PLAN_ORDER_ON ||
-                    (c->order_mode == PLAN_ORDER_AUTO && lanes == 1 && a.K >= ORDER_AUTO_MIN_K);
-    if (!on) return PLAN_OK;
+// Whether a full-horizon launch of K candidates at this lane count runs in
+// locality order (ordered launches then use one lane per candidate).
+static bool order_wanted(const plan_ctx *c, int K, int lanes) {
+    return c->order_mode == PLAN_ORDER_ON ||
+           (c->order_mode == PLAN_ORDER_AUTO && lanes == 1 && K >= ORDER_AUTO_MIN_K);
+}
+
+// Sort the candidates of a one-lane full-horizon launch by their proxy
+// trajectories and point a.order at the result. delta0 and vx0: the initial
+// steering angle and forward speed.
+static plan_status_t order_candidates(plan_ctx *c, RolloutArgs &a, float delta0, float vx0) {
     plan::OrderArgs o = c->ow;
     o.K = a.K;
     o.N = a.N;
@@ -400,13 +400,20 @@ static plan_status_t launch(plan_ctx *c, RolloutArgs &a, Kind kind) {
     auto_launch(a.K, &lanes, &block);
     if (c->lanes_opt) lanes = c->lanes_opt;
     if (c->block_opt) block = c->block_opt;
+    a.order = nullptr;
+    a.controls_lane = nullptr;
+    c->last_ordered = false;
+    const bool ordered = kind != Kind::chunk && order_wanted(c, a.K, lanes);
+    if (ordered && lanes != 1) {
+        lanes = 1;
+        block = c->block_opt ? c->block_opt : (((long long)a.K + 63) / 64 < 4096 ? 64 : 256);
+    }
     c->last_lanes = lanes;
     c->last_block = block;
     HIP_TRY(c, hipSetDevice(c->device));
     if (c->timing) HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
-    a.order = nullptr;
-    if (kind != Kind::chunk) {
-        const plan_status_t st = maybe_order(c, a, lanes, a.s0[12], a.s0[6]);
+    if (ordered) {
+        const plan_status_t st = order_candidates(c, a, a.s0[12], a.s0[6]);
         if (st != PLAN_OK) return st;
     }
     switch (kind) {
@@ -603,8 +610,11 @@ plan_status_t plan_rollout_est(plan_ctx *c, const float state0[7], const float *
     HIP_TRY(c, hipSetDevice(c->device));
     if (c->timing) HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
     // state (x, y, psi, v_y, omega_z, delta, v_x): one lane per candidate
-    const plan_status_t st = maybe_order(c, a, 1, state0[5], state0[6]);
-    if (st != PLAN_OK) return st;
+    c->last_ordered = false;
+    if (order_wanted(c, K, 1)) {
+        const plan_status_t st = order_candidates(c, a, state0[5], state0[6]);
+        if (st != PLAN_OK) return st;
+    }
     HIP_TRY(c, plan::launch_rollout_est(a, block, c->stream));
     if (c->timing) {
         HIP_TRY(c, hipEventRecord(c->ev1, c->stream));

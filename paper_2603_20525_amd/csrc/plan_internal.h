@@ -78,7 +78,7 @@ struct RolloutArgs {
     float *plan;
     SelectOut *sel_out, *sel_out_host;
     uint32_t sel_seq;  // sequence number published with the host copy
-    // full-horizon launches: lane group i simulates candidate order[i]
+    // one-lane full-horizon launches: lane i simulates candidate order[i]
     // (a permutation of 0..K-1), or candidate i if order is nullptr; with an
     // order, controls_lane (if not nullptr) holds the controls [N][2][K] in
     // lane order (column i = candidate order[i]), so the reads stay coalesced

@@ -210,7 +210,8 @@ __global__ __launch_bounds__(BLOCK) void rollout_srb(const RolloutArgs a) {
     if (!store) slot = a.K - 1;
     int k = slot;
     const float *up = a.controls + slot;
-    if constexpr (!CHUNK && !CKPT) {
+    if constexpr (LANES == 1 && !CHUNK && !CKPT) {
+        // ordered launches run one lane per candidate
         if (a.order) {
             // clamped so that a malformed order can only misassign, never
             // address outside the candidate arrays

@@ -79,7 +79,9 @@ def test_ordered_outputs_equal_unordered_bitwise_ragged_tiles():
     c = Ctx(w, 5000)
     u = dev(w.controls)
     off = c.run(P.PLAN_ORDER_OFF, u)
+    assert c.pl.get_launch()[0] == 4  # automatic shape at K = 5000
     on = c.run(P.PLAN_ORDER_ON, u)
+    assert c.pl.get_launch()[0] == 1  # ordered launches run one lane per candidate
     assert not off["rollout"][2] and on["rollout"][2] and on["est"][2]
     assert_same(off, on, "c2 K=5000")
     c.pl.close()
