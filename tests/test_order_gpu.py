@@ -51,7 +51,7 @@ class Ctx:
         spec = P.sample_spec(P.PLAN_SAMPLE_UNIFORM, 77, 3, (1.0, 0.5))
         J, fs, plan = nan(K), nan(13, K), nan(N, 2)
         r = pl.rollout_sampled_argmin(w.state0, spec, N, J, plan, fs)
-        out["sampled_argmin"] = (J, fs, plan, r)
+        out["sampled_argmin"] = (J, fs, plan, r, pl.get_order())
         J, fs = nan(K), nan(13, K)
         pl.rollout_sampled(w.state0, spec, N, J, fs)
         out["sampled"] = (J, fs)
@@ -118,7 +118,13 @@ def test_auto_orders_large_one_lane_launches_and_k_can_change():
     assert auto_big["rollout"][2] and auto_big["est"][2]
     assert c.pl.get_launch()[0] == 1
     auto_small = c.run(P.PLAN_ORDER_AUTO, u, K=5000)
-    assert not auto_small["rollout"][2]
+    assert not auto_small["rollout"][2] and not auto_small["sampled_argmin"][4]
+    # between the two automatic thresholds only the in-kernel-sampled
+    # launches are ordered
+    off_mid = c.run(P.PLAN_ORDER_OFF, u, K=120000)
+    auto_mid = c.run(P.PLAN_ORDER_AUTO, u, K=120000)
+    assert not auto_mid["rollout"][2] and auto_mid["sampled_argmin"][4]
+    assert_same(off_mid, auto_mid, "K=120000 auto")
     on_small = c.run(P.PLAN_ORDER_ON, u, K=5000)
     auto_big2 = c.run(P.PLAN_ORDER_AUTO, u)
     assert_same(off_big, auto_big, "K=200000 auto")
