@@ -372,8 +372,9 @@ plan_status_t plan_get_launch(const plan_ctx *ctx, int *lanes, int *block);
  * launches on the context's stream) and runs each wave on neighbouring
  * candidates, one lane per candidate (plan_set_launch's lane count applies
  * to unordered launches, its workgroup size to both); materialised
- * controls are first gathered into lane order (a buffer of
- * 2 max_N max_K floats that the context allocates on first use). Only the
+ * controls are first gathered into lane order (a buffer of 2 N K floats
+ * that the context grows on demand; without it the controls are read in
+ * place, with the same results). Only the
  * assignment of candidates to lanes changes: every output is bit-identical
  * with and without ordering. Modes: PLAN_ORDER_AUTO (default: one-lane
  * launches of at least 196 608 candidates, three waves per SIMD of the

@@ -50,7 +50,8 @@ struct plan_ctx {
     int order_mode = PLAN_ORDER_AUTO;
     bool last_ordered = false;
     plan::OrderArgs ow{};
-    float *ctrl_lane = nullptr;  // [max_N][2][max_K], allocated on first use
+    float *ctrl_lane = nullptr;  // lane-ordered controls, grown on demand
+    size_t ctrl_lane_floats = 0;
     // terrain preparation: intermediate grid of the separable smoothing
     float *smooth_tmp = nullptr;
     // adjoint workspace (grown on demand): state, checkpoints, segment scratch
@@ -382,18 +383,29 @@ static plan_status_t order_candidates(plan_ctx *c, RolloutArgs &a, float delta0,
     a.order = c->ow.vals[0];
     if (a.controls) {
         // materialised controls: one gather into lane order keeps the
-        // rollout's control reads coalesced
-        if (!c->ctrl_lane) {
-            const hipError_t e =
-                hipMalloc(&c->ctrl_lane, sizeof(float) * 2 * (size_t)c->max_N * c->max_K);
-            if (e != hipSuccess) {
-                c->ctrl_lane = nullptr;
-                return hip_fail(c, "hipMalloc(lane-ordered controls)", e);
+        // rollout's control reads coalesced. The copy grows on demand; if it
+        // cannot be allocated, the rollout reads the controls in place
+        // (scattered, same results).
+        const size_t need = 2 * (size_t)a.N * a.K;
+        if (c->ctrl_lane_floats < need) {
+            if (c->ctrl_lane) {
+                // the previous copy may still be read by a launch in flight
+                HIP_TRY(c, hipStreamSynchronize(c->stream));
+                HIP_TRY(c, hipFree(c->ctrl_lane));
             }
+            c->ctrl_lane = nullptr;
+            c->ctrl_lane_floats = 0;
+            if (hipMalloc(&c->ctrl_lane, sizeof(float) * need) == hipSuccess)
+                c->ctrl_lane_floats = need;
+            else
+                c->ctrl_lane = nullptr;
+            (void)hipGetLastError();  // an allocation failure is not sticky
         }
-        HIP_TRY(c, plan::launch_permute_controls(a.controls, a.order, a.K, a.N, c->ctrl_lane,
-                                                 c->stream));
-        a.controls_lane = c->ctrl_lane;
+        if (c->ctrl_lane) {
+            HIP_TRY(c, plan::launch_permute_controls(a.controls, a.order, a.K, a.N, c->ctrl_lane,
+                                                     c->stream));
+            a.controls_lane = c->ctrl_lane;
+        }
     }
     c->last_ordered = true;
     return PLAN_OK;

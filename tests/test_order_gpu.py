@@ -132,3 +132,21 @@ def test_auto_orders_large_one_lane_launches_and_k_can_change():
     assert_same(off_small, on_small, "K=5000 on after 200000")
     assert_same(off_big, auto_big2, "K=200000 auto again")
     c.pl.close()
+
+
+def test_lane_ordered_controls_grow_between_calls():
+    # the lane-ordered copy of the controls is grown on demand: a small
+    # ordered launch, then a larger one (regrow), then the small one again
+    w = inputs.c2(K=6000, N=30)
+    c = Ctx(w, 6000)
+    u = dev(w.controls)
+    small, large = u[:10].contiguous(), u
+    off_s = c.run(P.PLAN_ORDER_OFF, small, K=1500)
+    off_l = c.run(P.PLAN_ORDER_OFF, large)
+    on_s = c.run(P.PLAN_ORDER_ON, small, K=1500)
+    on_l = c.run(P.PLAN_ORDER_ON, large)
+    on_s2 = c.run(P.PLAN_ORDER_ON, small, K=1500)
+    assert_same(off_s, on_s, "N=10 K=1500")
+    assert_same(off_l, on_l, "N=30 K=6000 after regrow")
+    assert_same(off_s, on_s2, "N=10 K=1500 again")
+    c.pl.close()
