@@ -150,3 +150,52 @@ def test_lane_ordered_controls_grow_between_calls():
     assert_same(off_l, on_l, "N=30 K=6000 after regrow")
     assert_same(off_s, on_s2, "N=10 K=1500 again")
     c.pl.close()
+
+
+def test_ordered_rk4_rollout_bitwise():
+    # fourth-order Runge-Kutta through plan_rollout (its one-lane kernel
+    # carries the order like the Euler kernels)
+    w = inputs.c2(K=3000, N=20)
+    w.integ = dict(w.integ, method=P.PLAN_RK4)
+    T = w.terrain
+    pl = P.Planner(w.vehicle, w.cost, w.integ, w.K, w.N, T.W, T.H)
+    pl.set_terrain(dev(T.height), T.x0, T.y0, T.res)
+    u = dev(w.controls)
+    out = {}
+    for mode in (P.PLAN_ORDER_OFF, P.PLAN_ORDER_ON):
+        pl.set_order(mode)
+        J, fs = nan(w.K), nan(13, w.K)
+        pl.rollout(w.state0, u, J, fs)
+        torch.cuda.synchronize()
+        out[mode] = (J.cpu().numpy(), fs.cpu().numpy(), pl.get_order())
+    assert out[P.PLAN_ORDER_ON][2] and not out[P.PLAN_ORDER_OFF][2]
+    for a, b in zip(out[P.PLAN_ORDER_OFF][:2], out[P.PLAN_ORDER_ON][:2]):
+        assert not np.isnan(b).any()
+        np.testing.assert_array_equal(a, b)
+    pl.close()
+
+
+def test_ordered_gaussian_draws_with_nominal_bitwise():
+    # the proxy draws the same Gaussian controls as the rollout, around a
+    # nominal sequence, with candidate 0 kept on the nominal
+    w = inputs.c2(K=4000, N=16)
+    T = w.terrain
+    pl = P.Planner(w.vehicle, w.cost, w.integ, w.K, w.N, T.W, T.H)
+    pl.set_terrain(dev(T.height), T.x0, T.y0, T.res)
+    nominal = dev(np.stack([0.2 * np.sin(np.arange(16) / 3.0),
+                            0.3 * np.ones(16)], axis=1))
+    spec = P.sample_spec(P.PLAN_SAMPLE_GAUSSIAN, 91, 2, (0.5, 0.2), nominal=nominal,
+                         keep_nominal=True, N=16)
+    res = {}
+    for mode in (P.PLAN_ORDER_OFF, P.PLAN_ORDER_ON):
+        pl.set_order(mode)
+        J, fs, plan = nan(w.K), nan(13, w.K), nan(16, 2)
+        r = pl.rollout_sampled_argmin(w.state0, spec, 16, J, plan, fs)
+        torch.cuda.synchronize()
+        res[mode] = (J.cpu().numpy(), fs.cpu().numpy(), plan.cpu().numpy(), r)
+    off, on = res[P.PLAN_ORDER_OFF], res[P.PLAN_ORDER_ON]
+    assert off[3] == on[3]
+    for a, b in zip(off[:3], on[:3]):
+        assert not np.isnan(b).any()
+        np.testing.assert_array_equal(a, b)
+    pl.close()
