@@ -22,6 +22,7 @@ namespace {
 
 constexpr int ORDER_TILE = 2048;       // elements per scatter workgroup (256 threads x 8)
 constexpr int ORDER_BLOCK = 256;
+static_assert(ORDER_BLOCK == 256, "the scatter scans the 256 digit totals with one thread each");
 constexpr int ORDER_PROXY_SUB = 4;     // proxy substeps per control interval
 
 // IEEE float <-> unsigned with the same order (for atomic min / max).
@@ -153,61 +154,39 @@ __global__ __launch_bounds__(ORDER_BLOCK) void order_hist(OrderArgs o, int p) {
     o.hist[(size_t)threadIdx.x * nt + blockIdx.x] = cnt[threadIdx.x];
 }
 
-// Exclusive scan of hist[digit][tile] in digit-major order: the start of
-// each tile's run of each digit in the output. One workgroup walks the table
-// in chunks of 1024 x 8 entries, carrying the running total.
-__global__ __launch_bounds__(1024) void order_scan(OrderArgs o) {
-    constexpr int P = 8;
-    __shared__ unsigned wsum[16];
-    unsigned *h = o.hist;
-    const int total = 256 * ((o.K + ORDER_TILE - 1) / ORDER_TILE);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+// Per-digit exclusive scan of hist[digit][tile] over the tiles (in place)
+// and the digit's total: one wave per digit, 64 tiles per step.
+__global__ __launch_bounds__(ORDER_BLOCK) void order_scan(OrderArgs o) {
+    const int lane = threadIdx.x & 63;
+    const int d = blockIdx.x * (ORDER_BLOCK / 64) + (threadIdx.x >> 6);
+    const int nt = (o.K + ORDER_TILE - 1) / ORDER_TILE;
+    unsigned *h = o.hist + (size_t)d * nt;
     unsigned carry = 0u;
-    for (int c0 = 0; c0 < total; c0 += 1024 * P) {
-        const int i0 = c0 + (int)threadIdx.x * P;
-        unsigned v[P];
-        unsigned s = 0u;
+    for (int t0 = 0; t0 < nt; t0 += 64) {
+        const int t = t0 + lane;
+        const unsigned c = t < nt ? h[t] : 0u;
+        unsigned x = c;  // inclusive scan over the wave
 #pragma unroll
-        for (int q = 0; q < P; ++q) {
-            v[q] = i0 + q < total ? h[i0 + q] : 0u;
-            s += v[q];
+        for (int off = 1; off < 64; off <<= 1) {
+            const unsigned y = __shfl_up(x, off);
+            if (lane >= off) x += y;
         }
-        unsigned x = s;  // inclusive scan over the wave
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const unsigned y = __shfl_up(x, d);
-            if (lane >= d) x += y;
-        }
-        if (lane == 63) wsum[wv] = x;
-        __syncthreads();
-        if (threadIdx.x < 16) {
-            unsigned w = wsum[threadIdx.x];
-#pragma unroll
-            for (int d = 1; d < 16; d <<= 1) {
-                const unsigned y = __shfl_up(w, d, 16);
-                if ((int)threadIdx.x >= d) w += y;
-            }
-            wsum[threadIdx.x] = w;
-        }
-        __syncthreads();
-        unsigned run = carry + (wv ? wsum[wv - 1] : 0u) + (x - s);
-#pragma unroll
-        for (int q = 0; q < P; ++q) {
-            if (i0 + q < total) h[i0 + q] = run;
-            run += v[q];
-        }
-        carry += wsum[15];
-        __syncthreads();
+        if (t < nt) h[t] = carry + x - c;
+        carry += __shfl(x, 63);
     }
+    if (lane == 0) o.dtotal[d] = carry;
 }
 
-// Stable scatter of one tile by digit p. Each wave ranks its 512 elements in
-// eight rounds of 64: the lanes holding the same digit are found with eight
+// Stable scatter of one tile by digit p. The digits' output bases come from
+// an exclusive scan of the 256 digit totals, the tile's start within each
+// digit from the per-digit scan. Each wave ranks its 512 elements in eight
+// rounds of 64: the lanes holding the same digit are found with eight
 // ballots, and a per-wave, per-digit count in LDS carries the rank across
 // rounds. The last pass writes only the candidate order and resets the
 // offset range for the next call.
 __global__ __launch_bounds__(ORDER_BLOCK) void order_scatter(OrderArgs o, int p) {
     __shared__ unsigned cnt[ORDER_BLOCK / 64][256];
+    __shared__ unsigned dbase[256], wtot[ORDER_BLOCK / 64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int src = p & 1;
     const unsigned *kin = o.keys[src];
@@ -220,6 +199,21 @@ __global__ __launch_bounds__(ORDER_BLOCK) void order_scatter(OrderArgs o, int p)
     const int shift = 8 * p;
     for (int i = threadIdx.x; i < (ORDER_BLOCK / 64) * 256; i += ORDER_BLOCK)
         (&cnt[0][0])[i] = 0u;
+    {
+        // exclusive scan of the digit totals (ORDER_BLOCK = 256 threads, one per digit)
+        const unsigned c = o.dtotal[threadIdx.x];
+        unsigned x = c;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const unsigned y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wtot[wv] = x;
+        __syncthreads();
+        unsigned before = 0u;
+        for (int w = 0; w < wv; ++w) before += wtot[w];
+        dbase[threadIdx.x] = before + x - c;
+    }
     __syncthreads();
 
     constexpr int R = ORDER_TILE / ORDER_BLOCK;  // rounds per wave
@@ -251,7 +245,7 @@ __global__ __launch_bounds__(ORDER_BLOCK) void order_scatter(OrderArgs o, int p)
     {
         // per-digit start of each wave's elements in the output
         const int d = threadIdx.x;
-        unsigned run = off[(size_t)d * nt + tile];
+        unsigned run = dbase[d] + off[(size_t)d * nt + tile];
 #pragma unroll
         for (int w = 0; w < ORDER_BLOCK / 64; ++w) {
             const unsigned c = cnt[w][d];
@@ -313,7 +307,7 @@ hipError_t launch_locality_order(const OrderArgs &o, hipStream_t s) {
     const unsigned nt = (unsigned)order_tiles(o.K);
     for (int p = 0; p < 4; ++p) {
         hipLaunchKernelGGL(order_hist, dim3(nt), dim3(ORDER_BLOCK), 0, s, o, p);
-        hipLaunchKernelGGL(order_scan, dim3(1), dim3(1024), 0, s, o);
+        hipLaunchKernelGGL(order_scan, dim3(256 / (ORDER_BLOCK / 64)), dim3(ORDER_BLOCK), 0, s, o);
         hipLaunchKernelGGL(order_scatter, dim3(nt), dim3(ORDER_BLOCK), 0, s, o, p);
     }
     return hipGetLastError();

@@ -111,6 +111,7 @@ static void release(plan_ctx *c) {
         (void)hipFree(c->ow.vals[i]);
     }
     (void)hipFree(c->ow.hist);
+    (void)hipFree(c->ow.dtotal);
     if (c->sel_host) (void)hipHostFree(c->sel_host);
     if (c->bad_host) (void)hipHostFree(c->bad_host);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -292,6 +293,7 @@ plan_status_t plan_create(plan_ctx **out, const plan_vehicle_t *veh, const plan_
         CREATE_TRY(hipMalloc(&c->ow.vals[i], sizeof(int) * (size_t)max_K));
     }
     CREATE_TRY(hipMalloc(&c->ow.hist, sizeof(unsigned) * 256 * (size_t)c->ow.nt_max));
+    CREATE_TRY(hipMalloc(&c->ow.dtotal, sizeof(unsigned) * 256));
     CREATE_TRY(plan::launch_order_reset(c->ow, c->stream));
     CREATE_TRY(hipEventCreate(&c->ev0));
     CREATE_TRY(hipEventCreate(&c->ev1));

@@ -102,7 +102,8 @@ struct OrderArgs {
     unsigned *range;            // [8] ordered-bits minimum (0..3) and maximum (4..7)
     unsigned *keys[2];          // [max_K] each
     int *vals[2];               // [max_K] each; vals[0] receives the order
-    unsigned *hist;             // [256][tiles of K] digit counts, then offsets
+    unsigned *hist;             // [256][tiles of K] digit counts, then per-digit offsets
+    unsigned *dtotal;           // [256] digit totals of the current pass
     int nt_max;                 // order_tiles(max_K)
 };
 
