@@ -24,6 +24,9 @@ constexpr int ORDER_TILE = 2048;       // elements per scatter workgroup (256 th
 constexpr int ORDER_BLOCK = 256;
 static_assert(ORDER_BLOCK == 256, "the scatter scans the 256 digit totals with one thread each");
 constexpr int ORDER_PROXY_SUB = 4;     // proxy substeps per control interval
+// proxy workgroups: large, so that few atomics per value fold the range
+// (same-address atomics from every workgroup serialise)
+constexpr int ORDER_PROXY_BLOCK = 1024;
 
 // IEEE float <-> unsigned with the same order (for atomic min / max).
 __device__ __forceinline__ unsigned float_to_ordered(float f) {
@@ -41,9 +44,9 @@ __global__ void order_reset(OrderArgs o) {
 // Proxy trajectory of candidate k: lateral offsets after intervals
 // (m+1) N / 4 - 1, m = 0..3; their range goes to o.range by atomic min / max.
 template <bool SAMPLED>
-__global__ __launch_bounds__(ORDER_BLOCK) void order_proxy(OrderArgs o) {
-    __shared__ float red[8][ORDER_BLOCK / 64];
-    const int k = blockIdx.x * ORDER_BLOCK + threadIdx.x;
+__global__ __launch_bounds__(ORDER_PROXY_BLOCK) void order_proxy(OrderArgs o) {
+    __shared__ float red[8][ORDER_PROXY_BLOCK / 64];
+    const int k = blockIdx.x * ORDER_PROXY_BLOCK + threadIdx.x;
     float lat[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     const bool active = k < o.K;
     if (active) {
@@ -99,7 +102,7 @@ __global__ __launch_bounds__(ORDER_BLOCK) void order_proxy(OrderArgs o) {
     if (threadIdx.x < 8) {
         const int q = threadIdx.x;
         float r = red[q][0];
-        for (int w = 1; w < ORDER_BLOCK / 64; ++w)
+        for (int w = 1; w < ORDER_PROXY_BLOCK / 64; ++w)
             r = q < 4 ? fminf(r, red[q][w]) : fmaxf(r, red[q][w]);
         if (isfinite(r)) {
             if (q < 4)
@@ -298,11 +301,12 @@ hipError_t launch_order_reset(const OrderArgs &o, hipStream_t s) {
 
 hipError_t launch_locality_order(const OrderArgs &o, hipStream_t s) {
     if (o.K < 1 || o.K > o.lat_stride || order_tiles(o.K) > o.nt_max) return hipErrorInvalidValue;
-    const unsigned gk = (unsigned)((o.K + ORDER_BLOCK - 1) / ORDER_BLOCK);
+    const unsigned gp = (unsigned)((o.K + ORDER_PROXY_BLOCK - 1) / ORDER_PROXY_BLOCK);
     if (o.controls)
-        hipLaunchKernelGGL((order_proxy<false>), dim3(gk), dim3(ORDER_BLOCK), 0, s, o);
+        hipLaunchKernelGGL((order_proxy<false>), dim3(gp), dim3(ORDER_PROXY_BLOCK), 0, s, o);
     else
-        hipLaunchKernelGGL((order_proxy<true>), dim3(gk), dim3(ORDER_BLOCK), 0, s, o);
+        hipLaunchKernelGGL((order_proxy<true>), dim3(gp), dim3(ORDER_PROXY_BLOCK), 0, s, o);
+    const unsigned gk = (unsigned)((o.K + ORDER_BLOCK - 1) / ORDER_BLOCK);
     hipLaunchKernelGGL(order_keys, dim3(gk), dim3(ORDER_BLOCK), 0, s, o);
     const unsigned nt = (unsigned)order_tiles(o.K);
     for (int p = 0; p < 4; ++p) {
