@@ -194,6 +194,9 @@ def rows_leg():
     # extended single-track formulation at the same shape (materialised samples)
     s13 = w.state0
     s7 = [s13[0], s13[1], s13[3], s13[7], s13[11], s13[12], s13[6]]
+    # materialised controls are ordered on request (the automatic mode orders
+    # in-kernel uniform draws only); both orders are reported
+    pl.set_order(P.PLAN_ORDER_ON)
     ms_est = _time_ms(lambda: pl.rollout_est(s7, u, J))
     ms_srb = _time_ms(lambda: pl.rollout(w.state0, u, J))
     pl.set_order(P.PLAN_ORDER_OFF)

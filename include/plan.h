@@ -376,10 +376,11 @@ plan_status_t plan_get_launch(const plan_ctx *ctx, int *lanes, int *block);
  * that the context grows on demand; without it the controls are read in
  * place, with the same results). Only the
  * assignment of candidates to lanes changes: every output is bit-identical
- * with and without ordering. Modes: PLAN_ORDER_AUTO (default: one-lane
- * launches of at least 196 608 candidates, three waves per SIMD of the
- * 256-CU device, or 98 304 when the controls are drawn in the kernel),
- * PLAN_ORDER_OFF,
+ * with and without ordering. Ordering pays when the candidates of a wave
+ * spread far apart, as with the paper's uniform steering-rate samples; with
+ * candidates that stay close (Gaussian samples around a nominal) it was
+ * slower. Modes: PLAN_ORDER_AUTO (default: launches that draw uniform
+ * samples in the kernel, from 49 152 candidates on), PLAN_ORDER_OFF,
  * PLAN_ORDER_ON (every full-horizon launch). Errors: PLAN_EINVAL for another
  * mode. plan_get_order reports whether the most recent full-horizon rollout
  * was ordered (1) or not (0). */

@@ -345,22 +345,23 @@ plan_status_t plan_set_terrain(plan_ctx *c, const float *height_dev, int W, int 
 
 enum class Kind { plain, chunk, sampled, fused, fused_sampled };
 
-// Automatic locality order for one-lane launches. Materialised controls:
-// from three one-lane waves per SIMD of a 256-CU device (1024 SIMDs x 64
-// lanes x 3), where the texture path limits the rollout and the order gains
-// about a quarter of the kernel time for about 0.2 ms of sorting and
-// permuting; below it the gain was not reliably positive. Controls drawn in
-// the kernel (no permutation, no control reads): from one and a half waves
-// per SIMD, where the measured gain was 14 % and more.
-constexpr int ORDER_AUTO_MIN_K = 196608;
-constexpr int ORDER_AUTO_MIN_K_SAMPLED = 98304;
+// Automatic locality order: launches that draw uniform samples in the kernel
+// (the paper's sampling, steering rates spread over the admissible set), from
+// this many candidates on. There the candidates of a wave spread over tens
+// of metres and ordering them at one lane per candidate beats the unordered
+// automatic shape (at the paper's shape by about a quarter; from 49 152
+// candidates on at all). Candidates that stay close (Gaussian samples around
+// a nominal) were slower ordered, and the spread of materialised controls is
+// unknown, so those launches are ordered only on request.
+constexpr int ORDER_AUTO_MIN_K_UNIFORM = 49152;
 
 // Whether a full-horizon launch of K candidates at this lane count runs in
 // locality order (ordered launches then use one lane per candidate).
-static bool order_wanted(const plan_ctx *c, int K, int lanes, bool sampled) {
+// smp: the generator of a launch that draws its controls, else nullptr.
+static bool order_wanted(const plan_ctx *c, int K, const plan::SampleArgs *smp) {
     return c->order_mode == PLAN_ORDER_ON ||
-           (c->order_mode == PLAN_ORDER_AUTO && lanes == 1 &&
-            K >= (sampled ? ORDER_AUTO_MIN_K_SAMPLED : ORDER_AUTO_MIN_K));
+           (c->order_mode == PLAN_ORDER_AUTO && smp && smp->kind == PLAN_SAMPLE_UNIFORM &&
+            K >= ORDER_AUTO_MIN_K_UNIFORM);
 }
 
 // Sort the candidates of a one-lane full-horizon launch by their proxy
@@ -421,9 +422,8 @@ static plan_status_t launch(plan_ctx *c, RolloutArgs &a, Kind kind) {
     a.order = nullptr;
     a.controls_lane = nullptr;
     c->last_ordered = false;
-    const bool ordered =
-        kind != Kind::chunk &&
-        order_wanted(c, a.K, lanes, kind == Kind::sampled || kind == Kind::fused_sampled);
+    const bool sampled = kind == Kind::sampled || kind == Kind::fused_sampled;
+    const bool ordered = kind != Kind::chunk && order_wanted(c, a.K, sampled ? &a.smp : nullptr);
     if (ordered && lanes != 1) {
         lanes = 1;
         block = c->block_opt ? c->block_opt : (((long long)a.K + 63) / 64 < 4096 ? 64 : 256);
@@ -631,7 +631,7 @@ plan_status_t plan_rollout_est(plan_ctx *c, const float state0[7], const float *
     if (c->timing) HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
     // state (x, y, psi, v_y, omega_z, delta, v_x): one lane per candidate
     c->last_ordered = false;
-    if (order_wanted(c, K, 1, false)) {
+    if (order_wanted(c, K, nullptr)) {
         const plan_status_t st = order_candidates(c, a, state0[5], state0[6]);
         if (st != PLAN_OK) return st;
     }

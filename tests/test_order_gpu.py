@@ -104,10 +104,11 @@ def test_single_candidate_ordered():
     c.pl.close()
 
 
-def test_auto_orders_large_one_lane_launches_and_k_can_change():
+def test_auto_orders_large_uniform_sampled_launches_and_k_can_change():
     # paper-shape candidates (uniform steering rates, 50 substeps) on a short
-    # horizon; the automatic mode orders the one-lane launch at K >= 196 608,
-    # and alternating sizes on one context reuse the sort's workspace
+    # horizon; the automatic mode orders launches that draw uniform samples
+    # from K = 49 152 on (at one lane per candidate) and nothing else, and
+    # alternating sizes on one context reuse the sort's workspace
     w = inputs.paper_shape(K=200000)
     w.controls = np.ascontiguousarray(w.controls[:4])
     c = Ctx(w, 200000)
@@ -115,16 +116,23 @@ def test_auto_orders_large_one_lane_launches_and_k_can_change():
     off_big = c.run(P.PLAN_ORDER_OFF, u)
     off_small = c.run(P.PLAN_ORDER_OFF, u, K=5000)
     auto_big = c.run(P.PLAN_ORDER_AUTO, u)
-    assert auto_big["rollout"][2] and auto_big["est"][2]
+    assert auto_big["sampled_argmin"][4]
+    assert not auto_big["rollout"][2] and not auto_big["est"][2]
     assert c.pl.get_launch()[0] == 1
+    # Gaussian samples around a nominal stay close together: not ordered
+    gspec = P.sample_spec(P.PLAN_SAMPLE_GAUSSIAN, 5, 0, (0.1, 0.2))
+    J, plan = nan(200000), nan(4, 2)
+    c.pl.rollout_sampled_argmin(w.state0, gspec, 4, J, plan)
+    assert not c.pl.get_order()
+    # below the threshold the uniform draws are not ordered either
+    auto_40k = c.run(P.PLAN_ORDER_AUTO, u, K=40000)
+    assert not auto_40k["sampled_argmin"][4]
     auto_small = c.run(P.PLAN_ORDER_AUTO, u, K=5000)
     assert not auto_small["rollout"][2] and not auto_small["sampled_argmin"][4]
-    # between the two automatic thresholds only the in-kernel-sampled
-    # launches are ordered
-    off_mid = c.run(P.PLAN_ORDER_OFF, u, K=120000)
-    auto_mid = c.run(P.PLAN_ORDER_AUTO, u, K=120000)
+    off_mid = c.run(P.PLAN_ORDER_OFF, u, K=60000)
+    auto_mid = c.run(P.PLAN_ORDER_AUTO, u, K=60000)
     assert not auto_mid["rollout"][2] and auto_mid["sampled_argmin"][4]
-    assert_same(off_mid, auto_mid, "K=120000 auto")
+    assert_same(off_mid, auto_mid, "K=60000 auto")
     on_small = c.run(P.PLAN_ORDER_ON, u, K=5000)
     auto_big2 = c.run(P.PLAN_ORDER_AUTO, u)
     assert_same(off_big, auto_big, "K=200000 auto")
