@@ -377,10 +377,12 @@ plan_status_t plan_get_launch(const plan_ctx *ctx, int *lanes, int *block);
  * place, with the same results). Only the
  * assignment of candidates to lanes changes: every output is bit-identical
  * with and without ordering. Ordering pays when the candidates of a wave
- * spread far apart, as with the paper's uniform steering-rate samples; with
- * candidates that stay close (Gaussian samples around a nominal) it was
- * slower. Modes: PLAN_ORDER_AUTO (default: launches that draw uniform
- * samples in the kernel, from 49 152 candidates on), PLAN_ORDER_OFF,
+ * spread far apart and the steps are texture-bound, as with the paper's
+ * configuration (uniform steering-rate samples, 50 Euler substeps per
+ * control); with one substep per control it was slower, with uniform and
+ * with Gaussian draws. Modes: PLAN_ORDER_AUTO (default: launches that draw
+ * uniform samples in the kernel with at least 8 substeps per control, from
+ * 49 152 candidates on), PLAN_ORDER_OFF,
  * PLAN_ORDER_ON (every full-horizon launch). Errors: PLAN_EINVAL for another
  * mode. plan_get_order reports whether the most recent full-horizon rollout
  * was ordered (1) or not (0). */

@@ -23,7 +23,8 @@ namespace {
 constexpr int ORDER_TILE = 2048;       // elements per scatter workgroup (256 threads x 8)
 constexpr int ORDER_BLOCK = 256;
 static_assert(ORDER_BLOCK == 256, "the scatter scans the 256 digit totals with one thread each");
-constexpr int ORDER_PROXY_SUB = 4;     // proxy substeps per control interval
+constexpr int ORDER_PROXY_SUB = 4;     // proxy substeps per control interval (at most)
+constexpr int ORDER_PROXY_STEPS = 64;  // about this many proxy substeps over the horizon
 // proxy workgroups: large, so that few atomics per value fold the range
 // (same-address atomics from every workgroup serialise)
 constexpr int ORDER_PROXY_BLOCK = 1024;
@@ -52,7 +53,9 @@ __global__ __launch_bounds__(ORDER_PROXY_BLOCK) void order_proxy(OrderArgs o) {
     if (active) {
         const size_t K = (size_t)o.K;
         float d = o.delta0, v = o.vx0, psi = 0.0f, y = 0.0f;
-        const float h = o.dt * (1.0f / ORDER_PROXY_SUB);
+        // long horizons take fewer substeps per interval: the proxy only ranks
+        const int sub = max(1, min(ORDER_PROXY_SUB, ORDER_PROXY_STEPS / o.N));
+        const float h = o.dt / (float)sub;
         PhiloxBlock blk{};
         int m = 0;
         for (int n = 0; n < o.N; ++n) {
@@ -70,7 +73,7 @@ __global__ __launch_bounds__(ORDER_PROXY_BLOCK) void order_proxy(OrderArgs o) {
             v = fmaxf(v + o.accel_max * u1 * o.dt, o.vx_min);
             const float klim = o.mu_g / fmaxf(v * v, 1e-6f);
             const float kap = fminf(fmaxf(tanf(d) * o.inv_wheelbase, -klim), klim);
-            for (int s = 0; s < ORDER_PROXY_SUB; ++s) {
+            for (int s = 0; s < sub; ++s) {
                 psi += v * kap * h;
                 y += v * __sinf(psi) * h;
             }

@@ -346,14 +346,17 @@ plan_status_t plan_set_terrain(plan_ctx *c, const float *height_dev, int W, int 
 enum class Kind { plain, chunk, sampled, fused, fused_sampled };
 
 // Automatic locality order: launches that draw uniform samples in the kernel
-// (the paper's sampling, steering rates spread over the admissible set), from
-// this many candidates on. There the candidates of a wave spread over tens
-// of metres and ordering them at one lane per candidate beats the unordered
-// automatic shape (at the paper's shape by about a quarter; from 49 152
-// candidates on at all). Candidates that stay close (Gaussian samples around
-// a nominal) were slower ordered, and the spread of materialised controls is
-// unknown, so those launches are ordered only on request.
+// with many Euler substeps per control interval (the paper's configuration:
+// steering rates spread over the admissible set, 50 substeps), from this many
+// candidates on. There the candidates of a wave spread over tens of metres,
+// the steps are texture-bound and the sort is amortised over a long rollout:
+// ordering at one lane per candidate beat the unordered automatic shape from
+// 49 152 candidates on (by about a quarter at the paper's K). With one
+// substep per interval (a control draw every step, a short rollout) it lost,
+// with uniform and with Gaussian draws, and the spread of materialised
+// controls is unknown, so those launches are ordered only on request.
 constexpr int ORDER_AUTO_MIN_K_UNIFORM = 49152;
+constexpr int ORDER_AUTO_MIN_SUBSTEPS = 8;
 
 // Whether a full-horizon launch of K candidates at this lane count runs in
 // locality order (ordered launches then use one lane per candidate).
@@ -361,7 +364,7 @@ constexpr int ORDER_AUTO_MIN_K_UNIFORM = 49152;
 static bool order_wanted(const plan_ctx *c, int K, const plan::SampleArgs *smp) {
     return c->order_mode == PLAN_ORDER_ON ||
            (c->order_mode == PLAN_ORDER_AUTO && smp && smp->kind == PLAN_SAMPLE_UNIFORM &&
-            K >= ORDER_AUTO_MIN_K_UNIFORM);
+            c->integ.substeps >= ORDER_AUTO_MIN_SUBSTEPS && K >= ORDER_AUTO_MIN_K_UNIFORM);
 }
 
 // Sort the candidates of a one-lane full-horizon launch by their proxy

@@ -127,6 +127,15 @@ def test_auto_orders_large_uniform_sampled_launches_and_k_can_change():
     # below the threshold the uniform draws are not ordered either
     auto_40k = c.run(P.PLAN_ORDER_AUTO, u, K=40000)
     assert not auto_40k["sampled_argmin"][4]
+    # nor with one Euler substep per control (a draw every step, short rollout)
+    w1 = inputs.c2(K=8, N=10)
+    T1 = w1.terrain
+    pl1 = P.Planner(w1.vehicle, w1.cost, w1.integ, 50000, 10, T1.W, T1.H)
+    pl1.set_terrain(dev(T1.height), T1.x0, T1.y0, T1.res)
+    uspec = P.sample_spec(P.PLAN_SAMPLE_UNIFORM, 3, 0, (1.0, 0.0))
+    pl1.rollout_sampled_argmin(w1.state0, uspec, 10, nan(50000), nan(10, 2))
+    assert w1.integ["substeps"] == 1 and not pl1.get_order()
+    pl1.close()
     auto_small = c.run(P.PLAN_ORDER_AUTO, u, K=5000)
     assert not auto_small["rollout"][2] and not auto_small["sampled_argmin"][4]
     off_mid = c.run(P.PLAN_ORDER_OFF, u, K=60000)
