@@ -20,7 +20,7 @@
 namespace plan {
 namespace {
 
-constexpr int ORDER_TILE = 2048;       // elements per scatter workgroup (256 threads x 8)
+constexpr int ORDER_TILE = 1024;       // elements per scatter workgroup (256 threads x 4)
 constexpr int ORDER_BLOCK = 256;
 static_assert(ORDER_BLOCK == 256, "the scatter scans the 256 digit totals with one thread each");
 constexpr int ORDER_PROXY_SUB = 4;     // proxy substeps per control interval (at most)
@@ -185,7 +185,7 @@ __global__ __launch_bounds__(ORDER_BLOCK) void order_scan(OrderArgs o) {
 
 // Stable scatter of one tile by digit p. The digits' output bases come from
 // an exclusive scan of the 256 digit totals, the tile's start within each
-// digit from the per-digit scan. Each wave ranks its 512 elements in eight
+// digit from the per-digit scan. Each wave ranks its 256 elements in four
 // rounds of 64: the lanes holding the same digit are found with eight
 // ballots, and a per-wave, per-digit count in LDS carries the rank across
 // rounds. The last pass writes only the candidate order and resets the
