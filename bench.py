@@ -42,7 +42,7 @@ ALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
 # by what the same counters read for a 256 MiB device copy (fetch x2.0,
 # write x1.0); profiles/rollout_srb_c2_hbm_counters.md has the commands. Valid
 # for the kernel as profiled; None for other workloads.
-C2_TRAFFIC_BYTES = (3747.55 * 262144.0 / 131084.48 + 32.91) * 1024
+C2_TRAFFIC_BYTES = (3747.44 * 262144.0 / 131084.50 + 32.91) * 1024
 
 
 def workload(name):
