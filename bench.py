@@ -38,10 +38,11 @@ OPS_PER_STEP = 532
 # non-packed FP32 operation per lane per clock.
 ALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
 # HBM bytes per launch of the fused rollout kernel on the single-plan
-# workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per dispatch) scaled
-# by what the same counters read for a 256 MiB device copy (fetch x2.0,
-# write x1.0); profiles/rollout_srb_c2_hbm_counters.md has the commands. Valid
-# for the kernel as profiled; None for other workloads.
+# workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per dispatch; one
+# `--pmc` run each over `bench.py --steps 10 --warmup 2 --cpu-seconds 0
+# --serving 0 --rows 0`) scaled by what the same counters read for a 256 MiB
+# device copy (`bench.py --calibrate-copy 256`: fetch x2.0, write x1.0).
+# Valid for the kernel as profiled; None for other workloads.
 C2_TRAFFIC_BYTES = (3747.44 * 262144.0 / 131084.50 + 32.91) * 1024
 
 
