@@ -216,3 +216,17 @@ def test_ordered_gaussian_draws_with_nominal_bitwise():
         assert not np.isnan(b).any()
         np.testing.assert_array_equal(a, b)
     pl.close()
+
+
+def test_invalid_order_mode_is_rejected_and_keeps_the_mode():
+    w = inputs.c1(K=64, N=10)
+    c = Ctx(w, 64)
+    with pytest.raises(P.PlanError) as e:
+        c.pl.set_order(3)
+    assert e.value.status == P.PLAN_EINVAL
+    # the previous (default, automatic) mode is kept: a small launch stays unordered
+    J = nan(64)
+    c.pl.rollout(w.state0, dev(w.controls), J)
+    torch.cuda.synchronize()
+    assert not c.pl.get_order() and not np.isnan(J.cpu().numpy()).any()
+    c.pl.close()
