@@ -207,6 +207,64 @@ def test_constant_costmap_adds_four_wheel_lookups_per_second():
     assert J[0] == pytest.approx((5.0 + 4 * c0) * T + 15.0 * (100.0 - v0 * T), rel=1e-12)
 
 
+def test_euler_cost_is_left_riemann_sum_at_the_nodes():
+    """Level ground, straight line at constant speed over a costmap linear in
+    x (c = c0 + c1 x, exact in float32 at the nodes, so bilinear interpolation
+    reproduces it): the running cost at node n is L_n = w_t + 4 c0 +
+    c1 (4 x_n + 2 (L_f - L_r)), with x_n = x_s + n h v. Eq. framework:cost
+    integrated by forward Euler adds h L_n at the nodes n = 0..N-1 (the left
+    Riemann sum, reading of the cost quadrature): J must equal that sum plus
+    the terminal cost, and must differ from the right sum (nodes 1..N) by
+    h (L_N - L_0) = 4 h c1 v T."""
+    v = _veh()
+    c0, c1 = 2.0, 0.5
+    h_grid, x0g, y0g, res = _grid(lambda X, Y: 0.0 * X)
+    X = x0g + res * np.arange(h_grid.shape[1])
+    cm = np.repeat((c0 + c1 * X)[None, :].astype(np.float32), h_grid.shape[0], axis=0)
+    N, dt, vx, xs, gx = 20, 0.02, 5.0, -3.0, 30.0
+    o = _oracle(v, cost=_cost(goal_x=gx, goal_y=0.0), terrain=(h_grid, x0g, y0g, res),
+                costmap=cm)
+    s0 = state(x=xs, z=v["hR"], v=(vx, 0, 0)).astype(np.float32)
+    J, fs, ex = o.rollout(s0, np.zeros((N, 2, 1), np.float32))
+    assert ex[0] == -1
+    x_n = float(s0[0]) + dt * vx * np.arange(N + 1)
+    L_n = 5.0 + 4 * c0 + c1 * (4 * x_n + 2 * (v["Lf"] - v["Lr"]))
+    Phi = 15.0 * abs(gx - x_n[-1])
+    left = dt * L_n[:N].sum() + Phi
+    right = dt * L_n[1:].sum() + Phi
+    assert fs[0, 0] == pytest.approx(x_n[-1], rel=1e-13)
+    assert J[0] == pytest.approx(left, rel=1e-12)
+    assert abs(right - left) == pytest.approx(4 * dt * c1 * vx * N * dt, rel=1e-9)
+    assert abs(J[0] - right) > 1e-4 * abs(right)
+
+
+@pytest.mark.parametrize("v0,throttle,accel", [(6.0, 0.5, 1.5), (10.0, -0.5, -1.5),
+                                               (6.0, 2.0, 3.0), (6.0, -0.25, -0.75)])
+def test_throttle_prescribes_longitudinal_acceleration(v0, throttle, accel):
+    """Control channel 1 is the throttle in [-1, 1]; it prescribes the body
+    longitudinal acceleration v_x' = accel_max * clamp(throttle, -1, 1) with
+    accel_max = 3 m/s^2 (the v_x row of eq. models:6dof:A is the control
+    itself; reading of the control channels). Forward Euler then gives
+    v_x,N = v0 + N h a exactly, whatever else the chassis does, and, with the
+    pitch response removed (J_yy huge, so the rear constraint force's squat
+    moment turns nothing), x_N = x0 + h sum_n v_x,n = N h v0 + h^2 a N (N-1)/2:
+    the position update uses the node velocity (left point)."""
+    v = _veh(Jyy=1e12)
+    N, dt = 40, 0.02
+    o = _oracle(v, cost=_cost(goal_x=500.0, goal_y=0.0))
+    s0 = state(z=v["hR"], v=(v0, 0, 0)).astype(np.float32)
+    u = np.zeros((N, 2, 1), np.float32)
+    u[:, 1, 0] = throttle
+    J, fs, _ = o.rollout(s0, u)
+    assert fs[6, 0] == pytest.approx(v0 + N * dt * accel, rel=1e-13, abs=1e-13)
+    assert fs[0, 0] == pytest.approx(N * dt * v0 + dt * dt * accel * N * (N - 1) / 2,
+                                     rel=1e-12)
+    # the rear wheels carry the constraint force (M/2)(v_x' - g_x) on level ground
+    _, d = o.rhs(state(z=v["hR"], v=(v0, 0, 0)), 0.0, accel)
+    np.testing.assert_allclose(d["f"][2:, 0], v["M"] / 2 * accel, rtol=1e-14)
+    np.testing.assert_allclose(d["f"][:2, 0], 0.0, atol=0.0)
+
+
 # ------------------------------------------- P3 flat-ground reduction to EST
 
 @pytest.mark.parametrize("vy,delta", [(0.8, 0.2), (-1.5, -0.4), (0.3, 0.0)])
