@@ -10,16 +10,19 @@
 namespace plan {
 
 struct SelectOut {
-    // (k*, J*) of a selection. Each of the first two 8-byte words also holds
-    // the sequence number of the call that produced it, so a host polling
-    // the pinned copy knows both halves are that call's (a naturally aligned
-    // 8-byte store is never torn).
+    // (k*, J*) of a selection and, for the serving loop, the request's
+    // status. Each of the first three 8-byte words also holds the sequence
+    // number of the call that produced it, so a host polling the pinned copy
+    // knows every value it reads is that call's (a naturally aligned 8-byte
+    // store is never torn, but the record's two 16-byte stores may land in
+    // either order).
     int best_k;
     uint32_t seq_k;
     float best_cost;
     uint32_t seq_cost;
     int32_t status;  // serving: 0, or the plan_status_t of the request
-    uint32_t pad[3];
+    uint32_t seq_status;
+    uint32_t pad[2];
 };
 
 // Everything one rollout needs, passed by value as the kernel argument

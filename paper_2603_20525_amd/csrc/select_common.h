@@ -39,21 +39,23 @@ __device__ __forceinline__ unsigned long long wave_min(unsigned long long v) {
 }
 
 // The selection result: a device copy, and (optional) the pinned host copy
-// written as two 16-byte stores, the first holding (k*, seq, J*, seq).
+// written as two 16-byte stores, (k*, seq, J*, seq) and (status, seq, 0, 0).
+// Nothing orders the two stores as the host sees them, so every 8-byte word
+// the host reads carries seq.
 __device__ __forceinline__ void publish_result(SelectOut *out, SelectOut *out_host,
                                                unsigned long long m, uint32_t seq,
                                                int32_t status) {
     SelectOut o;
     o.best_k = (m == ~0ull) ? -1 : (int)(unsigned int)(m & 0xffffffffu);
     o.best_cost = (m == ~0ull) ? __builtin_inff() : key_cost(m);
-    o.seq_k = o.seq_cost = seq;
+    o.seq_k = o.seq_cost = o.seq_status = seq;
     o.status = status;
-    o.pad[0] = o.pad[1] = o.pad[2] = 0u;
+    o.pad[0] = o.pad[1] = 0u;
     *out = o;
     if (out_host) {
         uint4 *h = reinterpret_cast<uint4 *>(out_host);
         h[0] = make_uint4((unsigned int)o.best_k, seq, __float_as_uint(o.best_cost), seq);
-        h[1] = make_uint4((unsigned int)status, 0u, 0u, 0u);
+        h[1] = make_uint4((unsigned int)status, seq, 0u, 0u);
     }
 }
 

@@ -189,8 +189,9 @@ static void retire_front(plan_server *s) {
 }
 
 // Whether every result of step st has landed in its pinned ring entry (each
-// finishing slot's record carries the step's sequence number in both of its
-// 8-byte words). A step that finishes no request has nothing to publish.
+// finishing slot's record carries the step's sequence number in each of the
+// three 8-byte words the host reads: (k*, seq), (J*, seq), (status, seq)).
+// A step that finishes no request has nothing to publish.
 static bool results_landed(const plan_server *s, const Step &st) {
     if (st.finished.empty()) return false;
     const SelectOut *res = s->ring_host[st.ring];
@@ -198,7 +199,10 @@ static bool results_landed(const plan_server *s, const Step &st) {
         const uint64_t *w = reinterpret_cast<const uint64_t *>(&res[fr.first]);
         const uint64_t w0 = __atomic_load_n(&w[0], __ATOMIC_ACQUIRE);
         const uint64_t w1 = __atomic_load_n(&w[1], __ATOMIC_ACQUIRE);
-        if ((uint32_t)(w0 >> 32) != st.seq || (uint32_t)(w1 >> 32) != st.seq) return false;
+        const uint64_t w2 = __atomic_load_n(&w[2], __ATOMIC_ACQUIRE);
+        if ((uint32_t)(w0 >> 32) != st.seq || (uint32_t)(w1 >> 32) != st.seq ||
+            (uint32_t)(w2 >> 32) != st.seq)
+            return false;
     }
     return true;
 }

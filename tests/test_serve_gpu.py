@@ -177,6 +177,33 @@ def test_bad_terrain_flag_cleared_for_next_request(trace):
     srv.close()
 
 
+def test_status_of_each_request_through_one_slot_and_every_ring_entry(trace):
+    """One slot and a tick long enough for any horizon: request i finishes in
+    step i + 1 and publishes into ring entry i mod 4, so every ring entry is
+    reused with the other status four steps later (bad terrain where
+    i % 3 == 0). Each result must carry its own request's status, never the
+    previous occupant's."""
+    srv = _server(trace, slots=1, chunk=200)
+    ids, bad = [], []
+    for i, r in enumerate(trace):
+        T = r.w.terrain
+        if i % 3 == 0:
+            h = T.height.copy()
+            h[5 + i, 9] = np.nan
+            ids.append(srv.submit(dev(h), T.x0, T.y0, T.res, r.w.state0, r.u, r.w.cost,
+                                  r.w.integ, r.plan))
+            bad.append(True)
+        else:
+            ids.append(r.submit(srv))
+            bad.append(False)
+    srv.drain()
+    for rid, b in zip(ids, bad):
+        assert srv.result(rid)["status"] == (P.PLAN_EINVAL if b else 1), (rid, b)
+    good = [i for i, b in enumerate(bad) if not b]
+    _check(srv, [trace[i] for i in good], [ids[i] for i in good])
+    srv.close()
+
+
 def test_completion_queue(trace):
     srv = _server(trace, slots=4)
     ids = [r.submit(srv) for r in trace[:6]]
