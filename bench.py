@@ -5,14 +5,16 @@ One step = one plan of the sampling MPC planner: the HIP rollout of K
 candidate control sequences through the single-rigid-body model over the
 heightmap (stage cost and ESM constraint at every Euler step), followed by
 the argmin selection and the 8-byte readback of (k*, J*) -- what one MPC
-iteration needs before it can act. The default workload is a single plan of
-K=4096 candidates x N=100 steps (dt 0.02 s) over a 512x512 fractal-noise
-terrain with two berms, initial speed 15 m/s (synthetic, seeded).
+iteration needs before it can act. The default workload is the stress
+rollout: a single plan of K=65536 candidates x N=200 steps (dt 0.01 s) over a
+2048x2048 terrain at 0.05 m with alternating 15-degree side slopes, 0.5 m
+berms and 0.3 m ruts, initial speed 20 m/s (synthetic, seeded). The
+single-plan workload (K=4096, N=100, 512x512) is reported as a row.
 
 Prints one JSON line: rollout-steps/s (K*N*substeps per plan / wall time per
-plan), p50/p99 plan latency, the rollout kernel's ALU roofline fraction
-(HIP events on the planner's stream) and the FP64 oracle timed on the host
-cores on a bounded sample of the same workload.
+plan), p50/p99 plan latency (over at least 100 plans), the rollout kernel's
+ALU roofline fraction (HIP events on the planner's stream) and the FP64
+oracle timed on the host cores on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -37,13 +39,45 @@ OPS_PER_STEP = 532
 # MI355X vector ALU issue: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz, one
 # non-packed FP32 operation per lane per clock.
 ALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
-# HBM bytes per launch of the fused rollout kernel on the single-plan
-# workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per dispatch; one
-# `--pmc` run each over `bench.py --steps 10 --warmup 2 --cpu-seconds 0
-# --serving 0 --rows 0`) scaled by what the same counters read for a 256 MiB
-# device copy (`bench.py --calibrate-copy 256`: fetch x2.0, write x1.0).
-# Valid for the kernel as profiled; None for other workloads.
-C2_TRAFFIC_BYTES = (3747.44 * 262144.0 / 131084.50 + 32.91) * 1024
+# HBM bytes per launch of the fused rollout kernel, from rocprofv3
+# FETCH_SIZE / WRITE_SIZE (KiB per dispatch, one `--pmc` run each over this
+# script with `--steps 10 --warmup 2 --cpu-seconds 0 --serving 0 --rows 0`)
+# scaled by what the same counters read for a 256 MiB device copy
+# (`--calibrate-copy 256`). Each entry records the signature of the rollout
+# sources and build flags it was taken on (kernel_signature()); once they
+# change, the figure no longer describes the kernel and is reported as null.
+# workload: (FETCH_SIZE KiB, WRITE_SIZE KiB, fetch scale, write scale, signature)
+TRAFFIC_COUNTERS = {
+    # fused kernel at two lanes per candidate; copy calibration 262144 KiB read
+    # as 131085.39 KiB (x1.99979) and written as 262144.0 KiB (x1.0)
+    "c5": (54429.96, 385.69, 262144.0 / 131085.39, 1.0, "69693517c2390e54"),
+}
+ROLLOUT_SOURCES = ("rollout_step.h", "rollout_kernels.h", "rollout.hip", "rollout_multilane.hip",
+                   "plan_internal.h", "select_common.h", "sample.h")
+
+
+def kernel_signature():
+    """First 16 hex digits of a SHA-256 over the rollout kernel's sources and
+    the library's build script (its compiler flags)."""
+    import hashlib
+    h = hashlib.sha256()
+    pkg = os.path.join(ROOT, "paper_2603_20525_amd")
+    for name in ROLLOUT_SOURCES:
+        with open(os.path.join(pkg, "csrc", name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    with open(os.path.join(pkg, "build.py"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_bytes(workload_name):
+    """Counter-derived HBM bytes per launch, or None when no counters were
+    taken on the current kernel for this workload."""
+    t = TRAFFIC_COUNTERS.get(workload_name)
+    if t is None or t[4] != kernel_signature():
+        return None
+    fetch_kib, write_kib, fs, ws, _ = t
+    return (fetch_kib * fs + write_kib * ws) * 1024.0
 
 
 def workload(name):
@@ -371,12 +405,107 @@ def serving_leg(scale=1.0, chunk=16, slots=64):
     return {"plain": plain, "serving": serving}
 
 
+def measure_plan(w, steps, warmup, lanes=0, block=0, min_latency_plans=100):
+    """One workload through the one-launch plan path (rollout + argmin
+    epilogue, then the wait for (k*, J*)): the timed region of `steps` plans,
+    plan latency over max(steps, min_latency_plans) plans, the kernel's own
+    duration from HIP events on the planner's stream, and the two-call path
+    (rollout kernel, argmin kernel) for comparison. Inputs are resident in
+    HBM before the clock starts."""
+    import torch
+    from paper_2603_20525_amd import plan as P
+    T = w.terrain
+    K, N = w.K, w.N
+    pl = P.Planner(w.vehicle, w.cost, w.integ, K, N, T.W, T.H)
+    pl.set_terrain(torch.from_numpy(T.height).cuda(), T.x0, T.y0, T.res)
+    pl.set_launch(lanes, block)
+    u = torch.from_numpy(w.controls).cuda()
+    J = torch.empty(K, device="cuda")
+    plan = torch.empty(N, 2, device="cuda")
+
+    def fused_plan():
+        # one launch: rollout + argmin epilogue; the kernel writes (k*, J*)
+        # to pinned memory, the call waits for it
+        return pl.rollout_argmin(w.state0, u, J, plan)
+
+    def two_call_plan():
+        pl.rollout(w.state0, u, J)
+        return pl.select(u, J, plan)
+
+    for _ in range(warmup):
+        fused_plan()
+        two_call_plan()
+    torch.cuda.synchronize()
+
+    # timed region: `steps` plans through the one-launch path
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        k_best, j_best = fused_plan()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    # plan latency: each plan from the call to (k*, J*) visible on the host
+    n_lat = max(steps, min_latency_plans)
+    lat = []
+    for _ in range(n_lat):
+        ta = time.perf_counter()
+        fused_plan()
+        lat.append(time.perf_counter() - ta)
+
+    # kernel durations: the library brackets each rollout kernel with HIP
+    # events on its own stream (a separate pass, so the timed plans carry no
+    # event overhead)
+    pl.enable_timing(True)
+    kern_ms = []
+    for _ in range(n_lat):
+        fused_plan()
+        kern_ms.append(pl.last_rollout_ms())
+    pl.enable_timing(False)
+
+    # the same plans through the two-call path (rollout, then argmin kernel)
+    lat2 = []
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(n_lat):
+        ta = time.perf_counter()
+        r2 = two_call_plan()
+        lat2.append(time.perf_counter() - ta)
+    torch.cuda.synchronize()
+    elapsed2 = time.perf_counter() - t2
+    assert r2 == (k_best, j_best), "fused and two-call plans differ"
+    lanes_used, block_used = pl.get_launch()
+    pl.close()
+
+    steps_per_plan = K * N * w.integ["substeps"]
+    k_avg_s = sum(kern_ms) / len(kern_ms) / 1e3
+    achieved = OPS_PER_STEP * steps_per_plan / k_avg_s / 1e9
+    return {
+        "steps_per_plan": steps_per_plan,
+        "elapsed_s": elapsed,
+        "rollout_steps_per_s": steps_per_plan * steps / elapsed,
+        "ms_per_plan": elapsed / steps * 1e3,
+        "launch": {"lanes": lanes_used, "block": block_used},
+        "plan_latency_ms": {"p50": percentile(lat, 50) * 1e3, "p99": percentile(lat, 99) * 1e3,
+                            "plans": n_lat, "path": "one launch + wait for (k*, J*) per plan"},
+        "two_call_path": {"rollout_steps_per_s": steps_per_plan * n_lat / elapsed2,
+                          "p50_ms": percentile(lat2, 50) * 1e3,
+                          "p99_ms": percentile(lat2, 99) * 1e3, "plans": n_lat,
+                          "path": "plan_rollout + plan_select(ARGMIN) + wait"},
+        "rollout_kernel_ms": {"avg": k_avg_s * 1e3, "min": min(kern_ms), "max": max(kern_ms),
+                              "launches": len(kern_ms),
+                              "kernel": "rollout_srb (fused argmin epilogue)"},
+        "alu_achieved_gops": achieved,
+        "best": {"k": k_best, "J": j_best},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=30)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c5", "paper"])
+    ap.add_argument("--workload", default="c5", choices=["c2", "c5", "paper"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="seconds of oracle work for cpu_baseline (0 = skip)")
     ap.add_argument("--serving", type=int, default=1,
@@ -385,8 +514,8 @@ def main():
                     help="only run 5 device-to-device copies of MIB MiB and exit (the "
                          "reference kernel for scaling the HBM byte counters)")
     ap.add_argument("--rows", type=int, default=1,
-                    help="also measure the widened rows (paper shape, EST, RK4, adjoint, "
-                         "terrain preparation)")
+                    help="also measure the single-plan workload and the widened rows (paper "
+                         "shape, EST, RK4, adjoint, terrain preparation)")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     args = ap.parse_args()
@@ -397,7 +526,6 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2603_20525_amd import plan as P
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -415,100 +543,47 @@ def main():
     K, N, S = w.K, w.N, w.integ["substeps"]
     print(f"[bench] workload {args.workload}: {desc}", file=sys.stderr, flush=True)
 
-    pl = P.Planner(w.vehicle, w.cost, w.integ, K, N, T.W, T.H)
-    pl.set_terrain(torch.from_numpy(T.height).cuda(), T.x0, T.y0, T.res)
-    pl.set_launch(args.lanes, args.block)
-    u = torch.from_numpy(w.controls).cuda()
-    J = torch.empty(K, device="cuda")
-    plan = torch.empty(N, 2, device="cuda")
-    stream = torch.cuda.current_stream()
-
-    def fused_plan():
-        # one launch: rollout + argmin epilogue; the kernel writes (k*, J*)
-        # to pinned memory, the call waits for it
-        return pl.rollout_argmin(w.state0, u, J, plan)
-
-    def two_call_plan():
-        pl.rollout(w.state0, u, J)
-        return pl.select(u, J, plan)
-
-    for _ in range(args.warmup):
-        fused_plan()
-        two_call_plan()
-    torch.cuda.synchronize()
-    print(f"[bench] warmup {args.warmup} done; launch {pl.get_launch()}", file=sys.stderr,
+    m = measure_plan(w, args.steps, args.warmup, args.lanes, args.block)
+    print(f"[bench] timed {args.steps} plans in {m['elapsed_s']:.3f} s", file=sys.stderr,
           flush=True)
-
-    # timed region: K plans through the one-launch path
-    lat = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        ta = time.perf_counter()
-        k_best, j_best = fused_plan()
-        lat.append(time.perf_counter() - ta)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    print(f"[bench] timed {args.steps} plans in {elapsed:.3f} s", file=sys.stderr, flush=True)
-
-    # kernel durations: the library brackets each rollout kernel with HIP
-    # events on its own stream (a separate pass, so the timed region above
-    # carries no event overhead)
-    pl.enable_timing(True)
-    kern_ms = []
-    for i in range(args.steps):
-        fused_plan()
-        kern_ms.append(pl.last_rollout_ms())
-
-    # the same plans through the two-call path (rollout, then argmin kernel)
-    lat2 = []
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    for i in range(args.steps):
-        ta = time.perf_counter()
-        r2 = two_call_plan()
-        lat2.append(time.perf_counter() - ta)
-    torch.cuda.synchronize()
-    elapsed2 = time.perf_counter() - t2
-    pl.enable_timing(False)
-    assert r2 == (k_best, j_best), "fused and two-call plans differ"
-
-    steps_per_plan = K * N * S
-    value = steps_per_plan * args.steps / elapsed
-    k_avg_s = sum(kern_ms) / len(kern_ms) / 1e3
-    achieved = OPS_PER_STEP * steps_per_plan / k_avg_s / 1e9
-    lanes, block = pl.get_launch()
+    achieved = m["alu_achieved_gops"]
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": m["rollout_steps_per_s"],
         "unit": "rollout-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": m["ms_per_plan"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": desc, "K": K, "N": N, "substeps": S, "dt": w.integ["dt"],
-                   "terrain": f"{T.W}x{T.H} at {T.res} m", "launch": {"lanes": lanes, "block": block},
+                   "terrain": f"{T.W}x{T.H} at {T.res} m", "launch": m["launch"],
                    "path": "plan_rollout_argmin (rollout + argmin in one launch)"},
-        "plan_latency_ms": {"p50": percentile(lat, 50) * 1e3, "p99": percentile(lat, 99) * 1e3,
-                            "path": "one launch + wait for (k*, J*) per plan"},
-        "two_call_path": {"rollout_steps_per_s": steps_per_plan * args.steps / elapsed2,
-                          "p50_ms": percentile(lat2, 50) * 1e3,
-                          "p99_ms": percentile(lat2, 99) * 1e3,
-                          "path": "plan_rollout + plan_select(ARGMIN) + wait"},
-        "rollout_kernel_ms": {"avg": k_avg_s * 1e3, "min": min(kern_ms), "max": max(kern_ms),
-                              "kernel": "rollout_srb (fused argmin epilogue)"},
+        "plan_latency_ms": m["plan_latency_ms"],
+        "two_call_path": m["two_call_path"],
+        "rollout_kernel_ms": m["rollout_kernel_ms"],
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_GOPS, "unit": "Gop/s",
                      "frac": achieved / ALU_PEAK_GOPS,
-                     "traffic": C2_TRAFFIC_BYTES if args.workload == "c2" else None,
+                     "traffic": traffic_bytes(args.workload),
                      "traffic_unit": "bytes per launch (HBM, counter-derived)",
+                     "kernel_signature": kernel_signature(),
                      "ops_per_rollout_step": OPS_PER_STEP},
-        "best": {"k": k_best, "J": j_best},
+        "best": m["best"],
     }
+    if args.rows:
+        print("[bench] single-plan workload", file=sys.stderr, flush=True)
+        w2, desc2 = workload("c2")
+        m2 = measure_plan(w2, args.steps, args.warmup)
+        m2.pop("elapsed_s")
+        m2["workload"] = desc2
+        m2["alu_frac"] = m2.pop("alu_achieved_gops") / ALU_PEAK_GOPS
+        m2["traffic"] = traffic_bytes("c2")
+        out["single_plan_c2"] = m2
+        del w2
     if args.serving:
         print("[bench] serving trace: plain vs continuous batching", file=sys.stderr, flush=True)
         out["serving"] = {
@@ -526,7 +601,6 @@ def main():
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     else:
         out["cpu_baseline"] = None
-    pl.close()
     print(json.dumps(out), flush=True)
 
 
