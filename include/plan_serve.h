@@ -38,7 +38,11 @@ typedef struct plan_server plan_server; /* opaque, owned by the library */
  *               plan_rollout;
  *   controls_dev [N][2][K] candidate controls as for plan_rollout;
  *   cost, integ  per-request cost and integration parameters;
- *   plan_dev    [N][2] output: the argmin candidate's clamped controls. */
+ *   plan_dev    [N][2] output: the argmin candidate's clamped controls;
+ *   cost_dev    [K] output or NULL: every candidate's cost J_k (eq.
+ *               framework:cost, +inf for a non-finite candidate), copied
+ *               from the slot on the server's stream right after the launch
+ *               that finishes the request. */
 typedef struct {
     const float *height_dev;
     int W, H;
@@ -50,14 +54,16 @@ typedef struct {
     plan_cost_t cost;
     plan_integ_t integ;
     float *plan_dev;
+    float *cost_dev;
 } plan_request_t;
 
 /* State of one request. Times are seconds on the server's monotonic clock
  * (plan_server_now). t_done is when plan_server_step first observed the
  * result on the host: the kernel publishes (k*, J*) into pinned memory, and
  * the host sees it there before the launch has completed. The request's
- * plan_dev is written by that same launch, so read it through the server's
- * stream (or after plan_server_drain, which completes all device work). */
+ * plan_dev is written by that same launch (and cost_dev by a copy right after
+ * it), so read them through the server's stream (or after plan_server_drain,
+ * which completes all device work). */
 typedef struct {
     int status;       /* 0 pending, 1 done, < 0: plan_status_t of a failure */
     int best_k;       /* as plan_select; -1 if no candidate is finite */

@@ -333,6 +333,14 @@ static plan_status_t launch_step(plan_server *s) {
         s1 = s1 && s->reqs[s->slots[t.e[j].slot].req].r.integ.substeps == 1;
     SHIP(s, plan::launch_rollout_slots(s->slot_args, t, s->bad, s->ring_host[st.ring], st.seq,
                                        s1, lanes, block, s->stream));
+    // per-candidate costs of the requests that asked for them, copied before
+    // any later launch can reuse the slot
+    for (const auto &fr : st.finished) {
+        const plan_request_t &r = s->reqs[fr.second].r;
+        if (r.cost_dev)
+            SHIP(s, hipMemcpyAsync(r.cost_dev, s->cost + (size_t)fr.first * s->max_K,
+                                   sizeof(float) * r.K, hipMemcpyDeviceToDevice, s->stream));
+    }
     if (s->ev_pool.empty()) {
         hipEvent_t e;
         SHIP(s, hipEventCreateWithFlags(&e, hipEventDisableTiming));

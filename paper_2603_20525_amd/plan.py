@@ -497,7 +497,8 @@ class Request(C.Structure):
                 ("x0", C.c_float), ("y0", C.c_float), ("res", C.c_float),
                 ("costmap_dev", C.c_void_p), ("state0", C.c_float * 13),
                 ("controls_dev", C.c_void_p), ("K", C.c_int), ("N", C.c_int),
-                ("cost", Cost), ("integ", Integ), ("plan_dev", C.c_void_p)]
+                ("cost", Cost), ("integ", Integ), ("plan_dev", C.c_void_p),
+                ("cost_dev", C.c_void_p)]
 
 
 class Result(C.Structure):
@@ -569,8 +570,10 @@ class Server:
         self.h = h
         self._keep = {}
 
-    def submit(self, height, x0, y0, res, state0, controls, cost, integ, plan, costmap=None):
-        """All tensors are kept referenced until the request is read back."""
+    def submit(self, height, x0, y0, res, state0, controls, cost, integ, plan, costmap=None,
+               costs_out=None):
+        """All tensors are kept referenced until the request is read back.
+        costs_out ([K], optional) receives every candidate's cost."""
         H, W = height.shape
         N, two, K = controls.shape
         # the library copies the request, so one Request object is reused
@@ -585,10 +588,11 @@ class Server:
         r.cost = self._param(Cost, cost)
         r.integ = self._param(Integ, integ)
         r.plan_dev = _dptr(plan, "plan", 2 * N)
+        r.cost_dev = None if costs_out is None else _dptr(costs_out, "costs_out", K)
         rid = self._rid
         _scheck("plan_server_submit", _bind_server().plan_server_submit(self.h, C.byref(r),
                                                                          C.byref(rid)), self.h)
-        self._keep[rid.value] = (height, controls, plan, costmap)
+        self._keep[rid.value] = (height, controls, plan, costmap, costs_out)
         return rid.value
 
     def _param(self, cls, d):

@@ -120,9 +120,9 @@ def test_struct_layouts_match_the_header(tmp_path):
         " offsetof(plan_sample_t, seed), offsetof(plan_sample_t, stream),"
         " offsetof(plan_sample_t, scale), offsetof(plan_sample_t, nominal_dev),"
         " sizeof(plan_vehicle_t));\n"
-        '  printf("%zu %zu %zu %zu\\n", sizeof(plan_request_t),'
+        '  printf("%zu %zu %zu %zu %zu\\n", sizeof(plan_request_t),'
         " offsetof(plan_request_t, controls_dev), offsetof(plan_request_t, plan_dev),"
-        " sizeof(plan_result_t));\n"
+        " offsetof(plan_request_t, cost_dev), sizeof(plan_result_t));\n"
         "  return 0;\n}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(prog), "-o",
@@ -134,7 +134,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     assert a == [C.sizeof(P.Sample), P.Sample.seed.offset, P.Sample.stream.offset,
                  P.Sample.scale.offset, P.Sample.nominal_dev.offset, C.sizeof(P.Vehicle)]
     assert b == [C.sizeof(P.Request), P.Request.controls_dev.offset, P.Request.plan_dev.offset,
-                 C.sizeof(P.Result)]
+                 P.Request.cost_dev.offset, C.sizeof(P.Result)]
 
 
 def test_package_has_no_oracle_or_cpu_fallback():

@@ -12,7 +12,9 @@ from paper_2603_20525_amd import plan as P  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
-GRAD_RTOL = 2e-2   # relative to max(|fd|, 1e-2 of the candidate's largest |fd|)
+# relative to max(|fd|, 1e-2 of the candidate's largest |fd|); the worst entry
+# seen is 2.5e-3 (C4 top 32), the FP32 forward's own sensitivity to rounding
+GRAD_RTOL = 5e-3
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -81,10 +83,10 @@ def test_c4_top32_gradients_against_fp64_finite_differences():
     sub = np.ascontiguousarray(w.controls[:, :, top])
     Jg, g = gpu_grad(pl, w, sub)
     np.testing.assert_array_equal(Jg, J.cpu().numpy()[top])
-    worst, used, skipped = compare_fd(o, w, sub, g, range(0, 32, 4), label="c4 top-32")
+    worst, used, skipped = compare_fd(o, w, sub, g, range(32), label="c4 top-32")
     print(f"c4 top-32: {used} gradient entries vs FP64 FD, worst {worst:.3g} x tol, "
           f"{skipped} skipped at kinks")
-    assert used >= 0.8 * (used + skipped)
+    assert used >= 0.8 * 32 * 24
 
 
 def test_c1_gradients_every_candidate_sampled():
@@ -93,6 +95,7 @@ def test_c1_gradients_every_candidate_sampled():
     _, g = gpu_grad(pl, w, w.controls)
     worst, used, skipped = compare_fd(o, w, w.controls, g, range(16), n_entries=12, label="c1")
     print(f"c1: {used} entries, worst {worst:.3g} x tol, {skipped} skipped")
+    assert used >= 0.8 * 16 * 12
 
 
 def test_checkpoint_interval_does_not_change_the_gradient():
@@ -165,3 +168,4 @@ def test_paper_shape_substeps_gradient():
     worst, used, skipped = compare_fd(o, w, w.controls, g, range(0, 8, 2), n_entries=8,
                                       label="paper shape")
     print(f"paper shape: {used} entries, worst {worst:.3g} x tol, {skipped} skipped")
+    assert used >= 0.75 * 4 * 8

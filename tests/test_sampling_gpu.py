@@ -9,7 +9,7 @@ torch = pytest.importorskip("torch")
 import oracle  # noqa: E402  (test infrastructure)
 from paper_2603_20525_amd import inputs  # noqa: E402
 from paper_2603_20525_amd import plan as P  # noqa: E402
-from tests.parity import assert_rollout_parity, assert_screened_parity  # noqa: E402
+from tests.parity import assert_rollout_parity, assert_horizon_parity  # noqa: E402
 from tests.test_parity_gpu import SHAPES, Case, dev  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -138,7 +138,7 @@ def test_paper_scheme_sampled_in_kernel_matches_oracle():
     """The paper's scheme (steering rate uniform in [-1, 1] rad/s, no
     acceleration; 16 intervals of 0.25 s at 50 Euler substeps): in-kernel
     samples equal the oracle's bit for bit, so the rollout is compared with
-    the screened whole-horizon rule."""
+    the whole-horizon rule."""
     w = inputs.paper_shape(K=4096)
     case = Case(w)
     K, N = w.K, 16
@@ -149,12 +149,8 @@ def test_paper_scheme_sampled_in_kernel_matches_oracle():
     torch.cuda.synchronize()
     u_o = oracle.sample_controls(U, 6000, 0, [1.0, 0.0], K, N).astype(np.float32)
     assert np.array_equal(gpu_samples(case, spec, K, N), u_o)
-    idx = np.arange(0, K, 8)
-    mc, ms, ex = assert_screened_parity(J.cpu().numpy()[idx], fs.cpu().numpy()[:, idx], case.o,
-                                        w.state0, np.ascontiguousarray(u_o[:, :, idx]),
-                                        "paper scheme sampled in kernel")
-    print(f"paper scheme in-kernel: costs within 1e-4: {mc:.1%}, states: {ms:.1%}, "
-          f"ill conditioned: {ex:.1%}")
+    assert_horizon_parity(J.cpu().numpy(), fs.cpu().numpy(), case.o, w.state0, u_o,
+                          "paper scheme sampled in kernel", min_cost=0.99, min_state=0.86)
 
 
 def test_select_sampled_equals_select_on_materialised(c1big):
@@ -213,7 +209,8 @@ def test_paper_shape_full_size_one_launch_sampled_outputs():
     """The paper's configuration at full size in the launch the bench times
     (K = 204 288 candidates drawn in the kernel, 16 x 0.25 s at 50 Euler
     substeps, argmin epilogue): sampled candidates' costs against the oracle's
-    own draws and rollouts, and the selection against the cost array."""
+    own draws and rollouts for every candidate, and the selection against the
+    cost array and against the oracle's costs."""
     T = inputs.fbm_berm_terrain(2000)
     w = inputs.paper_shape(K=8, terrain=T)
     K, N = 204288, 16
@@ -232,14 +229,12 @@ def test_paper_shape_full_size_one_launch_sampled_outputs():
     u_best = oracle.sample_controls(U, 6000, 0, [1.0, 0.0], K, N)[:, :, bk]
     expect = np.stack([np.clip(u_best[:, 0], -1.0, 1.0), np.clip(u_best[:, 1], -1.0, 1.0)], 1)
     assert np.array_equal(plan.cpu().numpy(), expect.astype(np.float32))
-    # sampled candidates, including the winner, against the oracle
-    idx = np.unique(np.concatenate([np.arange(0, K, 797), [bk]]))
+    # every candidate against the oracle's own draws and rollouts, and the
+    # launch's pick against the oracle's costs
     u_all = oracle.sample_controls(U, 6000, 0, [1.0, 0.0], K, N).astype(np.float32)
-    u_s = np.ascontiguousarray(u_all[:, :, idx])
     o = oracle.Oracle(w.vehicle, w.cost, w.integ)
     o.set_terrain(T.height, T.x0, T.y0, T.res)
-    mc, ms, ex = assert_screened_parity(Jg[idx], fs.cpu().numpy()[:, idx], o, w.state0, u_s,
-                                        "paper shape full size, one launch")
-    print(f"paper shape K=204288 one launch: {len(idx)} sampled, costs within 1e-4 {mc:.1%}, "
-          f"states {ms:.1%}")
+    assert_horizon_parity(Jg, fs.cpu().numpy(), o, w.state0, u_all,
+                          "paper shape full size, one launch", min_cost=0.99, min_state=0.87,
+                          k_gpu=bk)
     pl.close()

@@ -1,14 +1,18 @@
 """GPU tests of the continuous-batching server (include/plan_serve.h): every
 request's result is bit-identical to the plain path (plan_rollout +
-plan_select) whether it runs alone or mixed with others, under any arrival
-pattern, tick length, slot limit or memory budget."""
+plan_select) and to the same request served alone, whether it runs alone or
+mixed with others, under any arrival pattern, tick length, slot limit or
+memory budget; and every served request of the trace matches the FP64
+oracle's rollout of that request."""
 import numpy as np
 import pytest
 
 torch = pytest.importorskip("torch")
 
+import oracle  # noqa: E402  (test infrastructure)
 from paper_2603_20525_amd import inputs  # noqa: E402
 from paper_2603_20525_amd import plan as P  # noqa: E402
+from tests.parity import assert_horizon_parity  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -234,3 +238,69 @@ def test_submit_validation(trace):
     with pytest.raises(P.PlanError):
         srv.submit(r.h, T.x0, T.y0, 0.0, r.w.state0, r.u, r.w.cost, r.w.integ, r.plan)
     srv.close()
+
+
+def _serve_trace(reqs, gap_per_step=0.005, **kw):
+    """Submit the requests in arrival order, one scheduling step per
+    gap_per_step seconds of arrival gap (so later requests join while earlier
+    ones are on the GPU), with a [K] cost output each; drain."""
+    srv = _server(reqs, **kw)
+    costs = [torch.full((r.w.K,), float("nan"), device="cuda") for r in reqs]
+    ids = []
+    for i, r in enumerate(reqs):
+        T = r.w.terrain
+        r.plan.zero_()
+        ids.append(srv.submit(r.h, T.x0, T.y0, T.res, r.w.state0, r.u, r.w.cost, r.w.integ,
+                              r.plan, costs_out=costs[i]))
+        if i + 1 < len(reqs):
+            for _ in range(int((reqs[i + 1].arrival - r.arrival) / gap_per_step)):
+                srv.step()
+    srv.drain()
+    res = [srv.result(i) for i in ids]
+    out = [(x, c.cpu().numpy(), r.plan.cpu().numpy()) for x, c, r in zip(res, costs, reqs)]
+    srv.close()
+    return out
+
+
+@pytest.fixture(scope="module")
+def full_trace():
+    return [Resident(r) for r in inputs.c3_trace()]
+
+
+def test_served_results_match_the_oracle(full_trace):
+    """All 64 requests of the serving trace (Poisson arrivals at 200 req/s, K
+    in {512..8192}, N in 40..160, each with its own terrain crop, start and
+    goal), served in the mix: every candidate's cost against the oracle's
+    rollout of that request (whole-horizon rule), the request's pick against
+    the oracle's costs, and its plan equal to the clamped controls of the
+    pick."""
+    served = _serve_trace(full_trace, slots=16, chunk=16)
+    compared = 0
+    for r, (res, J, plan) in zip(full_trace, served):
+        w, T = r.w, r.w.terrain
+        assert res["status"] == 1, res
+        # the pick is the lowest index of the request's minimal finite cost
+        fin = np.isfinite(J)
+        k = res["best_k"]
+        assert k == int(np.flatnonzero(J == J[fin].min())[0]) and res["best_cost"] == J[k]
+        o = oracle.Oracle(w.vehicle, w.cost, w.integ)
+        o.set_terrain(T.height, T.x0, T.y0, T.res)
+        assert_horizon_parity(J, None, o, w.state0, w.controls,
+                              f"served request {w.name} (K={w.K}, N={w.N})", min_cost=0.99,
+                              k_gpu=k)
+        ko, _, po = o.select(w.controls, J, mode=0)
+        assert ko == k
+        np.testing.assert_array_equal(plan, po.astype(np.float32))
+        compared += w.K
+    print(f"served trace: {len(full_trace)} requests, {compared} candidates against the oracle")
+
+
+def test_each_request_alone_equals_the_mix(full_trace):
+    """Every request of the trace served on its own gives the same bits as
+    in the mix: pick, cost of the pick, every candidate's cost, plan."""
+    mix = _serve_trace(full_trace, slots=16, chunk=16)
+    for r, (res, J, plan) in zip(full_trace, mix):
+        (res1, J1, plan1), = _serve_trace([r], slots=1, chunk=16)
+        assert (res1["best_k"], res1["best_cost"]) == (res["best_k"], res["best_cost"])
+        np.testing.assert_array_equal(J1, J)
+        np.testing.assert_array_equal(plan1, plan)

@@ -11,7 +11,7 @@ torch = pytest.importorskip("torch")
 import oracle  # noqa: E402  (test infrastructure)
 from paper_2603_20525_amd import inputs  # noqa: E402
 from paper_2603_20525_amd import plan as P  # noqa: E402
-from tests.parity import assert_screened_parity  # noqa: E402
+from tests.parity import assert_horizon_parity  # noqa: E402
 from tests.test_parity_gpu import dev  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -145,7 +145,7 @@ def test_costmap_argument_errors(planner):
 
 def test_rollout_over_costmaps_each_side_builds():
     """C1 with obstacles: the GPU builds its costmap with its own kernel, the
-    oracle with its own code; the rollouts must agree (screened rule)."""
+    oracle with its own code; the rollouts must agree (whole-horizon rule)."""
     w = inputs.c1(K=512)
     T = w.terrain
     polys = inputs.obstacle_polygons(T, seed=77, count=8)
@@ -162,7 +162,6 @@ def test_rollout_over_costmaps_each_side_builds():
     o = oracle.Oracle(w.vehicle, w.cost, w.integ)
     o.set_terrain(T.height, T.x0, T.y0, T.res,
                   oracle.costmap_polygons(polys, T.W, T.H, T.x0, T.y0, T.res, 1e6, 0.25))
-    mc, ms, ex = assert_screened_parity(J.cpu().numpy(), fs.cpu().numpy(), o, w.state0,
-                                        w.controls, "rollout over own costmaps")
-    print(f"rollout over own costmaps: costs within 1e-4 {mc:.1%}, states {ms:.1%}")
+    assert_horizon_parity(J.cpu().numpy(), fs.cpu().numpy(), o, w.state0, w.controls,
+                          "rollout over own costmaps", min_cost=0.99, min_state=0.95)
     pl.close()
