@@ -245,6 +245,25 @@ plan_status_t plan_rollout_grad(plan_ctx *ctx, const float state0[13],
                                 const float *weight_dev, int checkpoint_every,
                                 float *cost_dev, float *grad_dev);
 
+/* plan_rollout_grad without any allocation, for callers that cannot allocate
+ * device memory inside a call (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc). Arguments, outputs and results are
+ * those of plan_rollout_grad (same kernels, bit-identical outputs), but the
+ * checkpoints and segment states live in a fixed workspace of 16 MiB per GPU
+ * inside the library (held until the process ends) instead of the context's
+ * growing one: the call needs 4*(13 K (ceil(N/C) + 1) + 14 K C S) <= 16 MiB,
+ * with C = min(checkpoint_every, N) and S the context's substeps (e.g. K =
+ * 4096 candidates at N = 100, C = 10, S = 1 use 4.6 MiB). The workspace is
+ * shared by every call on that GPU, from any context or stream: calls that
+ * overlap on one GPU race and must be serialised by the caller. Nothing in
+ * it needs clearing between calls (each call writes what it reads).
+ * Errors: those of plan_rollout_grad except PLAN_ENOMEM; PLAN_EINVAL also
+ * when the workspace would exceed 16 MiB. */
+plan_status_t plan_rollout_grad_noalloc(plan_ctx *ctx, const float state0[13],
+                                        const float *controls_dev, int K, int N,
+                                        const float *weight_dev, int checkpoint_every,
+                                        float *cost_dev, float *grad_dev);
+
 /* Fill state_dev [13][K] with state0 (host, 13 floats) for every candidate
  * and cost_dev [K] with zero, on the context's stream.
  * Errors: PLAN_EINVAL (NULL pointers, K out of range, non-finite state0). */

@@ -7,6 +7,7 @@
 
 #include <atomic>
 #include <chrono>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -65,6 +66,33 @@ struct plan_ctx {
 };
 
 static thread_local std::string g_create_err;
+
+// Fixed adjoint workspace of plan_rollout_grad_noalloc, for callers that
+// cannot allocate device memory inside a call. One copy per GPU, held until
+// the process ends; every call on a GPU shares it (overlapping calls race).
+// Host code uses only the device address resolved per device at context
+// creation, never the symbol itself.
+constexpr size_t NOALLOC_FLOATS = (size_t)4 << 20;  // 16 MiB
+static __device__ __align__(256) float scratch[NOALLOC_FLOATS];
+constexpr int MAX_DEVICES = 64;
+static float *g_scratch_dev[MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+// With `device` current: resolve this device's copy of the workspace once.
+static hipError_t resolve_scratch(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    if (g_scratch_dev[device]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e == hipSuccess) g_scratch_dev[device] = static_cast<float *>(p);
+    return e;
+}
+
+static float *scratch_of(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return (device >= 0 && device < MAX_DEVICES) ? g_scratch_dev[device] : nullptr;
+}
 
 static plan_status_t fail(plan_ctx *c, plan_status_t st, const char *fmt, const char *a = "") {
     char buf[512];
@@ -271,6 +299,7 @@ plan_status_t plan_create(plan_ctx **out, const plan_vehicle_t *veh, const plan_
         }                                                   \
     } while (0)
     CREATE_TRY(hipGetDevice(&c->device));
+    CREATE_TRY(resolve_scratch(c->device));
     CREATE_TRY(hipMalloc(&c->tex, sizeof(float4) * (size_t)max_W * max_H));
     CREATE_TRY(hipMalloc(&c->smooth_tmp, sizeof(float) * (size_t)max_W * max_H));
     CREATE_TRY(hipMalloc(&c->bad_dev, sizeof(int)));
@@ -812,12 +841,13 @@ plan_status_t plan_rollout_chunk(plan_ctx *c, float *state_dev, float *cost_dev,
     return launch(c, a, Kind::chunk);
 }
 
-plan_status_t plan_rollout_grad(plan_ctx *c, const float state0[13], const float *controls_dev,
-                                int K, int N, const float *weight_dev, int checkpoint_every,
-                                float *cost_dev, float *grad_dev) {
-    if (!c) return PLAN_EINVAL;
+// Validation shared by plan_rollout_grad and plan_rollout_grad_noalloc;
+// *need receives the workspace size in floats.
+static plan_status_t grad_check(plan_ctx *c, const char *fn, const float *state0,
+                                const float *controls_dev, int K, int N, int checkpoint_every,
+                                const float *cost_dev, const float *grad_dev, size_t *need) {
     if (c->integ.method != PLAN_EULER)
-        return fail(c, PLAN_EINVAL, "%s supports PLAN_EULER integration only", "plan_rollout_grad");
+        return fail(c, PLAN_EINVAL, "%s supports PLAN_EULER integration only", fn);
     if (!state0 || !controls_dev || !cost_dev || !grad_dev)
         return fail(c, PLAN_EINVAL, "NULL argument");
     if (K < 1 || K > c->max_K) return fail(c, PLAN_EINVAL, "K outside [1, max_K]");
@@ -828,23 +858,21 @@ plan_status_t plan_rollout_grad(plan_ctx *c, const float state0[13], const float
     const int C = checkpoint_every < N ? checkpoint_every : N;
     const int nseg = (N + C - 1) / C;
     const size_t Kz = (size_t)K;
-    const size_t need = (size_t)(nseg + 1) * 13 * Kz                 // checkpoints
-                        + (size_t)C * c->integ.substeps * 14 * Kz;   // segment scratch
-    HIP_TRY(c, hipSetDevice(c->device));
-    if (need > c->gws_floats) {
-        HIP_TRY(c, hipStreamSynchronize(c->stream));
-        HIP_TRY(c, hipFree(c->gws));
-        c->gws = nullptr;
-        c->gws_floats = 0;
-        hipError_t e = hipMalloc(&c->gws, sizeof(float) * need);
-        if (e != hipSuccess) {
-            hip_fail(c, "hipMalloc(adjoint workspace)", e);
-            return e == hipErrorOutOfMemory ? PLAN_ENOMEM : PLAN_EDEVICE;
-        }
-        c->gws_floats = need;
-    }
-    float *ckpt = c->gws;
-    float *scratch = ckpt + (size_t)(nseg + 1) * 13 * Kz;
+    *need = (size_t)(nseg + 1) * 13 * Kz                 // checkpoints
+            + (size_t)C * c->integ.substeps * 14 * Kz;   // segment scratch
+    return PLAN_OK;
+}
+
+// Forward pass with checkpoints, then the backward pass, on workspace ws
+// (at least grad_check's *need floats; every float of it that is read is
+// first written by the same call).
+static plan_status_t grad_launch(plan_ctx *c, const float *state0, const float *controls_dev,
+                                 int K, int N, const float *weight_dev, int checkpoint_every,
+                                 float *cost_dev, float *grad_dev, float *ws) {
+    const int C = checkpoint_every < N ? checkpoint_every : N;
+    const int nseg = (N + C - 1) / C;
+    float *ckpt = ws;
+    float *seg = ckpt + (size_t)(nseg + 1) * 13 * (size_t)K;
     RolloutArgs a;
     fill_args(c, a);
     for (int q = 0; q < 13; ++q) a.s0[q] = state0[q];
@@ -865,9 +893,58 @@ plan_status_t plan_rollout_grad(plan_ctx *c, const float state0[13], const float
     if (c->block_opt) block = c->block_opt;
     HIP_TRY(c, plan::launch_rollout_ckpt(a, lanes, block, c->stream));
     // the backward kernel splits the wheels over the same lanes
-    HIP_TRY(c, plan::launch_adjoint_backward(a, C, ckpt, weight_dev, scratch, grad_dev, lanes,
+    HIP_TRY(c, plan::launch_adjoint_backward(a, C, ckpt, weight_dev, seg, grad_dev, lanes,
                                              c->stream));
     return PLAN_OK;
+}
+
+plan_status_t plan_rollout_grad(plan_ctx *c, const float state0[13], const float *controls_dev,
+                                int K, int N, const float *weight_dev, int checkpoint_every,
+                                float *cost_dev, float *grad_dev) {
+    if (!c) return PLAN_EINVAL;
+    size_t need = 0;
+    const plan_status_t st = grad_check(c, "plan_rollout_grad", state0, controls_dev, K, N,
+                                        checkpoint_every, cost_dev, grad_dev, &need);
+    if (st != PLAN_OK) return st;
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (need > c->gws_floats) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        HIP_TRY(c, hipFree(c->gws));
+        c->gws = nullptr;
+        c->gws_floats = 0;
+        hipError_t e = hipMalloc(&c->gws, sizeof(float) * need);
+        if (e != hipSuccess) {
+            hip_fail(c, "hipMalloc(adjoint workspace)", e);
+            return e == hipErrorOutOfMemory ? PLAN_ENOMEM : PLAN_EDEVICE;
+        }
+        c->gws_floats = need;
+    }
+    return grad_launch(c, state0, controls_dev, K, N, weight_dev, checkpoint_every, cost_dev,
+                       grad_dev, c->gws);
+}
+
+plan_status_t plan_rollout_grad_noalloc(plan_ctx *c, const float state0[13],
+                                        const float *controls_dev, int K, int N,
+                                        const float *weight_dev, int checkpoint_every,
+                                        float *cost_dev, float *grad_dev) {
+    if (!c) return PLAN_EINVAL;
+    size_t need = 0;
+    const plan_status_t st = grad_check(c, "plan_rollout_grad_noalloc", state0, controls_dev, K,
+                                        N, checkpoint_every, cost_dev, grad_dev, &need);
+    if (st != PLAN_OK) return st;
+    if (need > NOALLOC_FLOATS) {
+        char buf[160];
+        snprintf(buf, sizeof buf,
+                 "workspace of %zu bytes exceeds the fixed %zu-byte workspace "
+                 "(4 (13 K (ceil(N/C) + 1) + 14 K C S) bytes)",
+                 need * sizeof(float), NOALLOC_FLOATS * sizeof(float));
+        return fail(c, PLAN_EINVAL, "%s", buf);
+    }
+    float *ws = scratch_of(c->device);
+    if (!ws) return fail(c, PLAN_EDEVICE, "fixed workspace not resolved on this device");
+    HIP_TRY(c, hipSetDevice(c->device));
+    return grad_launch(c, state0, controls_dev, K, N, weight_dev, checkpoint_every, cost_dev,
+                       grad_dev, ws);
 }
 
 plan_status_t plan_select(plan_ctx *c, int mode, float lambda, const float *controls_dev,

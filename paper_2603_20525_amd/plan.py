@@ -55,6 +55,7 @@ class Sample(C.Structure):
 # every symbol include/plan.h declares
 EXPORTS = ("plan_create", "plan_set_stream", "plan_set_cost", "plan_set_terrain",
            "plan_rollout", "plan_rollout_est", "plan_rollout_chunk", "plan_init_state", "plan_rollout_grad",
+           "plan_rollout_grad_noalloc",
            "plan_select", "plan_sample_controls", "plan_rollout_sampled", "plan_select_sampled",
            "plan_rollout_argmin", "plan_rollout_sampled_argmin",
            "plan_smooth_terrain", "plan_costmap_polygons",
@@ -86,6 +87,7 @@ def lib():
                                          C.c_int]
         L.plan_init_state.argtypes = [vp, fp, vp, vp, C.c_int]
         L.plan_rollout_grad.argtypes = [vp, fp, vp, C.c_int, C.c_int, vp, C.c_int, vp, vp]
+        L.plan_rollout_grad_noalloc.argtypes = L.plan_rollout_grad.argtypes
         L.plan_select.argtypes = [vp, C.c_int, C.c_float, vp, vp, C.c_int, C.c_int, ip, fp, vp]
         sp = C.POINTER(Sample)
         L.plan_sample_controls.argtypes = [vp, sp, C.c_int, C.c_int, vp]
@@ -226,6 +228,20 @@ def plan_rollout_grad(ctx, state0, controls, cost, grad, weight=None, checkpoint
                                  _dptr(weight, "weight", K), int(checkpoint_every),
                                  _dptr(cost, "cost", K), _dptr(grad, "grad", 2 * N * K))
     _check("plan_rollout_grad", st, ctx)
+
+
+def plan_rollout_grad_noalloc(ctx, state0, controls, cost, grad, weight=None,
+                              checkpoint_every=10):
+    """plan_rollout_grad on the library's fixed per-GPU workspace (no
+    allocation; calls on one GPU must not overlap)."""
+    N, two, K = controls.shape
+    if two != 2:
+        raise ValueError("controls must be [N][2][K]")
+    s0 = (C.c_float * 13)(*[float(v) for v in state0])
+    st = lib().plan_rollout_grad_noalloc(ctx, s0, _dptr(controls, "controls"), K, N,
+                                         _dptr(weight, "weight", K), int(checkpoint_every),
+                                         _dptr(cost, "cost", K), _dptr(grad, "grad", 2 * N * K))
+    _check("plan_rollout_grad_noalloc", st, ctx)
 
 
 def plan_init_state(ctx, state0, state, cost):
