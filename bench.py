@@ -52,8 +52,8 @@ TRAFFIC_COUNTERS = {
     # as 131085.39 KiB (x1.99979) and written as 262144.0 KiB (x1.0)
     "c5": (54429.96, 385.69, 262144.0 / 131085.39, 1.0, "69693517c2390e54"),
 }
-ROLLOUT_SOURCES = ("rollout_step.h", "rollout_kernels.h", "rollout.hip", "rollout_multilane.hip",
-                   "plan_internal.h", "select_common.h", "sample.h")
+ROLLOUT_SOURCES = ("rollout_step.h", "rollout_kernels.h", "rollout.hip", "rollout_onelane_ilp.hip",
+                   "rollout_multilane.hip", "plan_internal.h", "select_common.h", "sample.h")
 
 
 def kernel_signature():
@@ -162,6 +162,15 @@ def _summ(lat, t_first, t_last, steps, n):
 # right-hand sides, the stage and combination updates, one set of limits.
 EST_OPS_PER_STEP = 130
 RK4_OPS_PER_STEP = 4 * (OPS_PER_STEP - 24) + 24 + 3 * 13 * 2 + 2 * 13
+# Adjoint, per candidate-step (same rules): the checkpointing forward pass
+# runs the Euler step (OPS_PER_STEP); the backward kernel recomputes the
+# step from its segment's checkpoint (OPS_PER_STEP) and evaluates the step's
+# vector-Jacobian product: its forward quantities (attitude and chassis 45,
+# four wheels of 128: gathers, slip, normal, suspension, tire) and the
+# reverse sweep (chassis rows, rotation, trigonometry 160; four wheels of 136;
+# wheel sums 63), 1 320 in all.
+ADJ_VJP_OPS_PER_STEP = 45 + 4 * 128 + 160 + 4 * 136 + 63
+ADJ_BWD_OPS_PER_STEP = OPS_PER_STEP + ADJ_VJP_OPS_PER_STEP
 HBM_PEAK_GBS = 8000.0
 
 
@@ -281,13 +290,27 @@ def rows_leg():
     w = inputs.c4()
     pl = P.Planner(w.vehicle, w.cost, w.integ, w.K, w.N, w.terrain.W, w.terrain.H)
     pl.set_terrain(dev(w.terrain.height), w.terrain.x0, w.terrain.y0, w.terrain.res)
-    res = {}
+    res = {"ops_per_step": {"forward": OPS_PER_STEP, "backward": ADJ_BWD_OPS_PER_STEP}}
     for name, Kk in (("K1024", w.K), ("top32", 32)):
         uk = dev(np.ascontiguousarray(w.controls[:, :, :Kk]))
         Jk = torch.empty(Kk, device="cuda")
         gk = torch.empty_like(uk)
         msg = _time_ms(lambda: pl.rollout_grad(w.state0, uk, Jk, gk, checkpoint_every=10))
-        res[name] = {"ms": msg, "forward_steps_per_s": Kk * w.N * 1e3 / msg}
+        # the backward kernel alone: HIP events on the planner's stream
+        pl.enable_timing(True)
+        bwd = []
+        for _ in range(5):
+            pl.rollout_grad(w.state0, uk, Jk, gk, checkpoint_every=10)
+            bwd.append(pl.last_rollout_ms())
+        pl.enable_timing(False)
+        bwd.sort()
+        ms_b = bwd[len(bwd) // 2]
+        steps = Kk * w.N
+        res[name] = {"ms": msg, "forward_steps_per_s": steps * 1e3 / msg,
+                     "alu_frac": alu((OPS_PER_STEP + ADJ_BWD_OPS_PER_STEP) * steps, msg / 1e3),
+                     "backward_kernel_ms": ms_b,
+                     "backward_alu_frac": alu(ADJ_BWD_OPS_PER_STEP * steps, ms_b / 1e3),
+                     "launch": list(pl.get_launch())}
     out["adjoint_c4"] = res
     pl.close()
 

@@ -410,7 +410,8 @@ plan_status_t plan_set_order(plan_ctx *ctx, int mode);
 plan_status_t plan_get_order(const plan_ctx *ctx, int *ordered);
 
 /* Kernel timing: when enabled, HIP events bracket each rollout kernel on the
- * context's stream; plan_last_rollout_ms waits for the end event and returns
+ * context's stream (for plan_rollout_grad and plan_rollout_grad_noalloc, the
+ * backward kernel); plan_last_rollout_ms waits for the end event and returns
  * the kernel's elapsed time in milliseconds. */
 plan_status_t plan_enable_timing(plan_ctx *ctx, int on);
 plan_status_t plan_last_rollout_ms(plan_ctx *ctx, float *ms);

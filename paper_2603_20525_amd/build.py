@@ -8,15 +8,19 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libplan.so")
-SOURCES = ["rollout.hip", "rollout_multilane.hip", "est.hip", "select.hip", "plan_api.hip",
-           "serve.hip", "adjoint.hip", "terrain_prep.hip", "order.hip"]
+SOURCES = ["rollout.hip", "rollout_onelane_ilp.hip", "rollout_multilane.hip", "est.hip",
+           "select.hip", "plan_api.hip", "serve.hip", "adjoint.hip", "terrain_prep.hip",
+           "order.hip"]
 
-# Per-source flags. The two- and four-lane rollout kernels are scheduled for
-# instruction-level parallelism: at small K each SIMD holds at most one wave,
-# so the per-step latency of a single wave is what counts (measured 3-4 %
-# faster; the one-lane kernels, which run at full occupancy, are not).
+# Per-source flags. The two- and four-lane rollout kernels, and the one-lane
+# kernels used for launches of at most one wave per SIMD, are scheduled for
+# instruction-level parallelism: each SIMD then holds at most one or two
+# waves, so the per-step latency of a single wave is what counts (measured
+# 3-4 % faster; the one-lane kernels of rollout.hip, which serve launches of
+# three or four waves per SIMD, are 2.6 % faster with the default schedule).
 SOURCE_FLAGS = {
     "rollout_multilane.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
+    "rollout_onelane_ilp.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
 }
 
 HIPCC_FLAGS = [

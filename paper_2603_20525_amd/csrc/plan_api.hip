@@ -45,6 +45,7 @@ struct plan_ctx {
     SelectOut *sel_host = nullptr;  // pinned
     uint32_t seq = 0;               // sequence number of the last published selection
     // launch shape
+    int simds = 1024;  // SIMDs of the device (4 per compute unit)
     int lanes_opt = 0, block_opt = 0;
     int last_lanes = 0, last_block = 0;
     // candidate order for gather locality (workspace for max_K)
@@ -239,18 +240,24 @@ bool finite_all(const float *p, int n) {
     return true;
 }
 
-void auto_launch(long long K, int *lanes, int *block) {
-    // Spread small candidate sets over more lanes (wheel-parallel); large
-    // sets use one lane per candidate to avoid redundant chassis work.
+void auto_launch(long long K, int simds, int *lanes, int *block) {
+    // Spread small candidate sets over more lanes (wheel-parallel); sets
+    // that give every SIMD a wave at one lane per candidate (65 536 on the
+    // MI355X's 1 024 SIMDs) use one lane, avoiding redundant chassis work.
     if (K <= 16384) {
         *lanes = 4;
-    } else if (K <= 65536) {
+    } else if (K < 65536) {
         *lanes = 2;
     } else {
         *lanes = 1;
     }
+    // Up to one wave per SIMD, four waves share each workgroup (and so a
+    // compute unit, its L1 and the fused selection's atomics: measured 2 %
+    // faster at both K = 4 096 x 4 lanes and K = 65 536 x 1 lane); with
+    // several waves per SIMD, one-wave workgroups balance better (2 % at the
+    // paper's 204 288 candidates).
     const long long waves = (K * *lanes + 63) / 64;
-    *block = (waves < 4096) ? 64 : 256;
+    *block = (waves <= simds) ? 256 : 64;
 }
 
 }  // namespace plan
@@ -299,6 +306,11 @@ plan_status_t plan_create(plan_ctx **out, const plan_vehicle_t *veh, const plan_
         }                                                   \
     } while (0)
     CREATE_TRY(hipGetDevice(&c->device));
+    {
+        int cus = 0;
+        CREATE_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+        if (cus > 0) c->simds = 4 * cus;
+    }
     CREATE_TRY(resolve_scratch(c->device));
     CREATE_TRY(hipMalloc(&c->tex, sizeof(float4) * (size_t)max_W * max_H));
     CREATE_TRY(hipMalloc(&c->smooth_tmp, sizeof(float) * (size_t)max_W * max_H));
@@ -448,7 +460,7 @@ static plan_status_t order_candidates(plan_ctx *c, RolloutArgs &a, float delta0,
 
 static plan_status_t launch(plan_ctx *c, RolloutArgs &a, Kind kind) {
     int lanes, block;
-    auto_launch(a.K, &lanes, &block);
+    auto_launch(a.K, c->simds, &lanes, &block);
     if (c->lanes_opt) lanes = c->lanes_opt;
     if (c->block_opt) block = c->block_opt;
     a.order = nullptr;
@@ -458,10 +470,13 @@ static plan_status_t launch(plan_ctx *c, RolloutArgs &a, Kind kind) {
     const bool ordered = kind != Kind::chunk && order_wanted(c, a.K, sampled ? &a.smp : nullptr);
     if (ordered && lanes != 1) {
         lanes = 1;
-        block = c->block_opt ? c->block_opt : (((long long)a.K + 63) / 64 < 4096 ? 64 : 256);
+        block = c->block_opt ? c->block_opt : (((long long)a.K + 63) / 64 <= c->simds ? 256 : 64);
     }
     c->last_lanes = lanes;
     c->last_block = block;
+    // one lane per candidate with at most one wave per SIMD: the kernels
+    // scheduled for instruction-level parallelism
+    const bool ilp = lanes == 1 && ((long long)a.K + 63) / 64 <= c->simds;
     HIP_TRY(c, hipSetDevice(c->device));
     if (c->timing) HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
     if (ordered) {
@@ -471,15 +486,15 @@ static plan_status_t launch(plan_ctx *c, RolloutArgs &a, Kind kind) {
     switch (kind) {
     case Kind::plain:
     case Kind::chunk:
-        HIP_TRY(c, plan::launch_rollout(a, lanes, block, kind == Kind::chunk, c->stream));
+        HIP_TRY(c, plan::launch_rollout(a, lanes, block, kind == Kind::chunk, c->stream, ilp));
         break;
     case Kind::sampled:
-        HIP_TRY(c, plan::launch_rollout_sampled(a, lanes, block, c->stream));
+        HIP_TRY(c, plan::launch_rollout_sampled(a, lanes, block, c->stream, ilp));
         break;
     case Kind::fused:
     case Kind::fused_sampled:
         HIP_TRY(c, plan::launch_rollout_argmin(a, lanes, block, kind == Kind::fused_sampled,
-                                               c->stream));
+                                               c->stream, ilp));
         break;
     }
     if (c->timing) {
@@ -888,13 +903,20 @@ static plan_status_t grad_launch(plan_ctx *c, const float *state0, const float *
     a.ckpt_every = C;
     // forward pass in one launch, storing the state at every C-th interval
     int lanes, block;
-    auto_launch(K, &lanes, &block);
+    auto_launch(K, c->simds, &lanes, &block);
     if (c->lanes_opt) lanes = c->lanes_opt;
     if (c->block_opt) block = c->block_opt;
+    c->last_lanes = lanes;
+    c->last_block = block;
     HIP_TRY(c, plan::launch_rollout_ckpt(a, lanes, block, c->stream));
     // the backward kernel splits the wheels over the same lanes
+    if (c->timing) HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
     HIP_TRY(c, plan::launch_adjoint_backward(a, C, ckpt, weight_dev, seg, grad_dev, lanes,
                                              c->stream));
+    if (c->timing) {
+        HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
+        c->ev_recorded = true;
+    }
     return PLAN_OK;
 }
 

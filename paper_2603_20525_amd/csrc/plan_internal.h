@@ -166,7 +166,11 @@ struct TickTable {
 
 // chunk = false: candidates start from s0 with zero cost. chunk = true:
 // they continue from a.state / a.cost. Both run the same step code.
-hipError_t launch_rollout(const RolloutArgs &a, int lanes, int block, bool chunk, hipStream_t s);
+// ilp (one lane per candidate only): use the kernels scheduled for
+// instruction-level parallelism, for launches of at most one wave per SIMD;
+// the arithmetic, and so every result, is the same either way.
+hipError_t launch_rollout(const RolloutArgs &a, int lanes, int block, bool chunk, hipStream_t s,
+                          bool ilp = false);
 
 // Full-horizon rollout that also stores every candidate's state at each
 // checkpoint (a.ckpt, a.ckpt_every): the adjoint's forward pass in one launch.
@@ -175,11 +179,12 @@ hipError_t launch_rollout_ckpt(const RolloutArgs &a, int lanes, int block, hipSt
 // Full-horizon rollout whose last workgroup to finish also selects the argmin
 // (a.sel_* and a.plan), with controls read (sampled = false) or drawn.
 hipError_t launch_rollout_argmin(const RolloutArgs &a, int lanes, int block, bool sampled,
-                                 hipStream_t s);
+                                 hipStream_t s, bool ilp = false);
 
 // As launch_rollout (full horizon from a.s0) with the controls drawn in the
 // kernel from a.smp instead of read from a.controls.
-hipError_t launch_rollout_sampled(const RolloutArgs &a, int lanes, int block, hipStream_t s);
+hipError_t launch_rollout_sampled(const RolloutArgs &a, int lanes, int block, hipStream_t s,
+                                  bool ilp = false);
 
 // controls [N][2][K] from the generator.
 hipError_t launch_sample_controls(const SampleArgs &sa, int K, int N, float *controls,
@@ -258,6 +263,8 @@ bool finite_all(const float *p, int n);
 bool valid_vehicle(const plan_vehicle_t &v);
 bool valid_cost(const plan_cost_t &c);
 bool valid_integ(const plan_integ_t &i);
-void auto_launch(long long K, int *lanes, int *block);
+// Launch shape for K candidates on a device of `simds` SIMDs: lanes per
+// candidate and the workgroup size.
+void auto_launch(long long K, int simds, int *lanes, int *block);
 
 }  // namespace plan

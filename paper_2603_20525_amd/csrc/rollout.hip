@@ -54,16 +54,19 @@ __global__ __launch_bounds__(256) void init_state(const RolloutArgs a) {
 
 }  // namespace
 
-// Public dispatch: one lane here, two and four lanes in rollout_multilane.hip.
+// Public dispatch: one lane here (or, with ilp, in rollout_onelane_ilp.hip),
+// two and four lanes in rollout_multilane.hip.
 hipError_t launch_rollout(const RolloutArgs &a, int lanes, int block, bool chunk,
-                          hipStream_t s) {
-    return lanes == 1 ? launch_rollout_lanes<1>(a, block, chunk, s)
-                      : launch_rollout_multi(a, lanes, block, chunk, s);
+                          hipStream_t s, bool ilp) {
+    if (lanes != 1) return launch_rollout_multi(a, lanes, block, chunk, s);
+    return ilp ? launch_rollout_ilp1(a, block, chunk, s)
+               : launch_rollout_lanes<1>(a, block, chunk, s);
 }
 
-hipError_t launch_rollout_sampled(const RolloutArgs &a, int lanes, int block, hipStream_t s) {
-    return lanes == 1 ? launch_sampled_lanes<1>(a, block, s)
-                      : launch_sampled_multi(a, lanes, block, s);
+hipError_t launch_rollout_sampled(const RolloutArgs &a, int lanes, int block, hipStream_t s,
+                                  bool ilp) {
+    if (lanes != 1) return launch_sampled_multi(a, lanes, block, s);
+    return ilp ? launch_sampled_ilp1(a, block, s) : launch_sampled_lanes<1>(a, block, s);
 }
 
 hipError_t launch_rollout_ckpt(const RolloutArgs &a, int lanes, int block, hipStream_t s) {
@@ -71,9 +74,10 @@ hipError_t launch_rollout_ckpt(const RolloutArgs &a, int lanes, int block, hipSt
 }
 
 hipError_t launch_rollout_argmin(const RolloutArgs &a, int lanes, int block, bool sampled,
-                                 hipStream_t s) {
-    return lanes == 1 ? launch_argmin_lanes<1>(a, block, sampled, s)
-                      : launch_argmin_multi(a, lanes, block, sampled, s);
+                                 hipStream_t s, bool ilp) {
+    if (lanes != 1) return launch_argmin_multi(a, lanes, block, sampled, s);
+    return ilp ? launch_argmin_ilp1(a, block, sampled, s)
+               : launch_argmin_lanes<1>(a, block, sampled, s);
 }
 
 hipError_t launch_rollout_slots(const RolloutArgs *slots, const TickTable &t, int *bad,

@@ -1,10 +1,12 @@
 // Rollout kernel templates (SRB model, stage cost, ESM constraint) and, per
-// lane count, their launch dispatch. Two translation units instantiate them:
-// rollout.hip (one lane per candidate) and rollout_multilane.hip (two and four
-// lanes per candidate, compiled with the max-ILP instruction scheduler, which
-// shortens the per-step latency of the lane-split kernels and lengthens the
-// one-lane kernel's). The arithmetic is the same in both, so results are
-// identical for every launch shape.
+// lane count, their launch dispatch. Three translation units instantiate
+// them: rollout.hip (one lane per candidate), rollout_onelane_ilp.hip (one
+// lane per candidate for launches of at most one wave per SIMD) and
+// rollout_multilane.hip (two and four lanes per candidate); the last two are
+// compiled with the max-ILP instruction scheduler, which shortens the
+// per-step latency of a wave that has its SIMD to itself and lengthens the
+// step where three or four one-lane waves share a SIMD. The arithmetic is the
+// same in all, so results are identical for every launch shape.
 #pragma once
 
 #include "plan_internal.h"
@@ -372,6 +374,12 @@ __forceinline__ hipError_t launch_slots_lanes(const RolloutArgs *slots, const Ti
 }
 
 }  // namespace
+
+// One-lane dispatch on the kernels built with the max-ILP scheduler, defined
+// in rollout_onelane_ilp.hip.
+hipError_t launch_rollout_ilp1(const RolloutArgs &a, int block, bool chunk, hipStream_t s);
+hipError_t launch_sampled_ilp1(const RolloutArgs &a, int block, hipStream_t s);
+hipError_t launch_argmin_ilp1(const RolloutArgs &a, int block, bool sampled, hipStream_t s);
 
 // Two- and four-lane dispatch, defined in rollout_multilane.hip.
 hipError_t launch_rollout_multi(const RolloutArgs &a, int lanes, int block, bool chunk,

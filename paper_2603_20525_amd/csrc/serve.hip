@@ -90,6 +90,7 @@ struct Step {
 
 struct plan_server {
     int device = 0;
+    int simds = 1024;  // SIMDs of the device (4 per compute unit)
     hipStream_t stream = nullptr;
     plan_vehicle_t veh{};
     int max_slots = 0, max_K = 0, max_N = 0, max_W = 0, max_H = 0, chunk = 1;
@@ -302,7 +303,7 @@ static plan_status_t launch_step(plan_server *s) {
         if (s->slots[i].req >= 0) total_K += s->reqs[s->slots[i].req].r.K;
     if (total_K == 0) return PLAN_OK;
     int lanes, block;
-    plan::auto_launch(total_K, &lanes, &block);
+    plan::auto_launch(total_K, s->simds, &lanes, &block);
     Step st;
     int blocks = 0;
     for (int i = 0; i < s->max_slots; ++i) {
@@ -394,6 +395,11 @@ plan_status_t plan_server_create(plan_server **out, const plan_vehicle_t *veh, i
     hipError_t e = hipSuccess;
     const size_t S = (size_t)max_slots;
     if (e == hipSuccess) e = hipGetDevice(&s->device);
+    if (e == hipSuccess) {
+        int cus = 0;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device);
+        if (e == hipSuccess && cus > 0) s->simds = 4 * cus;
+    }
     if (e == hipSuccess) e = hipMalloc(&s->tex, sizeof(float4) * S * max_W * max_H);
     if (e == hipSuccess) e = hipMalloc(&s->state, sizeof(float) * S * 13 * max_K);
     if (e == hipSuccess) e = hipMalloc(&s->cost, sizeof(float) * S * max_K);
