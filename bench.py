@@ -48,9 +48,11 @@ ALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
 # change, the figure no longer describes the kernel and is reported as null.
 # workload: (FETCH_SIZE KiB, WRITE_SIZE KiB, fetch scale, write scale, signature)
 TRAFFIC_COUNTERS = {
-    # fused kernel at two lanes per candidate; copy calibration 262144 KiB read
-    # as 131085.39 KiB (x1.99979) and written as 262144.0 KiB (x1.0)
-    "c5": (54429.96, 385.69, 262144.0 / 131085.39, 1.0, "69693517c2390e54"),
+    # fused kernel, one lane per candidate (c5) and four lanes (c2), 256-thread
+    # workgroups; copy calibration 262144 KiB read as 131085.35 KiB (x1.99979)
+    # and written as 262144.0 KiB (x1.0)
+    "c5": (54099.69, 273.69, 262144.0 / 131085.35, 1.0, "9ce239d8fd021bf0"),
+    "c2": (2157.76, 20.91, 262144.0 / 131085.35, 1.0, "9ce239d8fd021bf0"),
 }
 ROLLOUT_SOURCES = ("rollout_step.h", "rollout_kernels.h", "rollout.hip", "rollout_onelane_ilp.hip",
                    "rollout_multilane.hip", "plan_internal.h", "select_common.h", "sample.h")

@@ -104,9 +104,10 @@ enum { PLAN_ARGMIN = 0, PLAN_SOFTMIN = 1 };
  * once here (terrain texels 16*max_W*max_H bytes, the candidate-order
  * workspace about 32*max_K bytes, plus selection scratch).
  * hip_stream is a hipStream_t, or NULL for the default stream.
- * Errors: PLAN_EINVAL for NULL pointers, non-positive sizes or invalid
- * parameters (M, J, Lf+Lr, e, hR, dt <= 0, substeps < 1, non-finite values);
- * PLAN_ENOMEM; PLAN_EDEVICE. *out is set only on success. */
+ * Errors: PLAN_EINVAL for NULL pointers, non-positive sizes, a texel grid
+ * max_W*max_H of 2^27 nodes or more, or invalid parameters (M, J, Lf+Lr, e,
+ * hR, dt <= 0, substeps < 1, non-finite values); PLAN_ENOMEM; PLAN_EDEVICE.
+ * *out is set only on success. */
 plan_status_t plan_create(plan_ctx **out, const plan_vehicle_t *veh,
                           const plan_cost_t *cost, const plan_integ_t *integ,
                           int max_K, int max_N, int max_W, int max_H,

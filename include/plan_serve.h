@@ -73,7 +73,8 @@ typedef struct {
 } plan_result_t;
 
 /* Create a server on the current device. max_slots (<= 128) requests may be
- * resident at once, each with K <= max_K, N <= max_N, W <= max_W, H <= max_H.
+ * resident at once, each with K <= max_K, N <= max_N, W <= max_W, H <= max_H
+ * (max_W*max_H below 2^27).
  * A request's footprint is 16*W*H (texels) + 56*K (state, cost) + 8*K*N
  * (controls) + 8*N (plan) bytes; a request is admitted only while the summed
  * footprint of resident requests stays within budget_bytes.

@@ -26,8 +26,10 @@ __device__ __forceinline__ float4 bilinear(const RolloutArgs &a, float Px, float
     const int i = min((int)u, a.W - 2);
     const int j = min((int)v, a.H - 2);
     const float tx = u - (float)i, ty = v - (float)j;
-    const float4 *p = a.tex + (size_t)j * a.W + i;
-    const float4 t00 = p[0], t10 = p[1], t01 = p[a.W], t11 = p[a.W + 1];
+    const __amdgpu_buffer_rsrc_t rs = texel_rsrc(a);
+    const int off = (j * a.W + i) << 4, row = a.W << 4;
+    const float4 t00 = load_texel(rs, off, 0), t10 = load_texel(rs, off + 16, 0);
+    const float4 t01 = load_texel(rs, off, row), t11 = load_texel(rs, off + 16, row);
     return make_float4(lerp2(tx, ty, t00.x, t10.x, t01.x, t11.x),
                        lerp2(tx, ty, t00.y, t10.y, t01.y, t11.y),
                        lerp2(tx, ty, t00.z, t10.z, t01.z, t11.z),

@@ -280,8 +280,8 @@ plan_status_t plan_create(plan_ctx **out, const plan_vehicle_t *veh, const plan_
     if (!valid_integ(*integ)) return fail(nullptr, PLAN_EINVAL, "invalid integration parameters");
     if (max_K < 1 || max_N < 1 || max_W < 2 || max_H < 2)
         return fail(nullptr, PLAN_EINVAL, "max sizes must be K,N >= 1 and W,H >= 2");
-    if ((long long)max_W * max_H > (1ll << 28))
-        return fail(nullptr, PLAN_EINVAL, "terrain grid too large");
+    if ((long long)max_W * max_H >= (1ll << 27))
+        return fail(nullptr, PLAN_EINVAL, "terrain grid too large (W*H must be below 2^27)");
     if ((long long)max_K * 4 > 0x7fffffffll) return fail(nullptr, PLAN_EINVAL, "max_K too large");
 
     plan_ctx *c = new (std::nothrow) plan_ctx;

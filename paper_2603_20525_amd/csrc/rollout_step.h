@@ -88,6 +88,23 @@ struct Gather {
     float tx, ty, Pz;
 };
 
+// Buffer resource over the W x H float4 texel grid (fewer than 2^27 texels,
+// a limit plan_create and plan_server_create enforce, so every byte offset
+// fits in 31 bits). A buffer load takes a 32-bit offset from a scalar base
+// instead of a 64-bit address per lane, which saves the 64-bit address
+// arithmetic of the four gathers of each wheel.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t texel_rsrc(const RolloutArgs &a) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float4 *>(a.tex), 0,
+                                             a.W * a.H * 16, 0x00020000);
+}
+
+__device__ __forceinline__ float4 load_texel(__amdgpu_buffer_rsrc_t rs, int off, int soff) {
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, soff, 0);
+    return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z),
+                       __uint_as_float(v.w));
+}
+
 __device__ __forceinline__ Gather gather(const RolloutArgs &a, const Attitude &A, float x,
                                          float y, float z, const Arm &r) {
     // contact point P = p + R rho (world)
@@ -104,11 +121,15 @@ __device__ __forceinline__ Gather gather(const RolloutArgs &a, const Attitude &A
     const int j = min((int)v, a.H - 2);
     g.tx = u - (float)i;
     g.ty = v - (float)j;
-    const float4 *p = a.tex + (size_t)j * a.W + i;
-    g.t00 = p[0];
-    g.t10 = p[1];
-    g.t01 = p[a.W];
-    g.t11 = p[a.W + 1];
+    // one 32-bit byte offset per wheel: the right neighbour through the
+    // load's immediate offset, the next row through the scalar row pitch
+    const __amdgpu_buffer_rsrc_t rs = texel_rsrc(a);
+    const int off = (j * a.W + i) << 4;
+    const int row = a.W << 4;
+    g.t00 = load_texel(rs, off, 0);
+    g.t10 = load_texel(rs, off + 16, 0);
+    g.t01 = load_texel(rs, off, row);
+    g.t11 = load_texel(rs, off + 16, row);
     return g;
 }
 

@@ -304,6 +304,10 @@ static plan_status_t launch_step(plan_server *s) {
     if (total_K == 0) return PLAN_OK;
     int lanes, block;
     plan::auto_launch(total_K, s->simds, &lanes, &block);
+    // a tick's slots are small independent plans: one-wave workgroups spread
+    // each over more compute units (four-wave workgroups lengthened a lone
+    // request's latency at 200 req/s from 0.088 to 0.11 ms)
+    block = (total_K * lanes + 63) / 64 < 4096 ? 64 : 256;
     Step st;
     int blocks = 0;
     for (int i = 0; i < s->max_slots; ++i) {
@@ -376,7 +380,7 @@ plan_status_t plan_server_create(plan_server **out, const plan_vehicle_t *veh, i
         return sfail(nullptr, PLAN_EINVAL, "max_slots outside [1, 128]");
     if (max_K < 1 || max_N < 1 || max_W < 2 || max_H < 2 || chunk_intervals < 1)
         return sfail(nullptr, PLAN_EINVAL, "sizes must be K,N,chunk >= 1 and W,H >= 2");
-    if ((long long)max_K * 4 > 0x7fffffffll || (long long)max_W * max_H > (1ll << 28))
+    if ((long long)max_K * 4 > 0x7fffffffll || (long long)max_W * max_H >= (1ll << 27))
         return sfail(nullptr, PLAN_EINVAL, "sizes too large");
     if (budget_bytes == 0) return sfail(nullptr, PLAN_EINVAL, "budget must be positive");
     plan_server *s = new (std::nothrow) plan_server;
