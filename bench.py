@@ -34,8 +34,13 @@ METRIC = "candidate rollout-steps/sec and p50/p99 plan latency (serving vs plain
 # candidate, transcendentals counted as one: goal test 5, attitude 21,
 # kinematics 26, four wheels of 101, wheel sums 18, right-hand side rows 17,
 # ESM and soft cost 12, running cost 5, Euler update and clamps 19, control
-# clamp 5 per interval. Used for the algorithmic side of the ALU roofline.
-OPS_PER_STEP = 532
+# clamp 5 per interval: 532 with a costmap. A plan without a costmap has no
+# cost-channel term (its bilinear interpolation at the four wheels 24, its
+# wheel sum 3 and its addition to the running cost 1), and its kernels skip
+# it: 504. Every workload here runs without a costmap, so the algorithmic
+# side of the ALU roofline counts 504.
+OPS_PER_STEP_COSTMAP = 532
+OPS_PER_STEP = OPS_PER_STEP_COSTMAP - 28
 # MI355X vector ALU issue: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz, one
 # non-packed FP32 operation per lane per clock.
 ALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
@@ -49,10 +54,10 @@ ALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
 # workload: (FETCH_SIZE KiB, WRITE_SIZE KiB, fetch scale, write scale, signature)
 TRAFFIC_COUNTERS = {
     # fused kernel, one lane per candidate (c5) and four lanes (c2), 256-thread
-    # workgroups; copy calibration 262144 KiB read as 131085.35 KiB (x1.99979)
-    # and written as 262144.0 KiB (x1.0)
-    "c5": (54099.69, 273.69, 262144.0 / 131085.35, 1.0, "9ce239d8fd021bf0"),
-    "c2": (2157.76, 20.91, 262144.0 / 131085.35, 1.0, "9ce239d8fd021bf0"),
+    # workgroups, no costmap; copy calibration 262144 KiB read as 131085.48 KiB
+    # (x1.99979) and written as 262144.0 KiB (x1.0)
+    "c5": (54098.70, 273.69, 262144.0 / 131085.48, 1.0, "48a925eae0e63d76"),
+    "c2": (2157.26, 20.91, 262144.0 / 131085.48, 1.0, "48a925eae0e63d76"),
 }
 ROLLOUT_SOURCES = ("rollout_step.h", "rollout_kernels.h", "rollout.hip", "rollout_onelane_ilp.hip",
                    "rollout_multilane.hip", "plan_internal.h", "select_common.h", "sample.h")
@@ -164,14 +169,15 @@ def _summ(lat, t_first, t_last, steps, n):
 # right-hand sides, the stage and combination updates, one set of limits.
 EST_OPS_PER_STEP = 130
 RK4_OPS_PER_STEP = 4 * (OPS_PER_STEP - 24) + 24 + 3 * 13 * 2 + 2 * 13
-# Adjoint, per candidate-step (same rules): the checkpointing forward pass
-# runs the Euler step (OPS_PER_STEP); the backward kernel recomputes the
-# step from its segment's checkpoint (OPS_PER_STEP) and evaluates the step's
-# vector-Jacobian product: its forward quantities (attitude and chassis 45,
-# four wheels of 128: gathers, slip, normal, suspension, tire) and the
-# reverse sweep (chassis rows, rotation, trigonometry 160; four wheels of 136;
-# wheel sums 63), 1 320 in all.
-ADJ_VJP_OPS_PER_STEP = 45 + 4 * 128 + 160 + 4 * 136 + 63
+# Adjoint, per candidate-step (same rules, no costmap): the checkpointing
+# forward pass runs the Euler step (OPS_PER_STEP); the backward kernel
+# recomputes the step from its segment's checkpoint (OPS_PER_STEP) and
+# evaluates the step's vector-Jacobian product: its forward quantities
+# (attitude and chassis 45, four wheels of 128: gathers, slip, normal,
+# suspension, tire) and the reverse sweep (chassis rows, rotation,
+# trigonometry 160; four wheels of 128, the cost channel's cell-weight
+# derivatives left out; wheel sums 63), 1 292 in all.
+ADJ_VJP_OPS_PER_STEP = 45 + 4 * 128 + 160 + 4 * 128 + 63
 ADJ_BWD_OPS_PER_STEP = OPS_PER_STEP + ADJ_VJP_OPS_PER_STEP
 HBM_PEAK_GBS = 8000.0
 

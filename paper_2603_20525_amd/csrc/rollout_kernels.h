@@ -25,7 +25,7 @@ namespace {
 // a.controls. Lanes with store == false run a duplicate candidate only to
 // keep their lane group complete.
 template <int LANES, bool CHUNK, bool SAMPLED = false, bool RK4 = false, bool CKPT = false,
-          bool S1 = false>
+          bool S1 = false, bool CM = true>
 __device__ __forceinline__ float simulate(const RolloutArgs &a, int k, int sub, bool store,
                                           const float *up) {
     constexpr int WPL = 4 / LANES;  // wheels per lane
@@ -114,11 +114,11 @@ __device__ __forceinline__ float simulate(const RolloutArgs &a, int k, int sub, 
                 if (fmaf(gdx, gdx, gdy * gdy) <= a.goal_r2) continue;
             }
             if constexpr (RK4) {
-                rk4_step<LANES>(a, arms, st, J, dd, ax);
+                rk4_step<LANES, CM>(a, arms, st, J, dd, ax);
             } else if constexpr (SAMPLED) {
-                euler_step<LANES>(a, arms, st, J, dd, ax);
+                euler_step<LANES, CM>(a, arms, st, J, dd, ax);
             } else {
-                euler_step<LANES>(a, arms, st, J, dd, ax, [&]() {
+                euler_step<LANES, CM>(a, arms, st, J, dd, ax, [&]() {
                     nu0 = unext[0];
                     nu1 = unext[K];
                 });
@@ -199,9 +199,27 @@ __device__ __forceinline__ void argmin_epilogue(const RolloutArgs &a, unsigned l
     write_plan<SAMPLED>(kb, a.N, a.K, a.controls, a.smp, a.drate_max, a.plan, tid, BLOCK);
 }
 
+// One-lane full-horizon launches with several Euler substeps per interval and
+// no costmap (the paper's solver shape) are held to 128 VGPRs, four waves per
+// SIMD, so its 204 288 candidates (3.1 waves per SIMD) run in one round
+// instead of three full rounds and a tail: the materialised-control kernel
+// fits in 126 registers, the in-kernel-sampled one spills 15-17 registers
+// (its generator words, read once per interval) and is 4.7 % faster all the
+// same (2.93 -> 2.79 ms per ordered plan).
+// (The instantiation for launches of at most one wave per SIMD, built with
+// PLAN_ONE_WAVE_PER_SIMD, has no use for the bound.)
+#ifdef PLAN_ONE_WAVE_PER_SIMD
+template <int LANES, bool CHUNK, bool RK4, bool CKPT, bool S1, bool CM>
+constexpr bool ONE_LANE_4_WAVES = false;
+#else
+template <int LANES, bool CHUNK, bool RK4, bool CKPT, bool S1, bool CM>
+constexpr bool ONE_LANE_4_WAVES = LANES == 1 && !CHUNK && !RK4 && !CKPT && !S1 && !CM;
+#endif
+
 template <int LANES, int BLOCK, bool CHUNK, bool SAMPLED = false, bool FUSED = false,
-          bool RK4 = false, bool CKPT = false, bool S1 = false>
-__global__ __launch_bounds__(BLOCK) void rollout_srb(const RolloutArgs a) {
+          bool RK4 = false, bool CKPT = false, bool S1 = false, bool CM = true>
+__global__ __launch_bounds__(BLOCK, (ONE_LANE_4_WAVES<LANES, CHUNK, RK4, CKPT, S1, CM> ? 4 : 1))
+void rollout_srb(const RolloutArgs a) {
     const int gtid = blockIdx.x * BLOCK + threadIdx.x;
     const int sub = gtid & (LANES - 1);
     int slot = gtid / LANES;
@@ -221,7 +239,7 @@ __global__ __launch_bounds__(BLOCK) void rollout_srb(const RolloutArgs a) {
             up = a.controls_lane ? a.controls_lane + slot : a.controls + k;
         }
     }
-    const float J = simulate<LANES, CHUNK, SAMPLED, RK4, CKPT, S1>(a, k, sub, store, up);
+    const float J = simulate<LANES, CHUNK, SAMPLED, RK4, CKPT, S1, CM>(a, k, sub, store, up);
     if constexpr (FUSED)
         argmin_epilogue<BLOCK, SAMPLED>(a, (store && sub == 0) ? cost_key(J, k) : ~0ull,
                                         gridDim.x, a.sel_out_host, nullptr);
@@ -266,24 +284,25 @@ __global__ __launch_bounds__(BLOCK) void rollout_slots(const RolloutArgs *__rest
                                       ring + te.slot, bad + te.slot);
 }
 
-// Launch dispatch for one lane count L (block 64 or 256). Euler launches
-// with one substep per interval (a.S == 1) use the S1 instantiations, which
-// carry no substep loop.
-template <int L>
-__forceinline__ hipError_t launch_rollout_lanes(const RolloutArgs &a, int block, bool chunk,
-                                                hipStream_t s) {
+// Launch dispatch for one lane count L (block 64 or 256) and costmap flag CM
+// (the context's a.has_costmap). Euler launches with one substep per interval
+// (a.S == 1) use the S1 instantiations, which carry no substep loop.
+template <int L, bool CM>
+__forceinline__ hipError_t launch_rollout_cm(const RolloutArgs &a, int block, bool chunk,
+                                             hipStream_t s) {
     const long long threads = (long long)a.K * L;
     const unsigned grid = (unsigned)((threads + block - 1) / block);
 #define PLAN_LAUNCH(B, C)                                                                       \
     if (block == B && chunk == C) {                                                             \
         if (a.method == 1)                                                                      \
-            hipLaunchKernelGGL((rollout_srb<L, B, C, false, false, true>), dim3(grid), dim3(B),  \
-                               0, s, a);                                                        \
+            hipLaunchKernelGGL((rollout_srb<L, B, C, false, false, true, false, false, CM>),     \
+                               dim3(grid), dim3(B), 0, s, a);                                   \
         else if (a.S == 1)                                                                      \
-            hipLaunchKernelGGL((rollout_srb<L, B, C, false, false, false, false, true>),         \
+            hipLaunchKernelGGL((rollout_srb<L, B, C, false, false, false, false, true, CM>),     \
                                dim3(grid), dim3(B), 0, s, a);                                   \
         else                                                                                    \
-            hipLaunchKernelGGL((rollout_srb<L, B, C>), dim3(grid), dim3(B), 0, s, a);           \
+            hipLaunchKernelGGL((rollout_srb<L, B, C, false, false, false, false, false, CM>),    \
+                               dim3(grid), dim3(B), 0, s, a);                                   \
         return hipGetLastError();                                                               \
     }
     PLAN_LAUNCH(64, false)
@@ -295,16 +314,31 @@ __forceinline__ hipError_t launch_rollout_lanes(const RolloutArgs &a, int block,
 }
 
 template <int L>
-__forceinline__ hipError_t launch_sampled_lanes(const RolloutArgs &a, int block, hipStream_t s) {
+__forceinline__ hipError_t launch_rollout_lanes(const RolloutArgs &a, int block, bool chunk,
+                                                hipStream_t s) {
+    return a.has_costmap ? launch_rollout_cm<L, true>(a, block, chunk, s)
+                         : launch_rollout_cm<L, false>(a, block, chunk, s);
+}
+
+template <int L, bool CM>
+__forceinline__ hipError_t launch_sampled_cm(const RolloutArgs &a, int block, hipStream_t s) {
     const long long threads = (long long)a.K * L;
     const unsigned grid = (unsigned)((threads + block - 1) / block);
     if (block == 64)
-        hipLaunchKernelGGL((rollout_srb<L, 64, false, true>), dim3(grid), dim3(64), 0, s, a);
+        hipLaunchKernelGGL((rollout_srb<L, 64, false, true, false, false, false, false, CM>),
+                           dim3(grid), dim3(64), 0, s, a);
     else if (block == 256)
-        hipLaunchKernelGGL((rollout_srb<L, 256, false, true>), dim3(grid), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((rollout_srb<L, 256, false, true, false, false, false, false, CM>),
+                           dim3(grid), dim3(256), 0, s, a);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
+}
+
+template <int L>
+__forceinline__ hipError_t launch_sampled_lanes(const RolloutArgs &a, int block, hipStream_t s) {
+    return a.has_costmap ? launch_sampled_cm<L, true>(a, block, s)
+                         : launch_sampled_cm<L, false>(a, block, s);
 }
 
 template <int L>
@@ -327,28 +361,35 @@ __forceinline__ hipError_t launch_ckpt_lanes(const RolloutArgs &a, int block, hi
     return hipErrorInvalidValue;
 }
 
-template <int L>
-__forceinline__ hipError_t launch_argmin_lanes(const RolloutArgs &a, int block, bool sampled,
-                                               hipStream_t s) {
+template <int L, bool CM>
+__forceinline__ hipError_t launch_argmin_cm(const RolloutArgs &a, int block, bool sampled,
+                                            hipStream_t s) {
     const long long threads = (long long)a.K * L;
     const unsigned grid = (unsigned)((threads + block - 1) / block);
 #define PLAN_LAUNCH(B)                                                                          \
     if (block == B) {                                                                           \
         if (sampled)                                                                            \
-            hipLaunchKernelGGL((rollout_srb<L, B, false, true, true>), dim3(grid), dim3(B), 0,   \
-                               s, a);                                                           \
+            hipLaunchKernelGGL((rollout_srb<L, B, false, true, true, false, false, false, CM>),  \
+                               dim3(grid), dim3(B), 0, s, a);                                   \
         else if (a.S == 1)                                                                      \
-            hipLaunchKernelGGL((rollout_srb<L, B, false, false, true, false, false, true>),      \
+            hipLaunchKernelGGL((rollout_srb<L, B, false, false, true, false, false, true, CM>),  \
                                dim3(grid), dim3(B), 0, s, a);                                   \
         else                                                                                    \
-            hipLaunchKernelGGL((rollout_srb<L, B, false, false, true>), dim3(grid), dim3(B), 0,  \
-                               s, a);                                                           \
+            hipLaunchKernelGGL((rollout_srb<L, B, false, false, true, false, false, false, CM>), \
+                               dim3(grid), dim3(B), 0, s, a);                                   \
         return hipGetLastError();                                                               \
     }
     PLAN_LAUNCH(64)
     PLAN_LAUNCH(256)
 #undef PLAN_LAUNCH
     return hipErrorInvalidValue;
+}
+
+template <int L>
+__forceinline__ hipError_t launch_argmin_lanes(const RolloutArgs &a, int block, bool sampled,
+                                               hipStream_t s) {
+    return a.has_costmap ? launch_argmin_cm<L, true>(a, block, sampled, s)
+                         : launch_argmin_cm<L, false>(a, block, sampled, s);
 }
 
 // s1: every slot of the tick integrates with one substep per interval.

@@ -105,6 +105,18 @@ __device__ __forceinline__ float4 load_texel(__amdgpu_buffer_rsrc_t rs, int off,
                        __uint_as_float(v.w));
 }
 
+// The first three channels (h, f_x, f_y) of a texel; the cost channel reads
+// as 0 (the grid's cost channel is 0 wherever no costmap is set).
+__device__ __forceinline__ float4 load_texel3(__amdgpu_buffer_rsrc_t rs, int off, int soff) {
+    typedef unsigned u32x3 __attribute__((ext_vector_type(3)));
+    const u32x3 v = __builtin_amdgcn_raw_buffer_load_b96(rs, off, soff, 0);
+    return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), 0.0f);
+}
+
+// CM: the context has a costmap; without one only (h, f_x, f_y) are loaded
+// and the cost channel is neither interpolated nor summed (it is 0 there, so
+// the results are the same bits).
+template <bool CM = true>
 __device__ __forceinline__ Gather gather(const RolloutArgs &a, const Attitude &A, float x,
                                          float y, float z, const Arm &r) {
     // contact point P = p + R rho (world)
@@ -126,10 +138,17 @@ __device__ __forceinline__ Gather gather(const RolloutArgs &a, const Attitude &A
     const __amdgpu_buffer_rsrc_t rs = texel_rsrc(a);
     const int off = (j * a.W + i) << 4;
     const int row = a.W << 4;
-    g.t00 = load_texel(rs, off, 0);
-    g.t10 = load_texel(rs, off + 16, 0);
-    g.t01 = load_texel(rs, off, row);
-    g.t11 = load_texel(rs, off + 16, row);
+    if constexpr (CM) {
+        g.t00 = load_texel(rs, off, 0);
+        g.t10 = load_texel(rs, off + 16, 0);
+        g.t01 = load_texel(rs, off, row);
+        g.t11 = load_texel(rs, off + 16, row);
+    } else {
+        g.t00 = load_texel3(rs, off, 0);
+        g.t10 = load_texel3(rs, off + 16, 0);
+        g.t01 = load_texel3(rs, off, row);
+        g.t11 = load_texel3(rs, off + 16, row);
+    }
     return g;
 }
 
@@ -178,6 +197,7 @@ __device__ __forceinline__ WheelPre wheel_pre(const RolloutArgs &a, const Motion
     return p;
 }
 
+template <bool CM = true>
 __device__ __forceinline__ WheelOut wheel(const RolloutArgs &a, const Attitude &A,
                                           const Motion &m, const Arm &r, const Gather &g,
                                           const WheelPre &p) {
@@ -186,7 +206,7 @@ __device__ __forceinline__ WheelOut wheel(const RolloutArgs &a, const Attitude &
     const float th = lerp2(g.tx, g.ty, g.t00.x, g.t10.x, g.t01.x, g.t11.x);
     const float tfx = lerp2(g.tx, g.ty, g.t00.y, g.t10.y, g.t01.y, g.t11.y);
     const float tfy = lerp2(g.tx, g.ty, g.t00.z, g.t10.z, g.t01.z, g.t11.z);
-    const float tc = lerp2(g.tx, g.ty, g.t00.w, g.t10.w, g.t01.w, g.t11.w);
+    const float tc = CM ? lerp2(g.tx, g.ty, g.t00.w, g.t10.w, g.t01.w, g.t11.w) : 0.0f;
     // upward terrain normal (-f_x, -f_y, 1) resolved in the body frame
     const float nBx = fmaf(-A.R11, tfx, fmaf(-A.R21, tfy, A.R31));
     const float nBy = fmaf(-A.R12, tfx, fmaf(-A.R22, tfy, A.R32));
@@ -233,7 +253,7 @@ struct NoHook {
 // return value is the running cost rate L at the state. A hook other than
 // NoHook runs after the gathers are issued, behind a scheduling barrier so
 // that its loads stay after them.
-template <int LANES, class Hook = NoHook>
+template <int LANES, bool CM = true, class Hook = NoHook>
 __device__ __forceinline__ float srb_rhs(const RolloutArgs &a, const Arm (&arms)[4 / LANES],
                                          const float (&st)[13], float dd, float ax,
                                          float (&xd)[13], const Hook &hook = Hook()) {
@@ -249,7 +269,7 @@ __device__ __forceinline__ float srb_rhs(const RolloutArgs &a, const Arm (&arms)
     const Attitude A = attitude(psi, th, ph);
     Gather G[WPL];
 #pragma unroll
-    for (int q = 0; q < WPL; ++q) G[q] = gather(a, A, x, y, z, arms[q]);
+    for (int q = 0; q < WPL; ++q) G[q] = gather<CM>(a, A, x, y, z, arms[q]);
     if constexpr (!std::is_same<Hook, NoHook>::value) {
         __builtin_amdgcn_sched_barrier(0);
         hook();
@@ -297,22 +317,23 @@ __device__ __forceinline__ float srb_rhs(const RolloutArgs &a, const Arm (&arms)
     // order (w0 + w1) + (w2 + w3)
     WheelOut sum;
     if constexpr (WPL == 4) {
-        const WheelOut w0 = wheel(a, A, m, arms[0], G[0], pre[0]);
-        const WheelOut w1 = wheel(a, A, m, arms[1], G[1], pre[1]);
-        const WheelOut w2 = wheel(a, A, m, arms[2], G[2], pre[2]);
-        const WheelOut w3 = wheel(a, A, m, arms[3], G[3], pre[3]);
+        const WheelOut w0 = wheel<CM>(a, A, m, arms[0], G[0], pre[0]);
+        const WheelOut w1 = wheel<CM>(a, A, m, arms[1], G[1], pre[1]);
+        const WheelOut w2 = wheel<CM>(a, A, m, arms[2], G[2], pre[2]);
+        const WheelOut w3 = wheel<CM>(a, A, m, arms[3], G[3], pre[3]);
         sum = wadd(wadd(w0, w1), wadd(w2, w3));
     } else if constexpr (WPL == 2) {
-        sum = wadd(wheel(a, A, m, arms[0], G[0], pre[0]), wheel(a, A, m, arms[1], G[1], pre[1]));
+        sum = wadd(wheel<CM>(a, A, m, arms[0], G[0], pre[0]),
+                   wheel<CM>(a, A, m, arms[1], G[1], pre[1]));
     } else {
-        sum = wheel(a, A, m, arms[0], G[0], pre[0]);
+        sum = wheel<CM>(a, A, m, arms[0], G[0], pre[0]);
     }
     const float Fy = group_sum<LANES>(sum.Fy);
     const float Fz = group_sum<LANES>(sum.Fz);
     const float Mx = group_sum<LANES>(sum.Mx);
     const float My = group_sum<LANES>(sum.My);
     const float Mz = group_sum<LANES>(sum.Mz);
-    const float csum = group_sum<LANES>(sum.c);
+    const float csum = CM ? group_sum<LANES>(sum.c) : 0.0f;
 
     // right-hand side rows (Newton-Euler in the body frame)
     const float vyd = fmaf(Fy, a.invM, gBy) + fmaf(wx, vz, -(wz * vx));
@@ -334,7 +355,8 @@ __device__ __forceinline__ float srb_rhs(const RolloutArgs &a, const Arm (&arms)
     xd[10] = wyd;
     xd[11] = wzd;
     xd[12] = dd;
-    return L0 + csum;
+    // without a costmap the cost channel adds nothing (L0 + 0 is L0)
+    return CM ? L0 + csum : L0;
 }
 
 // Steering-angle limit and speed floor, applied to a completed step.
@@ -345,12 +367,12 @@ __device__ __forceinline__ void apply_limits(const RolloutArgs &a, float (&st)[1
 
 // One forward-Euler step (the paper's integrator): the running cost at the
 // node is added to J (left Riemann sum) and the state advanced in place.
-template <int LANES, class Hook = NoHook>
+template <int LANES, bool CM = true, class Hook = NoHook>
 __device__ __forceinline__ void euler_step(const RolloutArgs &a, const Arm (&arms)[4 / LANES],
                                            float (&st)[13], float &J, float dd, float ax,
                                            const Hook &hook = Hook()) {
     float xd[13];
-    const float L = srb_rhs<LANES>(a, arms, st, dd, ax, xd, hook);
+    const float L = srb_rhs<LANES, CM>(a, arms, st, dd, ax, xd, hook);
     J = fmaf(a.h, L, J);
 #pragma unroll
     for (int q = 0; q < 13; ++q) st[q] = fmaf(a.h, xd[q], st[q]);
@@ -360,32 +382,32 @@ __device__ __forceinline__ void euler_step(const RolloutArgs &a, const Arm (&arm
 // One classical fourth-order Runge-Kutta step on (state, J) with J' = L and
 // the control held (the alternative integrator the paper compared Euler
 // with); the limits apply to the completed step.
-template <int LANES>
+template <int LANES, bool CM = true>
 __device__ __forceinline__ void rk4_step(const RolloutArgs &a, const Arm (&arms)[4 / LANES],
                                          float (&st)[13], float &J, float dd, float ax) {
     float k[13], acc[13], stage[13];
-    float L = srb_rhs<LANES>(a, arms, st, dd, ax, k);
+    float L = srb_rhs<LANES, CM>(a, arms, st, dd, ax, k);
     float Lacc = L;
 #pragma unroll
     for (int q = 0; q < 13; ++q) {
         acc[q] = k[q];
         stage[q] = fmaf(a.h_half, k[q], st[q]);
     }
-    L = srb_rhs<LANES>(a, arms, stage, dd, ax, k);
+    L = srb_rhs<LANES, CM>(a, arms, stage, dd, ax, k);
     Lacc = fmaf(2.0f, L, Lacc);
 #pragma unroll
     for (int q = 0; q < 13; ++q) {
         acc[q] = fmaf(2.0f, k[q], acc[q]);
         stage[q] = fmaf(a.h_half, k[q], st[q]);
     }
-    L = srb_rhs<LANES>(a, arms, stage, dd, ax, k);
+    L = srb_rhs<LANES, CM>(a, arms, stage, dd, ax, k);
     Lacc = fmaf(2.0f, L, Lacc);
 #pragma unroll
     for (int q = 0; q < 13; ++q) {
         acc[q] = fmaf(2.0f, k[q], acc[q]);
         stage[q] = fmaf(a.h, k[q], st[q]);
     }
-    L = srb_rhs<LANES>(a, arms, stage, dd, ax, k);
+    L = srb_rhs<LANES, CM>(a, arms, stage, dd, ax, k);
     Lacc = Lacc + L;
     J = fmaf(a.h_sixth, Lacc, J);
 #pragma unroll

@@ -418,3 +418,28 @@ def test_error_codes_on_device():
     planner.rollout(w.state0, u, J)
     torch.cuda.synchronize()
     assert torch.isfinite(J).all()
+
+
+def test_no_costmap_kernels_equal_a_zero_costmap_bitwise():
+    """Without a costmap the kernels skip the cost channel; with an all-zero
+    costmap they load and sum it. The results are the same bits, for the plain,
+    one-launch and sampled paths and every lane count."""
+    w = inputs.c2(K=777, N=40)
+    T = w.terrain
+    ud = dev(w.controls)
+    plain = Case(w)
+    zero = Case(w, costmap=np.zeros_like(T.height))
+    spec = P.sample_spec(P.PLAN_SAMPLE_GAUSSIAN, 41, 0, (0.1, 0.2))
+    for lanes in (1, 2, 4):
+        out = []
+        for case in (plain, zero):
+            J, fs, _ = case.gpu(lanes=lanes)
+            J1 = torch.empty(w.K, device="cuda")
+            plan = torch.empty(w.N, 2, device="cuda")
+            k, jb = case.planner.rollout_argmin(w.state0, ud, J1, plan)
+            Js = torch.empty(w.K, device="cuda")
+            case.planner.rollout_sampled(w.state0, spec, w.N, Js)
+            torch.cuda.synchronize()
+            out.append((J, fs, J1.cpu().numpy(), plan.cpu().numpy(), k, Js.cpu().numpy()))
+        for a, b in zip(*out):
+            np.testing.assert_array_equal(a, b, err_msg=f"lanes={lanes}")
