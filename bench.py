@@ -31,16 +31,19 @@ if ROOT not in sys.path:
 METRIC = "candidate rollout-steps/sec and p50/p99 plan latency (serving vs plain)"
 
 # FP32 operations per rollout-step of the step definition, one lane per
-# candidate, transcendentals counted as one: goal test 5, attitude 21,
-# kinematics 26, four wheels of 101, wheel sums 18, right-hand side rows 17,
-# ESM and soft cost 12, running cost 5, Euler update and clamps 19, control
-# clamp 5 per interval: 532 with a costmap. A plan without a costmap has no
-# cost-channel term (its bilinear interpolation at the four wheels 24, its
-# wheel sum 3 and its addition to the running cost 1), and its kernels skip
-# it: 504. Every workload here runs without a costmap, so the algorithmic
-# side of the ALU roofline counts 504.
-OPS_PER_STEP_COSTMAP = 532
-OPS_PER_STEP = OPS_PER_STEP_COSTMAP - 28
+# candidate, transcendentals counted as one: goal test 5, attitude 21, CoM in
+# grid units 2, kinematics 26, four wheels of 81 (contact point and lookup
+# coordinates 9, cell index and weights 9, contact velocity 6, interpolation
+# of four channels from the cell's bilinear coefficients 12, normal 6,
+# extension 3, rate 6, spring and damper 7, slip 9, tire 5, forces and
+# moments 9), wheel sums 18, right-hand side rows 17, ESM and soft cost 12,
+# running cost 5, Euler update and clamps 19, control clamp 5 per interval:
+# 454 with a costmap. A plan without a costmap has no cost-channel term (its
+# interpolation at the four wheels 12, its wheel sum 3 and its addition to
+# the running cost 1), and its kernels skip it: 438. Every workload here runs
+# without a costmap, so the algorithmic side of the ALU roofline counts 438.
+OPS_PER_STEP_COSTMAP = 454
+OPS_PER_STEP = OPS_PER_STEP_COSTMAP - 16
 # MI355X vector ALU issue: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz, one
 # non-packed FP32 operation per lane per clock.
 ALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
@@ -162,22 +165,23 @@ def _summ(lat, t_first, t_last, steps, n):
 
 
 # Algorithmic FP32 operations per step of the other rollout variants (same
-# counting rules as OPS_PER_STEP). EST: one bilinear lookup of 3 channels with
-# its index arithmetic 40, angles from the normal 10, sincos psi, rotation and
+# counting rules as OPS_PER_STEP). EST: the cell under the CoM, its lookup
+# coordinates and the interpolation of two channels (f_x, f_y) 19, angles
+# from the normal 10, sincos psi, rotation and
 # world velocity 16, load transfer 6, two slip angles 10, tires 12, rows,
 # constraint and cost 20, Euler and limits 12, goal test 5. RK4: four
 # right-hand sides, the stage and combination updates, one set of limits.
-EST_OPS_PER_STEP = 130
+EST_OPS_PER_STEP = 109
 RK4_OPS_PER_STEP = 4 * (OPS_PER_STEP - 24) + 24 + 3 * 13 * 2 + 2 * 13
 # Adjoint, per candidate-step (same rules, no costmap): the checkpointing
 # forward pass runs the Euler step (OPS_PER_STEP); the backward kernel
 # recomputes the step from its segment's checkpoint (OPS_PER_STEP) and
 # evaluates the step's vector-Jacobian product: its forward quantities
-# (attitude and chassis 45, four wheels of 128: gathers, slip, normal,
-# suspension, tire) and the reverse sweep (chassis rows, rotation,
-# trigonometry 160; four wheels of 128, the cost channel's cell-weight
-# derivatives left out; wheel sums 63), 1 292 in all.
-ADJ_VJP_OPS_PER_STEP = 45 + 4 * 128 + 160 + 4 * 128 + 63
+# (attitude and chassis 45, CoM in grid units 2, four wheels of 111: gathers,
+# slip, normal, suspension, tire) and the reverse sweep (chassis rows,
+# rotation, trigonometry 160; four wheels of 107, the cost channel's
+# cell-weight derivatives left out; wheel sums 63), 1 142 in all.
+ADJ_VJP_OPS_PER_STEP = 45 + 2 + 4 * 111 + 160 + 4 * 107 + 63
 ADJ_BWD_OPS_PER_STEP = OPS_PER_STEP + ADJ_VJP_OPS_PER_STEP
 HBM_PEAK_GBS = 8000.0
 
@@ -350,10 +354,11 @@ def rows_leg():
     out["costmap_2048"] = {"ms": ms, "polygons": len(polys), "edges": edges,
                            "node_edge_tests_per_s": T.W * T.H * edges * 1e3 / ms,
                            "alu_frac": alu(25 * T.W * T.H * edges, ms / 1e3)}
-    # terrain pack (plan_set_terrain: slopes and texels, with its non-finite
-    # check and the host wait for it): heights and costmap read, texels written
+    # terrain pack (plan_set_terrain: slopes and the cells' bilinear
+    # coefficients, with its non-finite check and the host wait for it):
+    # heights and costmap read once, 64-byte cells written
     ms = _time_ms(lambda: pl.set_terrain(h, T.x0, T.y0, T.res, cm))
-    nbytes = (4 + 4 + 16) * T.W * T.H
+    nbytes = (4 + 4 + 64) * T.W * T.H
     out["terrain_pack_2048"] = {"ms": ms, "gb_per_s": nbytes / ms / 1e6,
                                 "hbm_frac": nbytes / ms / 1e6 / HBM_PEAK_GBS}
     pl.close()

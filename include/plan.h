@@ -101,11 +101,13 @@ enum { PLAN_ARGMIN = 0, PLAN_SOFTMIN = 1 };
 
 /* Create a context on the current HIP device. max_K, max_N, max_W, max_H bound
  * the sizes later calls may use; the library allocates its workspace for them
- * once here (terrain texels 16*max_W*max_H bytes, the candidate-order
- * workspace about 32*max_K bytes, plus selection scratch).
+ * once here (terrain cells 64*max_W*max_H bytes: each cell of the grid
+ * holds the bilinear coefficients of height, slopes and cost over it;
+ * the candidate-order workspace about 32*max_K bytes, plus selection
+ * scratch).
  * hip_stream is a hipStream_t, or NULL for the default stream.
- * Errors: PLAN_EINVAL for NULL pointers, non-positive sizes, a texel grid
- * max_W*max_H of 2^27 nodes or more, or invalid parameters (M, J, Lf+Lr, e,
+ * Errors: PLAN_EINVAL for NULL pointers, non-positive sizes, a terrain grid
+ * of max_W*max_H >= 2^26 nodes, or invalid parameters (M, J, Lf+Lr, e,
  * hR, dt <= 0, substeps < 1, non-finite values); PLAN_ENOMEM; PLAN_EDEVICE.
  * *out is set only on success. */
 plan_status_t plan_create(plan_ctx **out, const plan_vehicle_t *veh,
@@ -124,7 +126,7 @@ plan_status_t plan_set_cost(plan_ctx *ctx, const plan_cost_t *cost);
  * "Real-Time Implementation", pre-computed distance cost interpolated at run
  * time). height_dev is [H][W] FP32, node (i, j) at (x0 + i*res, y0 + j*res),
  * row j contiguous. costmap_dev is [H][W] FP32 cost units per second at each
- * node, or NULL for zero. The library copies both into its own texel grid, so
+ * node, or NULL for zero. The library packs both into its own cell grid, so
  * the caller may reuse the buffers once the stream has passed this call.
  * Synchronises the stream (once per terrain, off the per-plan path) to check
  * the data. Errors: PLAN_EINVAL for NULL height, W or H < 2 or above the
@@ -383,7 +385,7 @@ plan_status_t plan_get_launch(const plan_ctx *ctx, int *lanes, int *block);
 /* Candidate order of full-horizon rollouts (plan_rollout, plan_rollout_est,
  * plan_rollout_sampled, plan_rollout_argmin, plan_rollout_sampled_argmin).
  * Gather locality, not the paper: a wave of one-lane candidates gathers the
- * texels under 64 different vehicles each step, and when the candidates are
+ * terrain cells under 64 different vehicles each step, and when the candidates are
  * far apart the texture path rather than arithmetic limits the rollout. With
  * ordering, the library first sorts the candidates by a kinematic proxy of
  * their trajectories (single-track kinematics under the model's control

@@ -6,7 +6,7 @@
  * Co-Simulator" asks for a new plan every 40 ms). A server holding many such
  * planners receives problems of different sizes at unpredictable times. This
  * interface batches them: every admitted request occupies a device-resident
- * slot (its terrain texels, candidate states and running costs stay in HBM
+ * slot (its terrain cells, candidate states and running costs stay in HBM
  * between launches); each scheduling step launches ONE rollout kernel that
  * advances the candidates of every active slot by a few control intervals
  * and, in the same launch, selects the plans of the slots that finish.
@@ -74,8 +74,8 @@ typedef struct {
 
 /* Create a server on the current device. max_slots (<= 128) requests may be
  * resident at once, each with K <= max_K, N <= max_N, W <= max_W, H <= max_H
- * (max_W*max_H below 2^27).
- * A request's footprint is 16*W*H (texels) + 56*K (state, cost) + 8*K*N
+ * (max_W*max_H below 2^26).
+ * A request's footprint is 64*W*H (terrain cells) + 56*K (state, cost) + 8*K*N
  * (controls) + 8*N (plan) bytes; a request is admitted only while the summed
  * footprint of resident requests stays within budget_bytes.
  * chunk_intervals (>= 1) is how many control intervals one step advances

@@ -229,6 +229,11 @@ class Oracle:
             _lib.oracle_destroy(h)
             self._h = None
 
+    @property
+    def substeps(self) -> int:
+        """Euler (or RK4) steps per control interval."""
+        return int(self._integ.substeps)
+
     def set_terrain(self, height, x0, y0, res, costmap=None):
         h = _f32(height)
         H, W = h.shape

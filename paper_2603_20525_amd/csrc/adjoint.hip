@@ -27,14 +27,10 @@
 namespace plan {
 namespace {
 
-__device__ __forceinline__ float dlerp_dtx(float ty, float a00, float a10, float a01, float a11) {
-    return fmaf(ty, (a11 - a01) - (a10 - a00), a10 - a00);
-}
-
-__device__ __forceinline__ float dlerp_dty(float tx, float a00, float a10, float a01, float a11) {
-    const float b0 = fmaf(tx, a10 - a00, a00), b1 = fmaf(tx, a11 - a01, a01);
-    return b1 - b0;
-}
+// Partial derivatives of a channel's bilinear interpolant (cell
+// coefficients c = (c0, c_x, c_y, c_xy)) with respect to tx and ty.
+__device__ __forceinline__ float dbil_dtx(const float4 &c, float ty) { return fmaf(ty, c.w, c.y); }
+__device__ __forceinline__ float dbil_dty(const float4 &c, float tx) { return fmaf(tx, c.w, c.z); }
 
 // Adjoint contributions of one wheel to the chassis quantities it reads:
 // the rotation matrix, the rear constraint force, cos(delta), delta, the
@@ -113,18 +109,19 @@ __device__ void step_vjp(const RolloutArgs &a, const Arm (&arms)[4 / LANES],
     const float mm = fmaxf(0.0f, mm_raw);
 
     // this lane's wheels: forward quantities
-    float P_x[WPL], P_y[WPL], P_z[WPL], cl_u[WPL], cl_v[WPL], txv[WPL], tyv[WPL];
-    float4 T00[WPL], T10[WPL], T01[WPL], T11[WPL];
+    float P_z[WPL], cl_u[WPL], cl_v[WPL], txv[WPL], tyv[WPL];
+    float4 CH[WPL], CFX[WPL], CFY[WPL], CC[WPL];
     float vix[WPL], viy[WPL], viz[WPL], th_[WPL], tfx[WPL], tfy[WPL];
     float nBx[WPL], nBy[WPL], nBz[WPL], inz[WPL], chi[WPL], relx[WPL], rely[WPL], Dv[WPL],
         chid[WPL];
     float Fkr[WPL], Fk[WPL], Fb[WPL], Fz[WPL], rr[WPL], alpha[WPL], Ca[WPL], qq[WPL], Fyv[WPL];
     bool guard[WPL], fb_first[WPL];
-    // texel requests of this lane's wheels first; the hook's loads are
+    // terrain requests of this lane's wheels first; the hook's loads are
     // issued after them
+    const GridPos gp = grid_pos(a, x, y);
     Gather G[WPL];
 #pragma unroll
-    for (int i = 0; i < WPL; ++i) G[i] = gather(a, A, x, y, z, arms[i]);
+    for (int i = 0; i < WPL; ++i) G[i] = gather(a, A, gp, z, arms[i]);
     if constexpr (!std::is_same<Hook, NoHook>::value) {
         __builtin_amdgcn_sched_barrier(0);
         hook();
@@ -132,26 +129,25 @@ __device__ void step_vjp(const RolloutArgs &a, const Arm (&arms)[4 / LANES],
 #pragma unroll
     for (int i = 0; i < WPL; ++i) {
         const Arm r = arms[i];
-        P_x[i] = fmaf(A.R11, r.rx, fmaf(A.R12, r.ry, fmaf(A.R13, r.rz, x)));
-        P_y[i] = fmaf(A.R21, r.rx, fmaf(A.R22, r.ry, fmaf(A.R23, r.rz, y)));
-        P_z[i] = fmaf(A.R31, r.rx, fmaf(A.R32, r.ry, fmaf(A.R33, r.rz, z)));
-        const float ur = (P_x[i] - a.x0) * a.inv_res;
-        const float vr = (P_y[i] - a.y0) * a.inv_res;
+        // the lookup coordinates as the gather computed them
+        const float ur = fmaf(A.R11, r.gx, fmaf(A.R12, r.gy, fmaf(A.R13, r.gz, gp.xg)));
+        const float vr = fmaf(A.R21, r.gx, fmaf(A.R22, r.gy, fmaf(A.R23, r.gz, gp.yg)));
         cl_u[i] = (ur > 0.0f && ur < a.umax) ? 1.0f : 0.0f;  // NaN: clamped
         cl_v[i] = (vr > 0.0f && vr < a.vmax) ? 1.0f : 0.0f;
         const Gather &g = G[i];
+        P_z[i] = g.Pz;
         txv[i] = g.tx;
         tyv[i] = g.ty;
-        T00[i] = g.t00;
-        T10[i] = g.t10;
-        T01[i] = g.t01;
-        T11[i] = g.t11;
+        CH[i] = g.ch;
+        CFX[i] = g.cfx;
+        CFY[i] = g.cfy;
+        CC[i] = g.cc;
         vix[i] = fmaf(wy, r.rz, fmaf(-wz, r.ry, vx));
         viy[i] = fmaf(wz, r.rx, fmaf(-wx, r.rz, vy));
         viz[i] = fmaf(wx, r.ry, fmaf(-wy, r.rx, vz));
-        th_[i] = lerp2(g.tx, g.ty, g.t00.x, g.t10.x, g.t01.x, g.t11.x);
-        tfx[i] = lerp2(g.tx, g.ty, g.t00.y, g.t10.y, g.t01.y, g.t11.y);
-        tfy[i] = lerp2(g.tx, g.ty, g.t00.z, g.t10.z, g.t01.z, g.t11.z);
+        th_[i] = bil(g.ch, g.tx, g.ty);
+        tfx[i] = bil(g.cfx, g.tx, g.ty);
+        tfy[i] = bil(g.cfy, g.tx, g.ty);
         nBx[i] = fmaf(-A.R11, tfx[i], fmaf(-A.R21, tfy[i], A.R31));
         nBy[i] = fmaf(-A.R12, tfx[i], fmaf(-A.R22, tfy[i], A.R32));
         nBz[i] = fmaf(-A.R13, tfx[i], fmaf(-A.R23, tfy[i], A.R33));
@@ -301,16 +297,11 @@ __device__ void step_vjp(const RolloutArgs &a, const Arm (&arms)[4 / LANES],
         const float L_tfx = -A.R11 * L_nBx - A.R12 * L_nBy - A.R13 * L_nBz;
         const float L_tfy = -A.R21 * L_nBx - A.R22 * L_nBy - A.R23 * L_nBz;
         // bilinear terrain: d/dtx, d/dty of (h, f_x, f_y, c)
-        const float4 t00 = T00[i], t10 = T10[i], t01 = T01[i], t11 = T11[i];
         const float tx = txv[i], ty = tyv[i];
-        const float L_tx = L_hgt * dlerp_dtx(ty, t00.x, t10.x, t01.x, t11.x) +
-                           L_tfx * dlerp_dtx(ty, t00.y, t10.y, t01.y, t11.y) +
-                           L_tfy * dlerp_dtx(ty, t00.z, t10.z, t01.z, t11.z) +
-                           L_csum * dlerp_dtx(ty, t00.w, t10.w, t01.w, t11.w);
-        const float L_ty = L_hgt * dlerp_dty(tx, t00.x, t10.x, t01.x, t11.x) +
-                           L_tfx * dlerp_dty(tx, t00.y, t10.y, t01.y, t11.y) +
-                           L_tfy * dlerp_dty(tx, t00.z, t10.z, t01.z, t11.z) +
-                           L_csum * dlerp_dty(tx, t00.w, t10.w, t01.w, t11.w);
+        const float L_tx = L_hgt * dbil_dtx(CH[i], ty) + L_tfx * dbil_dtx(CFX[i], ty) +
+                           L_tfy * dbil_dtx(CFY[i], ty) + L_csum * dbil_dtx(CC[i], ty);
+        const float L_ty = L_hgt * dbil_dty(CH[i], tx) + L_tfx * dbil_dty(CFX[i], tx) +
+                           L_tfy * dbil_dty(CFY[i], tx) + L_csum * dbil_dty(CC[i], tx);
         const float L_Px = cl_u[i] * a.inv_res * L_tx;
         const float L_Py = cl_v[i] * a.inv_res * L_ty;
         // contact-point velocity
@@ -506,7 +497,7 @@ __global__ __launch_bounds__(64) void adjoint_backward(const RolloutArgs a, int 
 #pragma unroll
     for (int q = 0; q < WPL; ++q) arms[q] = arm(a, sub * WPL + q);
 
-    // Loads are issued one step ahead from inside the step (after its texel
+    // Loads are issued one step ahead from inside the step (after its terrain
     // requests): the next interval's controls in the recomputation, the
     // previous step's recomputed state and controls in the reverse sweep.
     // Indices are clamped to the segment, so every load stays in bounds.

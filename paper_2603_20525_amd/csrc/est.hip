@@ -8,8 +8,8 @@
 // SRB model and the ESM.
 //
 // One lane per candidate: the 7-component state stays in VGPRs; each Euler
-// step gathers one bilinear texel group under the CoM (height and slopes give
-// roll and pitch) and, when a costmap is set, four more at the wheels.
+// step interpolates the slopes of the terrain cell under the CoM (they give
+// roll and pitch) and, when a costmap is set, the cost at the four wheels.
 // Arithmetic is fixed by the source (no contraction, explicit fmaf), as in
 // the SRB kernel.
 #include "plan_internal.h"
@@ -18,22 +18,16 @@
 namespace plan {
 namespace {
 
-// Bilinear (h, f_x, f_y, cost) at (Px, Py), clamp-to-edge; a NaN coordinate
-// clamps to the grid origin, so every index is inside the grid.
-__device__ __forceinline__ float4 bilinear(const RolloutArgs &a, float Px, float Py) {
-    const float u = __builtin_amdgcn_fmed3f((Px - a.x0) * a.inv_res, 0.0f, a.umax);
-    const float v = __builtin_amdgcn_fmed3f((Py - a.y0) * a.inv_res, 0.0f, a.vmax);
-    const int i = min((int)u, a.W - 2);
-    const int j = min((int)v, a.H - 2);
-    const float tx = u - (float)i, ty = v - (float)j;
-    const __amdgpu_buffer_rsrc_t rs = texel_rsrc(a);
-    const int off = (j * a.W + i) << 4, row = a.W << 4;
-    const float4 t00 = load_texel(rs, off, 0), t10 = load_texel(rs, off + 16, 0);
-    const float4 t01 = load_texel(rs, off, row), t11 = load_texel(rs, off + 16, row);
-    return make_float4(lerp2(tx, ty, t00.x, t10.x, t01.x, t11.x),
-                       lerp2(tx, ty, t00.y, t10.y, t01.y, t11.y),
-                       lerp2(tx, ty, t00.z, t10.z, t01.z, t11.z),
-                       lerp2(tx, ty, t00.w, t10.w, t01.w, t11.w));
+// Bilinear interpolant of channel ch (0 h, 1 f_x, 2 f_y, 3 cost) at the
+// world point (Px, Py), clamp-to-edge; a NaN coordinate clamps to the grid
+// origin, so every cell is inside the grid.
+template <int CH>
+__device__ __forceinline__ float lookup(const RolloutArgs &a, const CellPos &c) {
+    return bil(load_coefs(cell_rsrc(a), c.off, CH), c.tx, c.ty);
+}
+
+__device__ __forceinline__ CellPos cell_at(const RolloutArgs &a, float Px, float Py) {
+    return cell_pos(a, (Px - a.x0) * a.inv_res, (Py - a.y0) * a.inv_res);
 }
 
 // One forward-Euler step of the EST formulation for one candidate: the
@@ -48,12 +42,13 @@ __device__ __forceinline__ void est_step(const RolloutArgs &a, float (&st)[7], f
     // under the CoM. With the 1-2-3 convention b_z = (sin th, -cos th sin ph,
     // cos ph cos th), so sin th = -f_x/s, cos th = sqrt(1 + f_y^2)/s,
     // sin ph = f_y/sqrt(1 + f_y^2), cos ph = 1/sqrt(1 + f_y^2).
-    const float4 T = bilinear(a, x, y);
-    const float q = fmaf(T.z, T.z, 1.0f);
-    const float rq = frsq(q), rs = frsq(fmaf(T.y, T.y, q));
-    const float sth = -T.y * rs;
+    const CellPos cg = cell_at(a, x, y);
+    const float Tfx = lookup<1>(a, cg), Tfy = lookup<2>(a, cg);
+    const float q = fmaf(Tfy, Tfy, 1.0f);
+    const float rq = frsq(q), rs = frsq(fmaf(Tfx, Tfx, q));
+    const float sth = -Tfx * rs;
     const float cth = (q * rq) * rs;
-    const float sph = T.z * rq;
+    const float sph = Tfy * rq;
     const float cph = rq;
     float sps, cps;
     __sincosf(psi, &sps, &cps);
@@ -103,7 +98,7 @@ __device__ __forceinline__ void est_step(const RolloutArgs &a, float (&st)[7], f
             const float ry = (w & 1) ? -a.half_e : a.half_e;
             const float Px = fmaf(R11, rx, fmaf(R12, ry, bx));
             const float Py = fmaf(R21, rx, fmaf(R22, ry, by));
-            c[w] = bilinear(a, Px, Py).w;
+            c[w] = lookup<3>(a, cell_at(a, Px, Py));
         }
         L = L + ((c[0] + c[1]) + (c[2] + c[3]));
     }

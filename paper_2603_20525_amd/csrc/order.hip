@@ -1,7 +1,7 @@
 // Candidate order for gather locality.
 //
 // A one-lane rollout wave runs 64 candidates side by side, and every step
-// each lane gathers the texels under its own four wheels. Candidates drawn
+// each lane gathers the terrain cells under its own four wheels. Candidates drawn
 // independently end up tens of metres apart, so a single gather instruction
 // touches up to 64 different cache lines and the texture path (address unit
 // and L1), not the vector ALUs, sets the pace at large K. Running candidates

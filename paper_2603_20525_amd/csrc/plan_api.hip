@@ -29,8 +29,8 @@ struct plan_ctx {
     plan_cost_t cost{};
     plan_integ_t integ{};
     int max_K = 0, max_N = 0, max_W = 0, max_H = 0;
-    // terrain texels
-    float4 *tex = nullptr;
+    // terrain cells [max_W * max_H][4]
+    float4 *cells = nullptr;
     int W = 0, H = 0;
     float x0 = 0, y0 = 0, res = 0;
     bool has_terrain = false;
@@ -124,7 +124,7 @@ static plan_status_t hip_fail(plan_ctx *c, const char *what, hipError_t e) {
 static void release(plan_ctx *c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    (void)hipFree(c->tex);
+    (void)hipFree(c->cells);
     (void)hipFree(c->bad_dev);
     (void)hipFree(c->part_keys);
     (void)hipFree(c->counters);
@@ -151,7 +151,7 @@ namespace plan {
 
 // Derived constants of one launch (double on the host, rounded once).
 void fill_rollout_args(RolloutArgs &a, const plan_vehicle_t &v, const plan_cost_t &co,
-                       const plan_integ_t &in, const float4 *tex, int W, int H, float x0,
+                       const plan_integ_t &in, const float4 *cells, int W, int H, float x0,
                        float y0, float res) {
     memset(&a, 0, sizeof a);
     const double L = (double)v.Lf + v.Lr;
@@ -166,6 +166,10 @@ void fill_rollout_args(RolloutArgs &a, const plan_vehicle_t &v, const plan_cost_
     a.Lr = v.Lr;
     a.half_e = 0.5f * v.e;
     a.hR = v.hR;
+    a.Lf_g = (float)((double)v.Lf / res);
+    a.Lr_g = (float)((double)v.Lr / res);
+    a.half_e_g = (float)(0.5 * (double)v.e / res);
+    a.hR_g = (float)((double)v.hR / res);
     a.kf = v.kf;
     a.kr = v.kr;
     a.bf = v.bf;
@@ -204,12 +208,14 @@ void fill_rollout_args(RolloutArgs &a, const plan_vehicle_t &v, const plan_cost_
     a.method = in.method;
     a.accel_max = in.accel_max;
     a.vx_min = in.vx_min;
-    a.tex = tex;
+    a.cells = cells;
     a.W = W;
     a.H = H;
     a.x0 = x0;
     a.y0 = y0;
     a.inv_res = (float)(1.0 / res);
+    a.x0_g = (float)((double)x0 / res);
+    a.y0_g = (float)((double)y0 / res);
     a.umax = (float)(W - 1);
     a.vmax = (float)(H - 1);
 }
@@ -263,7 +269,7 @@ void auto_launch(long long K, int simds, int *lanes, int *block) {
 }  // namespace plan
 
 static void fill_args(const plan_ctx *c, RolloutArgs &a) {
-    plan::fill_rollout_args(a, c->veh, c->cost, c->integ, c->tex, c->W, c->H, c->x0, c->y0,
+    plan::fill_rollout_args(a, c->veh, c->cost, c->integ, c->cells, c->W, c->H, c->x0, c->y0,
                             c->res);
     a.has_costmap = c->has_costmap;
 }
@@ -280,8 +286,8 @@ plan_status_t plan_create(plan_ctx **out, const plan_vehicle_t *veh, const plan_
     if (!valid_integ(*integ)) return fail(nullptr, PLAN_EINVAL, "invalid integration parameters");
     if (max_K < 1 || max_N < 1 || max_W < 2 || max_H < 2)
         return fail(nullptr, PLAN_EINVAL, "max sizes must be K,N >= 1 and W,H >= 2");
-    if ((long long)max_W * max_H >= (1ll << 27))
-        return fail(nullptr, PLAN_EINVAL, "terrain grid too large (W*H must be below 2^27)");
+    if (plan::terrain_cells(max_W, max_H) >= plan::MAX_TERRAIN_CELLS)
+        return fail(nullptr, PLAN_EINVAL, "terrain grid too large (W*H must be below 2^26)");
     if ((long long)max_K * 4 > 0x7fffffffll) return fail(nullptr, PLAN_EINVAL, "max_K too large");
 
     plan_ctx *c = new (std::nothrow) plan_ctx;
@@ -312,7 +318,7 @@ plan_status_t plan_create(plan_ctx **out, const plan_vehicle_t *veh, const plan_
         if (cus > 0) c->simds = 4 * cus;
     }
     CREATE_TRY(resolve_scratch(c->device));
-    CREATE_TRY(hipMalloc(&c->tex, sizeof(float4) * (size_t)max_W * max_H));
+    CREATE_TRY(hipMalloc(&c->cells, sizeof(float4) * 4 * plan::terrain_cells(max_W, max_H)));
     CREATE_TRY(hipMalloc(&c->smooth_tmp, sizeof(float) * (size_t)max_W * max_H));
     CREATE_TRY(hipMalloc(&c->bad_dev, sizeof(int)));
     CREATE_TRY(hipHostMalloc(&c->bad_host, sizeof(int), hipHostMallocDefault));
@@ -368,7 +374,7 @@ plan_status_t plan_set_terrain(plan_ctx *c, const float *height_dev, int W, int 
     HIP_TRY(c, hipSetDevice(c->device));
     c->has_terrain = false;
     HIP_TRY(c, hipMemsetAsync(c->bad_dev, 0, sizeof(int), c->stream));
-    HIP_TRY(c, plan::launch_pack_terrain(height_dev, costmap_dev, W, H, 1.0f / res, c->tex,
+    HIP_TRY(c, plan::launch_pack_terrain(height_dev, costmap_dev, W, H, 1.0f / res, c->cells,
                                          c->bad_dev, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->bad_host, c->bad_dev, sizeof(int), hipMemcpyDeviceToHost,
                               c->stream));

@@ -34,6 +34,7 @@ struct RolloutArgs {
     float invJxx, invJyy, invJzz;
     float dJyz, dJxz, dJxy;        // Jyy-Jzz, Jxx-Jzz, Jxx-Jyy
     float Lf, Lr, half_e, hR;
+    float Lf_g, Lr_g, half_e_g, hR_g;  // the same lever arms in grid units (times 1 / res)
     float kf, kr, bf, br;
     float Fsf, Fsr;                // nominal tire loads (g/2) K_zz,f / K_zz,r
     float Mhalf;                   // M/2 (rear longitudinal constraint force)
@@ -54,12 +55,16 @@ struct RolloutArgs {
     int S;                         // substeps per control
     int method;                    // 0 forward Euler, 1 fourth-order Runge-Kutta
     float accel_max, vx_min;
-    // terrain: float4 texels (h, f_x, f_y, cost) on a W x H grid
-    const float4 *tex;
+    // terrain: a W x H node grid stored as W x H cells, each the bilinear
+    // coefficients of the four channels (h, f_x, f_y, cost) over the cell
+    // (pack_cell; the last column and row are the grid's edge, constant
+    // outward)
+    const float4 *cells;
     int W, H;
     float x0, y0, inv_res;
+    float x0_g, y0_g;              // x0 / res, y0 / res
     float umax, vmax;              // W-1, H-1 as floats (clamp-to-edge)
-    int has_costmap;               // the texels' cost channel is not all zero
+    int has_costmap;               // the cost channel is not all zero
     // problem
     float s0[13];
     const float *controls;         // [N][2][K]
@@ -91,7 +96,7 @@ struct RolloutArgs {
 
 // Locality order of a full-horizon rollout (order.hip): the candidates
 // sorted by a kinematic proxy of their trajectories, so that each wave
-// gathers texels from nearby cells.
+// gathers from nearby terrain cells.
 struct OrderArgs {
     int K, N;
     const float *controls;  // [N][2][K], or nullptr: drawn from smp
@@ -120,13 +125,12 @@ hipError_t launch_locality_order(const OrderArgs &o, hipStream_t s);
 hipError_t launch_permute_controls(const float *controls, const int *order, int K, int N,
                                    float *out, hipStream_t s);
 
-// Texel (i, j) of the packed terrain: height, slopes by central differences
+// Node (i, j) of the terrain: height, slopes by central differences
 // (one-sided on the border) and the costmap's rate. Returns false if the
 // node's height or cost is not finite.
-__device__ __forceinline__ bool pack_texel(const float *__restrict__ hgt,
-                                           const float *__restrict__ cm, int W, int H,
-                                           float inv_res, int i, int j,
-                                           float4 *__restrict__ tex) {
+__device__ __forceinline__ bool terrain_node(const float *__restrict__ hgt,
+                                             const float *__restrict__ cm, int W, int H,
+                                             float inv_res, int i, int j, float4 &t) {
     const size_t q = (size_t)j * W + i;
     const float hc = hgt[q];
     float fx, fy;
@@ -143,9 +147,48 @@ __device__ __forceinline__ bool pack_texel(const float *__restrict__ hgt,
     else
         fy = (hgt[q + W] - hgt[q - W]) * (0.5f * inv_res);
     const float cc = cm ? cm[q] : 0.0f;
-    tex[q] = make_float4(hc, fx, fy, cc);
+    t = make_float4(hc, fx, fy, cc);
     return isfinite(hc) && isfinite(cc);
 }
+
+// Bilinear coefficients of one channel over a cell with corner values a00,
+// a10 (next column), a01 (next row), a11: the interpolant is
+// c0 + c_x t_x + c_y t_y + c_xy t_x t_y with t_x, t_y in [0, 1].
+__device__ __forceinline__ float4 bilinear_coefs(float a00, float a10, float a01, float a11) {
+    const float dx0 = a10 - a00, dx1 = a11 - a01;
+    return make_float4(a00, dx0, a01 - a00, dx1 - dx0);
+}
+
+// Cell (i, j), 0 <= i < W, 0 <= j < H, of the packed terrain: 64 bytes, the
+// coefficients of h, f_x, f_y and cost over the square from node (i, j) to
+// node (i+1, j+1), one float4 each. Interpolating within a cell then takes
+// one contiguous load and three multiply-adds per channel. The cells of the
+// last column (row) take node i+1 = i (j+1 = j): the interpolant there is
+// constant along x (y), so a query clamped to the grid's edge lands in such
+// a cell at weight 0 and reads the edge nodes exactly. Returns false if any
+// of the cell's nodes is not finite.
+__device__ __forceinline__ bool pack_cell(const float *__restrict__ hgt,
+                                          const float *__restrict__ cm, int W, int H,
+                                          float inv_res, int i, int j,
+                                          float4 *__restrict__ cells) {
+    const int i1 = min(i + 1, W - 1), j1 = min(j + 1, H - 1);
+    float4 n00, n10, n01, n11;
+    bool ok = terrain_node(hgt, cm, W, H, inv_res, i, j, n00);
+    ok &= terrain_node(hgt, cm, W, H, inv_res, i1, j, n10);
+    ok &= terrain_node(hgt, cm, W, H, inv_res, i, j1, n01);
+    ok &= terrain_node(hgt, cm, W, H, inv_res, i1, j1, n11);
+    float4 *c = cells + 4 * ((size_t)j * W + i);
+    c[0] = bilinear_coefs(n00.x, n10.x, n01.x, n11.x);
+    c[1] = bilinear_coefs(n00.y, n10.y, n01.y, n11.y);
+    c[2] = bilinear_coefs(n00.z, n10.z, n01.z, n11.z);
+    c[3] = bilinear_coefs(n00.w, n10.w, n01.w, n11.w);
+    return ok;
+}
+
+// Cells of a W x H node grid, and the largest grid the 32-bit byte offsets
+// of the cell loads can address.
+__host__ __device__ inline long long terrain_cells(long long W, long long H) { return W * H; }
+constexpr long long MAX_TERRAIN_CELLS = 1ll << 26;
 
 // One tick of the serving loop: which slots advance through which control
 // intervals, and which blocks of the launch belong to each slot.
@@ -209,8 +252,10 @@ hipError_t launch_adjoint_backward(const RolloutArgs &a, int C, const float *ckp
 
 hipError_t launch_init_state(const float *s0, float *state, float *cost, int K, hipStream_t s);
 
+// Packs the cells of a W x H grid (heights h, optional costmap c) into
+// cells; *bad is set if any node is not finite.
 hipError_t launch_pack_terrain(const float *h, const float *c, int W, int H, float inv_res,
-                               float4 *tex, int *bad, hipStream_t s);
+                               float4 *cells, int *bad, hipStream_t s);
 
 // Terrain preparation. Gaussian taps w[0 .. 2r] (normalised, FP32) of the
 // separable level-of-detail kernel; r <= MAX_SMOOTH_RADIUS.
@@ -256,7 +301,7 @@ hipError_t launch_select_sampled(const SampleArgs &sa, const float *cost, int K,
 
 // Host helpers shared by the plan and server entry points.
 void fill_rollout_args(RolloutArgs &a, const plan_vehicle_t &v, const plan_cost_t &co,
-                       const plan_integ_t &in, const float4 *tex, int W, int H, float x0,
+                       const plan_integ_t &in, const float4 *cells, int W, int H, float x0,
                        float y0, float res);
 double esm_level(const plan_vehicle_t &v);
 bool finite_all(const float *p, int n);

@@ -18,8 +18,9 @@
 //   * The 13-component state lives in VGPRs for the whole horizon; HBM traffic
 //     inside the loop is the per-interval control pair (coalesced over k in the
 //     [N][2][K] layout) and the terrain gathers, which hit L1/L2.
-//   * Terrain: float4 texels (h, f_x, f_y, cost) on the heightmap grid;
-//     software bilinear interpolation in FP32 with clamp-to-edge.
+//   * Terrain: one 64-byte record per heightmap cell holding the bilinear
+//     coefficients of (h, f_x, f_y, cost); software interpolation in FP32
+//     (three multiply-adds per channel) with clamp-to-edge.
 #include <string.h>
 
 #include "rollout_kernels.h"

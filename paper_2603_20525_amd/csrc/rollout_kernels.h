@@ -46,7 +46,7 @@ __device__ __forceinline__ float simulate(const RolloutArgs &a, int k, int sub, 
 
     // materialised controls are read one interval ahead (the index is clamped
     // to [n0, n1)). The Euler step requests the next pair right after its
-    // texel gathers, so waiting for the texels does not wait for it and the
+    // terrain gathers, so waiting for the texels does not wait for it and the
     // load stays in flight for the rest of the step; RK4 requests it at the
     // start of the interval.
     // up: this candidate's control column (interval n at up[2 n K], up[(2 n + 1) K])

@@ -65,9 +65,11 @@ __device__ __forceinline__ Attitude attitude(float psi, float th, float ph) {
     return A;
 }
 
-// Body-frame lever arm of wheel wi (fl, fr, rl, rr): constant in the body frame.
+// Body-frame lever arm of wheel wi (fl, fr, rl, rr): constant in the body
+// frame; (gx, gy, gz) is the same arm in grid units (times 1 / res).
 struct Arm {
     float rx, ry, rz;
+    float gx, gy, gz;
     bool front;
 };
 
@@ -77,85 +79,98 @@ __device__ __forceinline__ Arm arm(const RolloutArgs &a, int wi) {
     r.rx = r.front ? a.Lf : -a.Lr;
     r.ry = (wi & 1) ? -a.half_e : a.half_e;
     r.rz = -a.hR;
+    r.gx = r.front ? a.Lf_g : -a.Lr_g;
+    r.gy = (wi & 1) ? -a.half_e_g : a.half_e_g;
+    r.gz = -a.hR_g;
     return r;
 }
 
-// The four texels around a wheel's contact point plus the bilinear weights;
-// the loads are issued here and consumed in wheel(), so the gathers are in
-// flight while the chassis terms are computed.
+// CoM position in grid units, (x - x0) / res and (y - y0) / res, from
+// which every wheel's lookup coordinate follows as u = xg + (R rho)_x / res.
+struct GridPos {
+    float xg, yg;
+};
+
+__device__ __forceinline__ GridPos grid_pos(const RolloutArgs &a, float x, float y) {
+    return GridPos{fmaf(x, a.inv_res, -a.x0_g), fmaf(y, a.inv_res, -a.y0_g)};
+}
+
+// The terrain cell under a wheel's contact point: the bilinear coefficients
+// of its channels and the weights; the loads are issued here and consumed
+// in wheel(), so the gathers are in flight while the chassis terms are
+// computed.
 struct Gather {
-    float4 t00, t10, t01, t11;
+    float4 ch, cfx, cfy, cc;  // (c0, c_x, c_y, c_xy) of h, f_x, f_y, cost
     float tx, ty, Pz;
 };
 
-// Buffer resource over the W x H float4 texel grid (fewer than 2^27 texels,
-// a limit plan_create and plan_server_create enforce, so every byte offset
-// fits in 31 bits). A buffer load takes a 32-bit offset from a scalar base
-// instead of a 64-bit address per lane, which saves the 64-bit address
-// arithmetic of the four gathers of each wheel.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t texel_rsrc(const RolloutArgs &a) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float4 *>(a.tex), 0,
-                                             a.W * a.H * 16, 0x00020000);
+// Buffer resource over the W x H cells of 64 bytes (fewer than 2^26 cells, a
+// limit plan_create and plan_server_create enforce, so every byte offset
+// fits in 32 bits). A buffer load takes a 32-bit offset from a scalar base
+// instead of a 64-bit address per lane.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t cell_rsrc(const RolloutArgs &a) {
+    const unsigned bytes = (unsigned)(a.W * a.H) << 6;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float4 *>(a.cells), 0, (int)bytes,
+                                             0x00020000);
 }
 
-__device__ __forceinline__ float4 load_texel(__amdgpu_buffer_rsrc_t rs, int off, int soff) {
+// One channel's coefficients: the cell's byte offset plus 16 x channel,
+// the channel offset as the load's scalar offset.
+__device__ __forceinline__ float4 load_coefs(__amdgpu_buffer_rsrc_t rs, unsigned off, int ch) {
     typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
-    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, soff, 0);
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 16 * ch, 0);
     return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z),
                        __uint_as_float(v.w));
 }
 
-// The first three channels (h, f_x, f_y) of a texel; the cost channel reads
-// as 0 (the grid's cost channel is 0 wherever no costmap is set).
-__device__ __forceinline__ float4 load_texel3(__amdgpu_buffer_rsrc_t rs, int off, int soff) {
-    typedef unsigned u32x3 __attribute__((ext_vector_type(3)));
-    const u32x3 v = __builtin_amdgcn_raw_buffer_load_b96(rs, off, soff, 0);
-    return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), 0.0f);
+// Cell index and weights of lookup coordinates (u, v) in grid units:
+// clamp-to-edge with v_med3, which on gfx950 gives min(max(x, 0), umax) for
+// every input and maps a NaN coordinate to 0, so the cell is always inside
+// the grid. With u >= 0 the integer part (truncation) and the fraction
+// (v_fract) split u exactly; u = W-1 on the edge selects the last column's
+// cell at weight 0.
+struct CellPos {
+    unsigned off;  // byte offset of the cell
+    float tx, ty;
+};
+
+__device__ __forceinline__ CellPos cell_pos(const RolloutArgs &a, float ur, float vr) {
+    const float u = __builtin_amdgcn_fmed3f(ur, 0.0f, a.umax);
+    const float v = __builtin_amdgcn_fmed3f(vr, 0.0f, a.vmax);
+    CellPos p;
+    p.tx = __builtin_amdgcn_fractf(u);
+    p.ty = __builtin_amdgcn_fractf(v);
+    p.off = (unsigned)((int)v * a.W + (int)u) << 6;
+    return p;
 }
 
 // CM: the context has a costmap; without one only (h, f_x, f_y) are loaded
 // and the cost channel is neither interpolated nor summed (it is 0 there, so
 // the results are the same bits).
 template <bool CM = true>
-__device__ __forceinline__ Gather gather(const RolloutArgs &a, const Attitude &A, float x,
-                                         float y, float z, const Arm &r) {
-    // contact point P = p + R rho (world)
-    const float Px = fmaf(A.R11, r.rx, fmaf(A.R12, r.ry, fmaf(A.R13, r.rz, x)));
-    const float Py = fmaf(A.R21, r.rx, fmaf(A.R22, r.ry, fmaf(A.R23, r.rz, y)));
+__device__ __forceinline__ Gather gather(const RolloutArgs &a, const Attitude &A,
+                                         const GridPos &p, float z, const Arm &r) {
+    // contact point P = p + R rho: its height in the world, its horizontal
+    // position as lookup coordinates in grid units
+    const float ur = fmaf(A.R11, r.gx, fmaf(A.R12, r.gy, fmaf(A.R13, r.gz, p.xg)));
+    const float vr = fmaf(A.R21, r.gx, fmaf(A.R22, r.gy, fmaf(A.R23, r.gz, p.yg)));
     Gather g;
     g.Pz = fmaf(A.R31, r.rx, fmaf(A.R32, r.ry, fmaf(A.R33, r.rz, z)));
-    // clamp-to-edge with v_med3, which on gfx950 gives min(max(x, 0), umax)
-    // for every input and maps a NaN coordinate to 0, so the indices are
-    // always inside the grid
-    const float u = __builtin_amdgcn_fmed3f((Px - a.x0) * a.inv_res, 0.0f, a.umax);
-    const float v = __builtin_amdgcn_fmed3f((Py - a.y0) * a.inv_res, 0.0f, a.vmax);
-    const int i = min((int)u, a.W - 2);
-    const int j = min((int)v, a.H - 2);
-    g.tx = u - (float)i;
-    g.ty = v - (float)j;
-    // one 32-bit byte offset per wheel: the right neighbour through the
-    // load's immediate offset, the next row through the scalar row pitch
-    const __amdgpu_buffer_rsrc_t rs = texel_rsrc(a);
-    const int off = (j * a.W + i) << 4;
-    const int row = a.W << 4;
-    if constexpr (CM) {
-        g.t00 = load_texel(rs, off, 0);
-        g.t10 = load_texel(rs, off + 16, 0);
-        g.t01 = load_texel(rs, off, row);
-        g.t11 = load_texel(rs, off + 16, row);
-    } else {
-        g.t00 = load_texel3(rs, off, 0);
-        g.t10 = load_texel3(rs, off + 16, 0);
-        g.t01 = load_texel3(rs, off, row);
-        g.t11 = load_texel3(rs, off + 16, row);
-    }
+    const CellPos c = cell_pos(a, ur, vr);
+    g.tx = c.tx;
+    g.ty = c.ty;
+    const __amdgpu_buffer_rsrc_t rs = cell_rsrc(a);
+    g.ch = load_coefs(rs, c.off, 0);
+    g.cfx = load_coefs(rs, c.off, 1);
+    g.cfy = load_coefs(rs, c.off, 2);
+    g.cc = CM ? load_coefs(rs, c.off, 3) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     return g;
 }
 
-__device__ __forceinline__ float lerp2(float tx, float ty, float a00, float a10, float a01,
-                                       float a11) {
-    const float b0 = fmaf(tx, a10 - a00, a00), b1 = fmaf(tx, a11 - a01, a01);
-    return fmaf(ty, b1 - b0, b0);
+// Bilinear interpolant of one channel at (tx, ty) from its cell
+// coefficients: c0 + tx c_x + ty (c_y + tx c_xy).
+__device__ __forceinline__ float bil(const float4 &c, float tx, float ty) {
+    return fmaf(tx, c.y, fmaf(ty, fmaf(tx, c.w, c.z), c.x));
 }
 
 // Force and moment contributions of one wheel (sums of the force and moment
@@ -203,10 +218,10 @@ __device__ __forceinline__ WheelOut wheel(const RolloutArgs &a, const Attitude &
                                           const WheelPre &p) {
     const float vix = p.vix, viy = p.viy, viz = p.viz;
     // bilinear height, slopes and cost rate at the contact point
-    const float th = lerp2(g.tx, g.ty, g.t00.x, g.t10.x, g.t01.x, g.t11.x);
-    const float tfx = lerp2(g.tx, g.ty, g.t00.y, g.t10.y, g.t01.y, g.t11.y);
-    const float tfy = lerp2(g.tx, g.ty, g.t00.z, g.t10.z, g.t01.z, g.t11.z);
-    const float tc = CM ? lerp2(g.tx, g.ty, g.t00.w, g.t10.w, g.t01.w, g.t11.w) : 0.0f;
+    const float th = bil(g.ch, g.tx, g.ty);
+    const float tfx = bil(g.cfx, g.tx, g.ty);
+    const float tfy = bil(g.cfy, g.tx, g.ty);
+    const float tc = CM ? bil(g.cc, g.tx, g.ty) : 0.0f;
     // upward terrain normal (-f_x, -f_y, 1) resolved in the body frame
     const float nBx = fmaf(-A.R11, tfx, fmaf(-A.R21, tfy, A.R31));
     const float nBy = fmaf(-A.R12, tfx, fmaf(-A.R22, tfy, A.R32));
@@ -242,7 +257,7 @@ __device__ __forceinline__ WheelOut wadd(const WheelOut &p, const WheelOut &q) {
     return WheelOut{p.Fy + q.Fy, p.Fz + q.Fz, p.Mx + q.Mx, p.My + q.My, p.Mz + q.Mz, p.c + q.c};
 }
 
-// Work a caller issues inside the step right after the texel gathers (a
+// Work a caller issues inside the step right after the terrain gathers (a
 // load whose latency should overlap the rest of the step).
 struct NoHook {
     __device__ __forceinline__ void operator()() const {}
@@ -267,9 +282,10 @@ __device__ __forceinline__ float srb_rhs(const RolloutArgs &a, const Arm (&arms)
     // attitude and this lane's terrain requests first, so the
     // gathers overlap the chassis arithmetic below
     const Attitude A = attitude(psi, th, ph);
+    const GridPos gp = grid_pos(a, x, y);
     Gather G[WPL];
 #pragma unroll
-    for (int q = 0; q < WPL; ++q) G[q] = gather<CM>(a, A, x, y, z, arms[q]);
+    for (int q = 0; q < WPL; ++q) G[q] = gather<CM>(a, A, gp, z, arms[q]);
     if constexpr (!std::is_same<Hook, NoHook>::value) {
         __builtin_amdgcn_sched_barrier(0);
         hook();
@@ -310,7 +326,7 @@ __device__ __forceinline__ float srb_rhs(const RolloutArgs &a, const Arm (&arms)
 #pragma unroll
     for (int q = 0; q < WPL; ++q) pre[q] = wheel_pre(a, m, arms[q]);
     // everything above is independent of the terrain: keep it between the
-    // gather issue and the first use of a texel
+    // gather issue and the first use of a cell's coefficients
     __builtin_amdgcn_sched_barrier(0);
 
     // wheel forces: this lane's share, then the group sum in fixed

@@ -23,15 +23,16 @@ constexpr int SM_BLOCK = 1024;                     // softmin: threads per block
 
 // --------------------------------------------------------------- terrain ----
 // Node slopes by central differences (one-sided on the border), merged with
-// the costmap into float4 texels (h, f_x, f_y, cost).
+// the costmap, as the bilinear coefficients of each cell (pack_cell): one
+// thread per cell.
 __global__ __launch_bounds__(256) void pack_terrain(const float *__restrict__ hgt,
                                                     const float *__restrict__ cm, int W, int H,
-                                                    float inv_res, float4 *__restrict__ tex,
+                                                    float inv_res, float4 *__restrict__ cells,
                                                     int *__restrict__ bad) {
     const int i = blockIdx.x * 16 + (threadIdx.x & 15);
     const int j = blockIdx.y * 16 + (threadIdx.x >> 4);
     if (i >= W || j >= H) return;
-    if (!pack_texel(hgt, cm, W, H, inv_res, i, j, tex)) atomicOr(bad, 1);
+    if (!pack_cell(hgt, cm, W, H, inv_res, i, j, cells)) atomicOr(bad, 1);
 }
 
 // ---------------------------------------------------------------- argmin ----
@@ -171,9 +172,9 @@ __global__ __launch_bounds__(SM_BLOCK) void select_softmin(
 int select_blocks(int K) { return (K + SEL_CHUNK - 1) / SEL_CHUNK; }
 
 hipError_t launch_pack_terrain(const float *h, const float *c, int W, int H, float inv_res,
-                               float4 *tex, int *bad, hipStream_t s) {
+                               float4 *cells, int *bad, hipStream_t s) {
     dim3 grid((W + 15) / 16, (H + 15) / 16);
-    hipLaunchKernelGGL(pack_terrain, grid, dim3(256), 0, s, h, c, W, H, inv_res, tex, bad);
+    hipLaunchKernelGGL(pack_terrain, grid, dim3(256), 0, s, h, c, W, H, inv_res, cells, bad);
     return hipGetLastError();
 }
 

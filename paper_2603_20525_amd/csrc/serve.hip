@@ -1,6 +1,6 @@
 // Continuous-batching planning server (include/plan_serve.h).
 //
-// Device residency: every slot owns a texel grid, a [13][max_K] state block
+// Device residency: every slot owns a terrain cell grid, a [13][max_K] state block
 // and a [max_K] running-cost block for the whole life of the server; a
 // request's controls and plan output stay in the caller's buffers. A step
 // launches one rollout over all resident requests (rollout_slots: each
@@ -39,14 +39,14 @@ struct AdmitEntry {
     RolloutArgs args;
     const float *height;
     const float *costmap;
-    float4 *tex;
+    float4 *cells;
     int slot, W, H;
     float inv_res;
 };
 
 // Admission of every request a step admits, in one launch: blockIdx.y picks
 // the request; thread t writes candidate t's initial state and zero running
-// cost and packs texel t of its terrain; thread 0 publishes the launch
+// cost and packs cell t of its terrain; thread 0 publishes the launch
 // arguments. The slot's bad-terrain flag was cleared by the rollout that
 // finished its previous request (or at server creation).
 __global__ __launch_bounds__(256) void admit_batch(const AdmitEntry *__restrict__ ents,
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void admit_batch(const AdmitEntry *__restrict_
     }
     if (t < e.W * e.H) {
         const int i = t % e.W, j = t / e.W;
-        if (!plan::pack_texel(e.height, e.costmap, e.W, e.H, e.inv_res, i, j, e.tex))
+        if (!plan::pack_cell(e.height, e.costmap, e.W, e.H, e.inv_res, i, j, e.cells))
             atomicOr(bad + e.slot, 1);
     }
 }
@@ -97,7 +97,7 @@ struct plan_server {
     unsigned long long budget = 0, used = 0;
     std::chrono::steady_clock::time_point t0;
     // device memory
-    float4 *tex = nullptr;
+    float4 *cells = nullptr;  // [max_slots][max_W * max_H][4]
     float *state = nullptr;
     float *cost = nullptr;
     RolloutArgs *slot_args = nullptr;
@@ -149,12 +149,12 @@ static double now_of(const plan_server *s) {
 }
 
 static unsigned long long footprint(const plan_request_t &r) {
-    return 16ull * r.W * r.H + 56ull * r.K + 8ull * r.K * r.N + 8ull * r.N;
+    return 64ull * r.W * r.H + 56ull * r.K + 8ull * r.K * r.N + 8ull * r.N;
 }
 
 static void server_release(plan_server *s) {
     (void)hipStreamSynchronize(s->stream);
-    (void)hipFree(s->tex);
+    (void)hipFree(s->cells);
     (void)hipFree(s->state);
     (void)hipFree(s->cost);
     (void)hipFree(s->slot_args);
@@ -256,9 +256,10 @@ static plan_status_t admit(plan_server *s) {
         const plan_request_t &r = q.r;
         AdmitEntry &e = stage[count++];
         memset(&e, 0, sizeof e);
-        e.tex = s->tex + (size_t)slot * s->max_W * s->max_H;
+        e.cells = s->cells + (size_t)slot * 4 * plan::terrain_cells(s->max_W, s->max_H);
         RolloutArgs &a = e.args;
-        plan::fill_rollout_args(a, s->veh, r.cost, r.integ, e.tex, r.W, r.H, r.x0, r.y0, r.res);
+        plan::fill_rollout_args(a, s->veh, r.cost, r.integ, e.cells, r.W, r.H, r.x0, r.y0,
+                                r.res);
         for (int j = 0; j < 13; ++j) a.s0[j] = r.state0[j];
         a.controls = r.controls_dev;
         a.K = r.K;
@@ -277,7 +278,8 @@ static plan_status_t admit(plan_server *s) {
         e.W = r.W;
         e.H = r.H;
         e.inv_res = 1.0f / r.res;
-        const long long work = (long long)r.W * r.H > r.K ? (long long)r.W * r.H : r.K;
+        const long long nc = plan::terrain_cells(r.W, r.H);
+        const long long work = nc > r.K ? nc : r.K;
         extent = work > extent ? work : extent;
         s->slots[slot].req = id;
         s->slots[slot].progress = 0;
@@ -380,8 +382,10 @@ plan_status_t plan_server_create(plan_server **out, const plan_vehicle_t *veh, i
         return sfail(nullptr, PLAN_EINVAL, "max_slots outside [1, 128]");
     if (max_K < 1 || max_N < 1 || max_W < 2 || max_H < 2 || chunk_intervals < 1)
         return sfail(nullptr, PLAN_EINVAL, "sizes must be K,N,chunk >= 1 and W,H >= 2");
-    if ((long long)max_K * 4 > 0x7fffffffll || (long long)max_W * max_H >= (1ll << 27))
-        return sfail(nullptr, PLAN_EINVAL, "sizes too large");
+    if ((long long)max_K * 4 > 0x7fffffffll ||
+        plan::terrain_cells(max_W, max_H) >= plan::MAX_TERRAIN_CELLS)
+        return sfail(nullptr, PLAN_EINVAL,
+                     "sizes too large (K*4 below 2^31, W*H below 2^26)");
     if (budget_bytes == 0) return sfail(nullptr, PLAN_EINVAL, "budget must be positive");
     plan_server *s = new (std::nothrow) plan_server;
     if (!s) return sfail(nullptr, PLAN_ENOMEM, "host allocation failed");
@@ -404,7 +408,8 @@ plan_status_t plan_server_create(plan_server **out, const plan_vehicle_t *veh, i
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device);
         if (e == hipSuccess && cus > 0) s->simds = 4 * cus;
     }
-    if (e == hipSuccess) e = hipMalloc(&s->tex, sizeof(float4) * S * max_W * max_H);
+    if (e == hipSuccess)
+        e = hipMalloc(&s->cells, sizeof(float4) * 4 * S * plan::terrain_cells(max_W, max_H));
     if (e == hipSuccess) e = hipMalloc(&s->state, sizeof(float) * S * 13 * max_K);
     if (e == hipSuccess) e = hipMalloc(&s->cost, sizeof(float) * S * max_K);
     if (e == hipSuccess) e = hipMalloc(&s->slot_args, sizeof(RolloutArgs) * S);

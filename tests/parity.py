@@ -105,9 +105,19 @@ def assert_argmin_parity(k_gpu, ora_J, label=""):
 #
 # The step map is compared one control interval at a time, so both sides
 # start from identical float32 state and differ only by one interval of
-# rounding (~1e-6 relative): F_s - k chi then differs by a few newtons at most
-# (~1e-5 of F_s ~ 2 kN) and a wheel speed by far less than 1 mm/s.
+# rounding (~1e-6 relative): over one Euler step F_s - k chi then differs by
+# a few newtons at most (~1e-5 of F_s ~ 2 kN) and a wheel speed by far less
+# than 1 mm/s. Over an interval of many Euler steps the touchdown instant is
+# more sensitive: at the paper's shape (50 steps per interval) the oracle
+# itself, restarted from its float32 state perturbed by 2^-22 relative
+# (random signs, 8 draws per candidate-interval), lands a wheel one step
+# earlier or later, and so misses the base tolerance 30-fold, in 13.5 % of
+# candidate-intervals with a touchdown margin below 1e-4, 0.3 % of those in
+# [1e-4, 3e-4) and none of 20 400 sampled above 3e-4; TD_EPS_MULTI covers that
+# band with a factor of three (1.4 % of the paper shape's candidate-intervals
+# fall below it, within MAX_EXEMPT).
 TD_EPS = 1e-4
+TD_EPS_MULTI = 1e-3
 SLIP_EPS = 1e-3
 # Past 72 degrees of roll or pitch the paper scores a rollover; the model's
 # contact geometry no longer describes the vehicle (wheels above the chassis)
@@ -290,6 +300,7 @@ def assert_step_map_parity(planner, o, controls_np, controls_dev, state0, chunk,
     worst_s = worst_c = 0.0
     exempt = total = near_count = rolled_count = relaxed_count = compared = 0
     nonfinite_count = 0
+    td_eps = TD_EPS if chunk * o.substeps == 1 else TD_EPS_MULTI
     for n0 in range(0, N, chunk):
         n1 = min(N, n0 + chunk)
         fin = n1 == N
@@ -314,7 +325,7 @@ def assert_step_map_parity(planner, o, controls_np, controls_dev, state0, chunk,
             probe = np.maximum(state_err(sp, so).max(axis=0), cost_err(cp, co))
         bound = np.maximum(1.0, STEP_FACTOR * np.nan_to_num(probe, nan=np.inf))
         rolled = (tilt > ROLLOVER) & start_fin
-        near = ~((td > TD_EPS) & (sl > SLIP_EPS)) & ~rolled & start_fin
+        near = ~((td > td_eps) & (sl > SLIP_EPS)) & ~rolled & start_fin
         near_count += int(near.sum())
         rolled_count += int(rolled.sum())
         near |= rolled | ~start_fin

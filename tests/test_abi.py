@@ -64,11 +64,15 @@ def test_create_rejects_invalid_arguments_without_a_device(lib):
     assert lib.plan_create(C.byref(h), C.byref(v), C.byref(c), C.byref(bi), 8, 8, 8, 8, None) == P.PLAN_EINVAL
     for sizes in ((0, 8, 8, 8), (8, 0, 8, 8), (8, 8, 1, 8), (8, 8, 8, 1)):
         assert lib.plan_create(C.byref(h), C.byref(v), C.byref(c), C.byref(i), *sizes, None) == P.PLAN_EINVAL
-    # texel grids of 2^27 nodes or more (their byte offsets would not fit in
-    # 31 bits) are refused before anything touches a device
+    # terrain grids of 2^26 nodes or more (the byte offsets of their 64-byte
+    # cells, one per node, would not fit in 32 bits) are refused before
+    # anything touches a device, the limit itself (W*H = 2^26) included
     assert lib.plan_create(C.byref(h), C.byref(v), C.byref(c), C.byref(i), 8, 8, 1 << 14, 1 << 13,
                            None) == P.PLAN_EINVAL
-    assert "2^27" in P.plan_last_error(None)
+    assert "2^26" in P.plan_last_error(None)
+    assert lib.plan_create(C.byref(h), C.byref(v), C.byref(c), C.byref(i), 8, 8, 1 << 13,
+                           1 << 13, None) == P.PLAN_EINVAL
+    assert "2^26" in P.plan_last_error(None)
     assert not h.value
 
 
@@ -105,6 +109,8 @@ def test_server_create_and_submit_reject_invalid_arguments(lib):
     bad = P._struct(P.Vehicle, dict(inputs.WORKLOAD_VEHICLE, M=0.0))
     assert cr(C.byref(h), C.byref(bad), 4, 8, 8, 8, 8, 1 << 20, 4, None) == P.PLAN_EINVAL
     assert cr(C.byref(h), C.byref(v), 4, 8, 8, 1 << 14, 1 << 13, 1 << 20, 4, None) == P.PLAN_EINVAL
+    assert cr(C.byref(h), C.byref(v), 4, 8, 8, 1 << 13, 1 << 13, 1 << 20, 4,
+              None) == P.PLAN_EINVAL
     assert not h.value
     rid = C.c_int(0)
     assert lib.plan_server_submit(None, None, C.byref(rid)) == P.PLAN_EINVAL

@@ -121,7 +121,7 @@ def test_slot_limit_bounds_residency(trace):
 
 
 def test_memory_budget_admission(trace):
-    fp = [16 * 256 * 256 + 56 * r.w.K + 8 * r.w.K * r.w.N + 8 * r.w.N for r in trace]
+    fp = [64 * 256 * 256 + 56 * r.w.K + 8 * r.w.K * r.w.N + 8 * r.w.N for r in trace]
     budget = max(fp) + min(fp) - 1  # the largest never shares with another
     srv = _server(trace, budget=budget)
     ids = [r.submit(srv) for r in trace]
