@@ -57,7 +57,7 @@ struct RolloutArgs {
     float accel_max, vx_min;
     // terrain: a W x H node grid stored as W x H cells, each the bilinear
     // coefficients of the four channels (h, f_x, f_y, cost) over the cell
-    // (pack_cell; the last column and row are the grid's edge, constant
+    // (pack_tile; the last column and row are the grid's edge, constant
     // outward)
     const float4 *cells;
     int W, H;
@@ -125,32 +125,6 @@ hipError_t launch_locality_order(const OrderArgs &o, hipStream_t s);
 hipError_t launch_permute_controls(const float *controls, const int *order, int K, int N,
                                    float *out, hipStream_t s);
 
-// Node (i, j) of the terrain: height, slopes by central differences
-// (one-sided on the border) and the costmap's rate. Returns false if the
-// node's height or cost is not finite.
-__device__ __forceinline__ bool terrain_node(const float *__restrict__ hgt,
-                                             const float *__restrict__ cm, int W, int H,
-                                             float inv_res, int i, int j, float4 &t) {
-    const size_t q = (size_t)j * W + i;
-    const float hc = hgt[q];
-    float fx, fy;
-    if (i == 0)
-        fx = (hgt[q + 1] - hc) * inv_res;
-    else if (i == W - 1)
-        fx = (hc - hgt[q - 1]) * inv_res;
-    else
-        fx = (hgt[q + 1] - hgt[q - 1]) * (0.5f * inv_res);
-    if (j == 0)
-        fy = (hgt[q + W] - hc) * inv_res;
-    else if (j == H - 1)
-        fy = (hc - hgt[q - W]) * inv_res;
-    else
-        fy = (hgt[q + W] - hgt[q - W]) * (0.5f * inv_res);
-    const float cc = cm ? cm[q] : 0.0f;
-    t = make_float4(hc, fx, fy, cc);
-    return isfinite(hc) && isfinite(cc);
-}
-
 // Bilinear coefficients of one channel over a cell with corner values a00,
 // a10 (next column), a01 (next row), a11: the interpolant is
 // c0 + c_x t_x + c_y t_y + c_xy t_x t_y with t_x, t_y in [0, 1].
@@ -161,27 +135,82 @@ __device__ __forceinline__ float4 bilinear_coefs(float a00, float a10, float a01
 
 // Cell (i, j), 0 <= i < W, 0 <= j < H, of the packed terrain: 64 bytes, the
 // coefficients of h, f_x, f_y and cost over the square from node (i, j) to
-// node (i+1, j+1), one float4 each. Interpolating within a cell then takes
-// one contiguous load and three multiply-adds per channel. The cells of the
-// last column (row) take node i+1 = i (j+1 = j): the interpolant there is
-// constant along x (y), so a query clamped to the grid's edge lands in such
-// a cell at weight 0 and reads the edge nodes exactly. Returns false if any
-// of the cell's nodes is not finite.
-__device__ __forceinline__ bool pack_cell(const float *__restrict__ hgt,
-                                          const float *__restrict__ cm, int W, int H,
-                                          float inv_res, int i, int j,
-                                          float4 *__restrict__ cells) {
-    const int i1 = min(i + 1, W - 1), j1 = min(j + 1, H - 1);
-    float4 n00, n10, n01, n11;
-    bool ok = terrain_node(hgt, cm, W, H, inv_res, i, j, n00);
-    ok &= terrain_node(hgt, cm, W, H, inv_res, i1, j, n10);
-    ok &= terrain_node(hgt, cm, W, H, inv_res, i, j1, n01);
-    ok &= terrain_node(hgt, cm, W, H, inv_res, i1, j1, n11);
-    float4 *c = cells + 4 * ((size_t)j * W + i);
-    c[0] = bilinear_coefs(n00.x, n10.x, n01.x, n11.x);
-    c[1] = bilinear_coefs(n00.y, n10.y, n01.y, n11.y);
-    c[2] = bilinear_coefs(n00.z, n10.z, n01.z, n11.z);
-    c[3] = bilinear_coefs(n00.w, n10.w, n01.w, n11.w);
+// node (i+1, j+1), one float4 each; node values are the height, its slopes
+// by central differences (one-sided on the border) and the costmap's rate.
+// Interpolating within a cell then takes one contiguous load and three
+// multiply-adds per channel. The cells of the last column (row) take node
+// i+1 = i (j+1 = j): the interpolant there is constant along x (y), so a
+// query clamped to the grid's edge lands in such a cell at weight 0 and
+// reads the edge nodes exactly.
+//
+// One 16 x 16 tile of cells packed by a 256-thread workgroup: the heights
+// of the tile's nodes and their neighbours are staged in LDS once, each
+// node's values computed once, and the cells written as consecutive float4
+// by consecutive lanes (one 1 KB row of the tile per wave and store).
+constexpr int PACK_TILE = 16;
+
+struct PackLds {
+    float h[PACK_TILE + 3][PACK_TILE + 3];       // heights of nodes i0-1 .. i0+17 (clamped)
+    float4 node[PACK_TILE + 1][PACK_TILE + 1];   // node values of nodes i0 .. i0+16 (clamped)
+};
+
+// Packs the cells (i0 .. i0+15, j0 .. j0+15) that lie inside the grid;
+// returns false in a thread that found a non-finite node. Every thread of
+// the workgroup must call it (it synchronises the workgroup).
+__device__ inline bool pack_tile(const float *__restrict__ hgt, const float *__restrict__ cm,
+                                 int W, int H, float inv_res, int i0, int j0,
+                                 float4 *__restrict__ cells, PackLds &L) {
+    constexpr int T = PACK_TILE;
+    const int t = threadIdx.x;
+    for (int q = t; q < (T + 3) * (T + 3); q += 256) {
+        const int li = q % (T + 3), lj = q / (T + 3);
+        const int gi = min(max(i0 - 1 + li, 0), W - 1), gj = min(max(j0 - 1 + lj, 0), H - 1);
+        L.h[lj][li] = hgt[(size_t)gj * W + gi];
+    }
+    __syncthreads();
+    bool ok = true;
+    for (int q = t; q < (T + 1) * (T + 1); q += 256) {
+        const int li = q % (T + 1), lj = q / (T + 1);
+        const int gi = min(i0 + li, W - 1), gj = min(j0 + lj, H - 1);
+        const int hi = gi - i0 + 1, hj = gj - j0 + 1;
+        const float hc = L.h[hj][hi];
+        float fx, fy;
+        if (gi == 0)
+            fx = (L.h[hj][hi + 1] - hc) * inv_res;
+        else if (gi == W - 1)
+            fx = (hc - L.h[hj][hi - 1]) * inv_res;
+        else
+            fx = (L.h[hj][hi + 1] - L.h[hj][hi - 1]) * (0.5f * inv_res);
+        if (gj == 0)
+            fy = (L.h[hj + 1][hi] - hc) * inv_res;
+        else if (gj == H - 1)
+            fy = (hc - L.h[hj - 1][hi]) * inv_res;
+        else
+            fy = (L.h[hj + 1][hi] - L.h[hj - 1][hi]) * (0.5f * inv_res);
+        const float cc = cm ? cm[(size_t)gj * W + gi] : 0.0f;
+        L.node[lj][li] = make_float4(hc, fx, fy, cc);
+        ok = ok && isfinite(hc) && isfinite(cc);
+    }
+    __syncthreads();
+    // float4 q of the tile: cell q / 4 (row-major in the tile), channel q % 4
+    for (int q = t; q < T * T * 4; q += 256) {
+        const int ch = q & 3, cl = q >> 2;
+        const int ci = cl % T, cj = cl / T;
+        const int i = i0 + ci, j = j0 + cj;
+        if (i >= W || j >= H) continue;
+        const float4 n00 = L.node[cj][ci], n10 = L.node[cj][ci + 1];
+        const float4 n01 = L.node[cj + 1][ci], n11 = L.node[cj + 1][ci + 1];
+        float4 c;
+        if (ch == 0)
+            c = bilinear_coefs(n00.x, n10.x, n01.x, n11.x);
+        else if (ch == 1)
+            c = bilinear_coefs(n00.y, n10.y, n01.y, n11.y);
+        else if (ch == 2)
+            c = bilinear_coefs(n00.z, n10.z, n01.z, n11.z);
+        else
+            c = bilinear_coefs(n00.w, n10.w, n01.w, n11.w);
+        cells[4 * ((size_t)j * W + i) + ch] = c;
+    }
     return ok;
 }
 

@@ -23,16 +23,16 @@ constexpr int SM_BLOCK = 1024;                     // softmin: threads per block
 
 // --------------------------------------------------------------- terrain ----
 // Node slopes by central differences (one-sided on the border), merged with
-// the costmap, as the bilinear coefficients of each cell (pack_cell): one
-// thread per cell.
+// the costmap, as the bilinear coefficients of each cell: one 16 x 16 tile
+// of cells per workgroup (pack_tile).
 __global__ __launch_bounds__(256) void pack_terrain(const float *__restrict__ hgt,
                                                     const float *__restrict__ cm, int W, int H,
                                                     float inv_res, float4 *__restrict__ cells,
                                                     int *__restrict__ bad) {
-    const int i = blockIdx.x * 16 + (threadIdx.x & 15);
-    const int j = blockIdx.y * 16 + (threadIdx.x >> 4);
-    if (i >= W || j >= H) return;
-    if (!pack_cell(hgt, cm, W, H, inv_res, i, j, cells)) atomicOr(bad, 1);
+    __shared__ PackLds lds;
+    if (!pack_tile(hgt, cm, W, H, inv_res, blockIdx.x * PACK_TILE, blockIdx.y * PACK_TILE,
+                   cells, lds))
+        atomicOr(bad, 1);
 }
 
 // ---------------------------------------------------------------- argmin ----
@@ -173,7 +173,7 @@ int select_blocks(int K) { return (K + SEL_CHUNK - 1) / SEL_CHUNK; }
 
 hipError_t launch_pack_terrain(const float *h, const float *c, int W, int H, float inv_res,
                                float4 *cells, int *bad, hipStream_t s) {
-    dim3 grid((W + 15) / 16, (H + 15) / 16);
+    dim3 grid((W + PACK_TILE - 1) / PACK_TILE, (H + PACK_TILE - 1) / PACK_TILE);
     hipLaunchKernelGGL(pack_terrain, grid, dim3(256), 0, s, h, c, W, H, inv_res, cells, bad);
     return hipGetLastError();
 }

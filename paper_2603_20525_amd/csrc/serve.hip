@@ -46,12 +46,13 @@ struct AdmitEntry {
 
 // Admission of every request a step admits, in one launch: blockIdx.y picks
 // the request; thread t writes candidate t's initial state and zero running
-// cost and packs cell t of its terrain; thread 0 publishes the launch
-// arguments. The slot's bad-terrain flag was cleared by the rollout that
-// finished its previous request (or at server creation).
+// cost, workgroup b packs tile b of its terrain (pack_tile); thread 0
+// publishes the launch arguments. The slot's bad-terrain flag was cleared by
+// the rollout that finished its previous request (or at server creation).
 __global__ __launch_bounds__(256) void admit_batch(const AdmitEntry *__restrict__ ents,
                                                    RolloutArgs *__restrict__ slot_args,
                                                    int *__restrict__ bad) {
+    __shared__ plan::PackLds lds;
     const AdmitEntry &e = ents[blockIdx.y];
     const int t = blockIdx.x * 256 + threadIdx.x;
     if (t == 0) slot_args[e.slot] = e.args;
@@ -61,9 +62,12 @@ __global__ __launch_bounds__(256) void admit_batch(const AdmitEntry *__restrict_
         for (int q = 0; q < 13; ++q) e.args.state[(size_t)q * K + t] = e.args.s0[q];
         e.args.cost[t] = 0.0f;
     }
-    if (t < e.W * e.H) {
-        const int i = t % e.W, j = t / e.W;
-        if (!plan::pack_cell(e.height, e.costmap, e.W, e.H, e.inv_res, i, j, e.cells))
+    const int tiles_x = (e.W + plan::PACK_TILE - 1) / plan::PACK_TILE;
+    const int tiles_y = (e.H + plan::PACK_TILE - 1) / plan::PACK_TILE;
+    if ((int)blockIdx.x < tiles_x * tiles_y) {  // uniform over the workgroup
+        const int bx = blockIdx.x % tiles_x, by = blockIdx.x / tiles_x;
+        if (!plan::pack_tile(e.height, e.costmap, e.W, e.H, e.inv_res, bx * plan::PACK_TILE,
+                             by * plan::PACK_TILE, e.cells, lds))
             atomicOr(bad + e.slot, 1);
     }
 }
@@ -278,8 +282,11 @@ static plan_status_t admit(plan_server *s) {
         e.W = r.W;
         e.H = r.H;
         e.inv_res = 1.0f / r.res;
-        const long long nc = plan::terrain_cells(r.W, r.H);
-        const long long work = nc > r.K ? nc : r.K;
+        // workgroups: one per 256 candidates, one per tile of the terrain
+        const long long tiles = (long long)((r.W + plan::PACK_TILE - 1) / plan::PACK_TILE) *
+                                ((r.H + plan::PACK_TILE - 1) / plan::PACK_TILE);
+        const long long kb = ((long long)r.K + 255) / 256;
+        const long long work = tiles > kb ? tiles : kb;
         extent = work > extent ? work : extent;
         s->slots[slot].req = id;
         s->slots[slot].progress = 0;
@@ -290,7 +297,7 @@ static plan_status_t admit(plan_server *s) {
     if (count == 0) return PLAN_OK;
     SHIP(s, hipMemcpyAsync(s->admit_dev, stage, sizeof(AdmitEntry) * count,
                            hipMemcpyHostToDevice, s->stream));
-    const dim3 grid((unsigned)((extent + 255) / 256), (unsigned)count);
+    const dim3 grid((unsigned)extent, (unsigned)count);
     hipLaunchKernelGGL(admit_batch, grid, dim3(256), 0, s->stream, s->admit_dev, s->slot_args,
                        s->bad);
     SHIP(s, hipGetLastError());
