@@ -483,11 +483,28 @@ static plan_status_t launch(plan_ctx *c, RolloutArgs &a, Kind kind) {
     // one lane per candidate with at most one wave per SIMD: the kernels
     // scheduled for instruction-level parallelism
     const bool ilp = lanes == 1 && ((long long)a.K + 63) / 64 <= c->simds;
+    // automatic one-lane launches of the paper's shape (several substeps per
+    // interval, no costmap, forward Euler) whose last round of waves would be
+    // a small remainder: that remainder runs four lanes per candidate
+    int split = 0;
+    if (!c->lanes_opt && !c->block_opt && lanes == 1 && block == 64 && kind != Kind::chunk &&
+        a.S > 1 && !a.has_costmap && a.method == 0)
+        split = plan::balanced_split(a.K, c->simds);
     HIP_TRY(c, hipSetDevice(c->device));
     if (c->timing) HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
     if (ordered) {
         const plan_status_t st = order_candidates(c, a, a.s0[12], a.s0[6]);
         if (st != PLAN_OK) return st;
+    }
+    if (split > 0) {
+        HIP_TRY(c, plan::launch_rollout_balanced(
+                       a, split, kind == Kind::sampled || kind == Kind::fused_sampled,
+                       kind == Kind::fused || kind == Kind::fused_sampled, c->stream));
+        if (c->timing) {
+            HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
+            c->ev_recorded = true;
+        }
+        return PLAN_OK;
     }
     switch (kind) {
     case Kind::plain:

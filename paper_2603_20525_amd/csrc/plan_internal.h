@@ -258,6 +258,16 @@ hipError_t launch_rollout_argmin(const RolloutArgs &a, int lanes, int block, boo
 hipError_t launch_rollout_sampled(const RolloutArgs &a, int lanes, int block, hipStream_t s,
                                   bool ilp = false);
 
+// One-lane full-horizon launches of several Euler substeps per interval
+// without a costmap, whose K is R whole rounds of one wave per SIMD (R = 1..3)
+// plus a remainder of at most a quarter round: the remainder runs four lanes
+// per candidate in the same launch (rollout_balanced). balanced_split returns
+// the number of one-lane 64-thread workgroups, or 0 when K is not of that
+// form. Plain or fused (argmin epilogue), materialised or sampled controls.
+int balanced_split(long long K, int simds);
+hipError_t launch_rollout_balanced(const RolloutArgs &a, int split, bool sampled, bool fused,
+                                   hipStream_t s);
+
 // controls [N][2][K] from the generator.
 hipError_t launch_sample_controls(const SampleArgs &sa, int K, int N, float *controls,
                                   hipStream_t s);

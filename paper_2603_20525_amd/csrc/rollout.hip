@@ -81,6 +81,32 @@ hipError_t launch_rollout_argmin(const RolloutArgs &a, int lanes, int block, boo
                : launch_argmin_lanes<1>(a, block, sampled, s);
 }
 
+int balanced_split(long long K, int simds) {
+    const long long round = 64ll * simds;  // candidates of one wave per SIMD
+    const long long R = K / round, rem = K - R * round;
+    if (R < 1 || R > 3 || rem == 0 || 4 * rem > round) return 0;
+    return (int)(R * round / 64);
+}
+
+hipError_t launch_rollout_balanced(const RolloutArgs &a, int split, bool sampled, bool fused,
+                                   hipStream_t s) {
+    const long long tail = (long long)a.K - 64ll * split;
+    if (split < 1 || tail < 1) return hipErrorInvalidValue;
+    const unsigned grid = (unsigned)(split + (tail * 4 + 63) / 64);
+#define PLAN_LAUNCH(SMP, FU)                                                                    \
+    if (sampled == SMP && fused == FU) {                                                        \
+        hipLaunchKernelGGL((rollout_balanced<64, SMP, FU, false, false>), dim3(grid), dim3(64),  \
+                           0, s, a, split);                                                     \
+        return hipGetLastError();                                                               \
+    }
+    PLAN_LAUNCH(false, false)
+    PLAN_LAUNCH(true, false)
+    PLAN_LAUNCH(false, true)
+    PLAN_LAUNCH(true, true)
+#undef PLAN_LAUNCH
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_rollout_slots(const RolloutArgs *slots, const TickTable &t, int *bad,
                                 SelectOut *ring, uint32_t seq, bool s1, int lanes, int block,
                                 hipStream_t s) {

@@ -245,6 +245,47 @@ void rollout_srb(const RolloutArgs a) {
                                         gridDim.x, a.sel_out_host, nullptr);
 }
 
+// A one-lane full-horizon launch whose candidates fill R whole rounds of one
+// wave per SIMD plus a small remainder (the paper's 204 288 candidates are
+// 3.12 waves per SIMD): run one lane per candidate would give that remainder
+// a fourth wave on a few SIMDs and make the whole launch wait for them.
+// Here workgroups [0, split) run one lane per candidate on slots
+// [0, split x BLOCK) and the rest run four lanes per candidate on the
+// remaining slots, so the remainder's work (about half a one-lane wave per
+// 16 candidates) spreads over four times as many SIMDs. Every candidate's
+// arithmetic is the same at any lane count, so results equal the one-lane
+// launch's bit for bit. Held to four waves per SIMD like the one-lane kernel
+// of the same shape.
+template <int BLOCK, bool SAMPLED, bool FUSED, bool S1, bool CM>
+__global__ __launch_bounds__(BLOCK, 4) void rollout_balanced(const RolloutArgs a, int split) {
+    const bool four = (int)blockIdx.x >= split;  // uniform over the workgroup
+    int slot, sub;
+    if (!four) {
+        slot = (int)blockIdx.x * BLOCK + (int)threadIdx.x;
+        sub = 0;
+    } else {
+        const int g = ((int)blockIdx.x - split) * BLOCK + (int)threadIdx.x;
+        slot = split * BLOCK + (g >> 2);
+        sub = g & 3;
+    }
+    const bool store = slot < a.K;
+    if (!store) slot = a.K - 1;
+    int k = slot;
+    const float *up = a.controls + slot;
+    if (a.order) {
+        k = min(max(a.order[slot], 0), a.K - 1);
+        up = a.controls_lane ? a.controls_lane + slot : a.controls + k;
+    }
+    float J;
+    if (four)
+        J = simulate<4, false, SAMPLED, false, false, S1, CM>(a, k, sub, store, up);
+    else
+        J = simulate<1, false, SAMPLED, false, false, S1, CM>(a, k, 0, store, up);
+    if constexpr (FUSED)
+        argmin_epilogue<BLOCK, SAMPLED>(a, (store && sub == 0) ? cost_key(J, k) : ~0ull,
+                                        gridDim.x, a.sel_out_host, nullptr);
+}
+
 // Several independent plans in one launch (the serving loop's tick). Entry e
 // of the table owns blocks [e.block_start, next block_start) and advances
 // slot e.slot through intervals [e.n0, e.n1); every block belongs to exactly

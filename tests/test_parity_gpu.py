@@ -295,6 +295,34 @@ def test_nonsquare_terrain_and_leaving_the_map():
     assert_rollout_parity(J, fs, Jo, fso, "non-square / off-map")
 
 
+@pytest.mark.parametrize("W,H,x,y", [(2, 2, 3.0, 2.5), (2, 37, 4.0, 2.0), (17, 3, 0.5, 4.0),
+                                     (33, 18, 1.0, 4.5)])
+def test_small_and_ragged_terrain_grids(W, H, x, y):
+    """Grids of one cell row or column, and grids that end inside a pack tile
+    (16 x 16 cells): the vehicle starts off the map or next to its edge, so
+    the lookups run through the clamped edge cells. Heights vary along both
+    axes; the 33 x 18 grid carries a costmap. Step map of every candidate,
+    then the whole horizon."""
+    res = 0.5
+    X, Y = np.meshgrid(np.arange(W) * res, np.arange(H) * res)
+    h = (0.15 * np.sin(0.9 * X) + 0.1 * np.cos(0.7 * Y) + 0.03 * X).astype(np.float32)
+    T = inputs.Terrain(h, 0.0, 0.0, res)
+    s0 = inputs.settled_state(T, x, y, 0.3, 8.0, inputs.WORKLOAD_VEHICLE["hR"])
+    u = inputs.gaussian_controls(W * 100 + H, 256, 50, 0.02)
+    cost = dict(inputs.BASE_COST, goal_x=40.0, goal_y=20.0)
+    w = inputs.Workload("grid", dict(inputs.WORKLOAD_VEHICLE), cost, dict(inputs.BASE_INTEG), T,
+                        s0, u)
+    cm = None
+    if W > 16:
+        cm = (20.0 * (1.0 + np.sin(0.5 * X) * np.cos(0.4 * Y))).astype(np.float32)
+    case = Case(w, costmap=cm)
+    assert_step_map_parity(case.planner, case.o, w.controls, dev(w.controls), w.state0, 1,
+                           label=f"{W}x{H} grid step map")
+    J, fs, _ = case.gpu()
+    Jo, fso, _ = case.oracle()
+    assert_rollout_parity(J, fs, Jo, fso, f"{W}x{H} grid")
+
+
 def test_single_candidate_single_interval_and_max_sizes():
     w = inputs.c1(K=1, N=1)
     case = Case(w)
