@@ -14,99 +14,86 @@
 namespace plan {
 namespace {
 
-constexpr int ROW_OUT = 8;                      // outputs per thread, row pass
+constexpr int ROW_OUT = 4;                      // outputs per thread, row pass
 constexpr int ROW_TILE = 256 * ROW_OUT;         // outputs per workgroup, row pass
 constexpr int COL_W = 32;                       // columns per workgroup, column pass
-constexpr int COL_LD = COL_W + 1;               // LDS row stride (the two row groups of a
-                                                // wave fall in different banks)
-constexpr int COL_RUN = 16;                     // consecutive rows per thread, column pass
-constexpr int COL_T = (256 / COL_W) * COL_RUN;  // rows per workgroup, column pass (128)
-
-// Sliding-window sums over a staged line: acc[o] = sum_k w[k] x[o + k],
-// k = 0 .. 2r in order, for OUT outputs. The window advances OUT taps per
-// refill, so its registers rotate by static indexing instead of a move per
-// tap; ld(q) reads x[q] from LDS.
-template <int OUT, class Load>
-__device__ __forceinline__ void window_sums(const SmoothTaps &taps, int r, Load ld,
-                                            float (&acc)[OUT]) {
-    float buf[2 * OUT];
-#pragma unroll
-    for (int o = 0; o < OUT; ++o) {
-        acc[o] = 0.0f;
-        buf[o] = ld(o);
-    }
-    for (int k0 = 0; k0 <= 2 * r; k0 += OUT) {
-#pragma unroll
-        for (int o = 0; o < OUT; ++o) buf[OUT + o] = ld(k0 + OUT + o);
-#pragma unroll
-        for (int kk = 0; kk < OUT; ++kk) {
-            if (k0 + kk <= 2 * r) {  // uniform over the workgroup
-                const float w = taps.w[k0 + kk];
-#pragma unroll
-                for (int o = 0; o < OUT; ++o) acc[o] = fmaf(w, buf[kk + o], acc[o]);
-            }
-        }
-#pragma unroll
-        for (int o = 0; o < OUT; ++o) buf[o] = buf[OUT + o];
-    }
-}
+constexpr int COL_RUN = 8;                      // consecutive rows per thread, column pass
+constexpr int COL_T = (256 / COL_W) * COL_RUN;  // rows per workgroup, column pass (64)
 
 // Row pass: tmp[j][i] = sum_k w[k] h[j][clamp(i + k - r)], k = 0 .. 2r in
-// order. Each thread produces ROW_OUT neighbouring outputs from the LDS row
-// tile (staged with its halo and OUT floats of padding for the last refill).
+// order. Each thread produces ROW_OUT neighbouring outputs from one sliding
+// window of the LDS row tile.
 __global__ __launch_bounds__(256) void smooth_rows(const float *__restrict__ h, int W, int H,
                                                    const SmoothTaps taps,
                                                    float *__restrict__ tmp) {
-    __shared__ float tile[ROW_TILE + 2 * MAX_SMOOTH_RADIUS + ROW_OUT];
+    __shared__ float tile[ROW_TILE + 2 * MAX_SMOOTH_RADIUS];
     const int r = taps.r;
     const int j = blockIdx.y;
     if (j >= H) return;  // whole workgroup (grid rows = H)
     const int i0 = blockIdx.x * ROW_TILE;
     const float *row = h + (size_t)j * W;
-    for (int q = threadIdx.x; q < ROW_TILE + 2 * r + ROW_OUT; q += 256) {
+    for (int q = threadIdx.x; q < ROW_TILE + 2 * r; q += 256) {
         const int i = min(max(i0 + q - r, 0), W - 1);
         tile[q] = row[i];
     }
     __syncthreads();
     const int base = threadIdx.x * ROW_OUT;  // first output of this thread in the tile
     float acc[ROW_OUT];
-    window_sums<ROW_OUT>(taps, r, [&](int q) { return tile[base + q]; }, acc);
-    const int i = i0 + base;
-    float *dst = tmp + (size_t)j * W + i;
-    if ((W & 3) == 0 && i + ROW_OUT <= W) {
-        // rows start 16-byte aligned: two 16-byte stores
-        reinterpret_cast<float4 *>(dst)[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
-        reinterpret_cast<float4 *>(dst)[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
-    } else {
 #pragma unroll
-        for (int o = 0; o < ROW_OUT; ++o)
-            if (i + o < W) dst[o] = acc[o];
+    for (int o = 0; o < ROW_OUT; ++o) acc[o] = 0.0f;
+    float win[ROW_OUT];
+#pragma unroll
+    for (int o = 0; o < ROW_OUT - 1; ++o) win[o + 1] = tile[base + o];
+    for (int k = 0; k <= 2 * r; ++k) {
+        // window = tile[base + k .. base + k + ROW_OUT - 1]
+#pragma unroll
+        for (int o = 0; o < ROW_OUT - 1; ++o) win[o] = win[o + 1];
+        win[ROW_OUT - 1] = tile[base + k + ROW_OUT - 1];
+        const float w = taps.w[k];
+#pragma unroll
+        for (int o = 0; o < ROW_OUT; ++o) acc[o] = fmaf(w, win[o], acc[o]);
     }
+    float *dst = tmp + (size_t)j * W + i0 + base;
+#pragma unroll
+    for (int o = 0; o < ROW_OUT; ++o)
+        if (i0 + base + o < W) dst[o] = acc[o];
 }
 
 // Column pass: out[j][i] = sum_k w[k] tmp[clamp(j + k - r)][i]; a tile of
-// COL_T rows x COL_W columns plus the vertical halo (and ROW_OUT-style
-// padding) is staged in LDS (at most 398 x 33 floats, 52.5 KB). Thread t owns
-// column t % COL_W and the COL_RUN consecutive rows starting at
-// (t / COL_W) * COL_RUN.
+// COL_T rows x COL_W columns plus the vertical halo is staged in LDS (at most
+// 318 x 32 floats, 40.7 KB). Thread t owns column t % COL_W and the COL_RUN
+// consecutive rows starting at (t / COL_W) * COL_RUN, swept with a sliding
+// window of the column.
 __global__ __launch_bounds__(256) void smooth_cols(const float *__restrict__ tmp, int W, int H,
                                                    const SmoothTaps taps,
                                                    float *__restrict__ out) {
-    __shared__ float tile[(COL_T + 2 * MAX_SMOOTH_RADIUS + COL_RUN) * COL_LD];
+    __shared__ float tile[(COL_T + 2 * MAX_SMOOTH_RADIUS) * COL_W];
     const int r = taps.r;
     const int i0 = blockIdx.x * COL_W, j0 = blockIdx.y * COL_T;
-    const int rows = COL_T + 2 * r + COL_RUN;
+    const int rows = COL_T + 2 * r;
     const int c = threadIdx.x & (COL_W - 1);
     const int i = min(i0 + c, W - 1);
     for (int q = threadIdx.x / COL_W; q < rows; q += 256 / COL_W) {
         const int j = min(max(j0 + q - r, 0), H - 1);
-        tile[q * COL_LD + c] = tmp[(size_t)j * W + i];
+        tile[q * COL_W + c] = tmp[(size_t)j * W + i];
     }
     __syncthreads();
     if (i0 + c >= W) return;
     const int t0 = (threadIdx.x / COL_W) * COL_RUN;  // first output row in the tile
     float acc[COL_RUN];
-    window_sums<COL_RUN>(taps, r, [&](int q) { return tile[(t0 + q) * COL_LD + c]; }, acc);
+#pragma unroll
+    for (int o = 0; o < COL_RUN; ++o) acc[o] = 0.0f;
+    float win[COL_RUN];
+#pragma unroll
+    for (int o = 0; o < COL_RUN - 1; ++o) win[o + 1] = tile[(t0 + o) * COL_W + c];
+    for (int k = 0; k <= 2 * r; ++k) {
+#pragma unroll
+        for (int o = 0; o < COL_RUN - 1; ++o) win[o] = win[o + 1];
+        win[COL_RUN - 1] = tile[(t0 + k + COL_RUN - 1) * COL_W + c];
+        const float w = taps.w[k];
+#pragma unroll
+        for (int o = 0; o < COL_RUN; ++o) acc[o] = fmaf(w, win[o], acc[o]);
+    }
 #pragma unroll
     for (int o = 0; o < COL_RUN; ++o) {
         const int j = j0 + t0 + o;
