@@ -200,12 +200,14 @@ __device__ __forceinline__ WheelPre wheel_pre(const RolloutArgs &a, const Motion
     p.viy = fmaf(m.wz, r.rx, fmaf(-m.wx, r.rz, m.vy));
     p.viz = fmaf(m.wx, r.ry, fmaf(-m.wy, r.rx, m.vz));
     // slip angle (literal atan of the velocity ratio; 0/0 gives -delta_i),
-    // evaluated without a branch so the step stays one basic block
+    // evaluated without a branch so the step stays one basic block. For
+    // finite velocities the ratio is NaN only at 0/0 (v_rcp(0) is infinite),
+    // which maps to ratio 0, atan 0 = 0; a NaN velocity means a non-finite
+    // state, which scores +inf at the end whatever the slip angle.
     const float dl = r.front ? m.delta : 0.0f;
-    const bool guard = (p.vix == 0.0f && p.viy == 0.0f);
-    const float ratio = guard ? 0.0f : p.viy * frcp(p.vix);
-    const float at = atanf(ratio);
-    const float alpha = guard ? -dl : at - dl;
+    float ratio = p.viy * frcp(p.vix);
+    ratio = (ratio == ratio) ? ratio : 0.0f;
+    const float alpha = atanf(ratio) - dl;
     const float Ca = a.C * alpha;
     p.tire = -Ca * a.mu;
     p.q = frsq(fmaf(Ca, Ca, a.mu2));
