@@ -32,17 +32,18 @@ METRIC = "candidate rollout-steps/sec and p50/p99 plan latency (serving vs plain
 
 # FP32 operations per rollout-step of the step definition, one lane per
 # candidate, transcendentals counted as one: goal test 5, attitude 21, CoM in
-# grid units 2, kinematics 26, four wheels of 78 (contact point and lookup
+# grid units 2, kinematics 26, four wheels of 74 (contact point and lookup
 # coordinates 9, cell index and weights 9, contact velocity 6, interpolation
 # of four channels from the cell's bilinear coefficients 12, normal 6,
-# extension 3, rate 6, spring and damper 7, slip 6, tire 5, forces and
-# moments 9), wheel sums 18, right-hand side rows 17, ESM and soft cost 12,
-# running cost 5, Euler update and clamps 19, control clamp 5 per interval:
-# 442 with a costmap. A plan without a costmap has no cost-channel term (its
+# extension 3, rate 6, spring and damper 7, slip 6, tire 5, forces and the
+# moment terms rx Fz and rx fy 5), wheel sums 18, the three moments from
+# those sums 4, right-hand side rows 17, ESM and soft cost 12, running cost
+# 5, Euler update and clamps 19, control clamp 5 per interval: 430 with a
+# costmap. A plan without a costmap has no cost-channel term (its
 # interpolation at the four wheels 12, its wheel sum 3 and its addition to
-# the running cost 1), and its kernels skip it: 426. Every workload here runs
-# without a costmap, so the algorithmic side of the ALU roofline counts 426.
-OPS_PER_STEP_COSTMAP = 442
+# the running cost 1), and its kernels skip it: 414. Every workload here runs
+# without a costmap, so the algorithmic side of the ALU roofline counts 414.
+OPS_PER_STEP_COSTMAP = 430
 OPS_PER_STEP = OPS_PER_STEP_COSTMAP - 16
 # MI355X vector ALU issue: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz, one
 # non-packed FP32 operation per lane per clock.

@@ -70,12 +70,13 @@ __device__ __forceinline__ Attitude attitude(float psi, float th, float ph) {
 struct Arm {
     float rx, ry, rz;
     float gx, gy, gz;
-    bool front;
+    bool front, left;  // left: ry = +e/2
 };
 
 __device__ __forceinline__ Arm arm(const RolloutArgs &a, int wi) {
     Arm r;
     r.front = wi < 2;
+    r.left = (wi & 1) == 0;
     r.rx = r.front ? a.Lf : -a.Lr;
     r.ry = (wi & 1) ? -a.half_e : a.half_e;
     r.rz = -a.hR;
@@ -173,10 +174,17 @@ __device__ __forceinline__ float bil(const float4 &c, float tx, float ty) {
     return fmaf(tx, c.y, fmaf(ty, fmaf(tx, c.w, c.z), c.x));
 }
 
-// Force and moment contributions of one wheel (sums of the force and moment
-// equations of the SRB section).
+// Force contributions of one wheel to the sums of the force and moment
+// equations of the SRB section. The moments about the CoM are not formed
+// per wheel: every wheel has the same lever arm rz = -hR and ry = +-e/2, and
+// the rear traction force acts on both rear wheels, so
+//   sum Mx = (e/2) (sum of +-Fz) - rz (sum fy),
+//   sum My = rz (2 FxR) - sum rx Fz,
+//   sum Mz = sum rx fy - (e/2) FxR + (e/2) FxR = sum rx fy,
+// and each wheel contributes Fz with the sign of its ry (Sx), rx Fz (Tx) and
+// rx fy (Ux).
 struct WheelOut {
-    float Fy, Fz, Mx, My, Mz, c;
+    float Fy, Fz, Sx, Tx, Ux, c;
 };
 
 struct Motion {
@@ -243,20 +251,19 @@ __device__ __forceinline__ WheelOut wheel(const RolloutArgs &a, const Attitude &
     const float Fz = Fk + Fb;
     // sigmoid tire
     const float Fy = (Fz * p.tire) * p.q;
-    const float Fx = r.front ? 0.0f : m.FxR;
     const float fy = r.front ? Fy * m.cosd : Fy;
     WheelOut o;
     o.Fy = fy;
     o.Fz = Fz;
-    o.Mx = fmaf(r.ry, Fz, -(r.rz * fy));
-    o.My = fmaf(r.rz, Fx, -(r.rx * Fz));
-    o.Mz = fmaf(r.rx, fy, -(r.ry * Fx));
+    o.Sx = r.left ? Fz : -Fz;
+    o.Tx = r.rx * Fz;
+    o.Ux = r.rx * fy;
     o.c = tc;
     return o;
 }
 
 __device__ __forceinline__ WheelOut wadd(const WheelOut &p, const WheelOut &q) {
-    return WheelOut{p.Fy + q.Fy, p.Fz + q.Fz, p.Mx + q.Mx, p.My + q.My, p.Mz + q.Mz, p.c + q.c};
+    return WheelOut{p.Fy + q.Fy, p.Fz + q.Fz, p.Sx + q.Sx, p.Tx + q.Tx, p.Ux + q.Ux, p.c + q.c};
 }
 
 // Work a caller issues inside the step right after the terrain gathers (a
@@ -348,10 +355,13 @@ __device__ __forceinline__ float srb_rhs(const RolloutArgs &a, const Arm (&arms)
     }
     const float Fy = group_sum<LANES>(sum.Fy);
     const float Fz = group_sum<LANES>(sum.Fz);
-    const float Mx = group_sum<LANES>(sum.Mx);
-    const float My = group_sum<LANES>(sum.My);
-    const float Mz = group_sum<LANES>(sum.Mz);
+    const float Sx = group_sum<LANES>(sum.Sx);
+    const float Tx = group_sum<LANES>(sum.Tx);
+    const float Mz = group_sum<LANES>(sum.Ux);
     const float csum = CM ? group_sum<LANES>(sum.c) : 0.0f;
+    // moments about the CoM (see WheelOut): rz = -hR
+    const float Mx = fmaf(a.half_e, Sx, a.hR * Fy);
+    const float My = fmaf(-a.hR, m.FxR + m.FxR, -Tx);
 
     // right-hand side rows (Newton-Euler in the body frame)
     const float vyd = fmaf(Fy, a.invM, gBy) + fmaf(wx, vz, -(wz * vx));
