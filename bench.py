@@ -32,18 +32,19 @@ METRIC = "candidate rollout-steps/sec and p50/p99 plan latency (serving vs plain
 
 # FP32 operations per rollout-step of the step definition, one lane per
 # candidate, transcendentals counted as one: goal test 5, attitude 21, CoM in
-# grid units 2, kinematics 26, four wheels of 74 (contact point and lookup
-# coordinates 9, cell index and weights 9, contact velocity 6, interpolation
-# of four channels from the cell's bilinear coefficients 12, normal 6,
-# extension 3, rate 6, spring and damper 7, slip 6, tire 5, forces and the
-# moment terms rx Fz and rx fy 5), wheel sums 18, the three moments from
-# those sums 4, right-hand side rows 17, ESM and soft cost 12, running cost
-# 5, Euler update and clamps 19, control clamp 5 per interval: 430 with a
-# costmap. A plan without a costmap has no cost-channel term (its
+# grid units 2, kinematics 24, the four wheels' contact points and lookup
+# coordinates 21 and contact velocities 13 (the lever arms share their
+# front/rear and left/right terms), per wheel 59 (cell index and weights 9,
+# interpolation of four channels from the cell's bilinear coefficients 12,
+# normal 6, extension 3, rate 6, spring and damper 7, slip 6, tire 5, forces
+# and the moment terms rx Fz and rx fy 5), wheel sums 18, the three moments
+# from those sums 4, right-hand side rows 17, ESM and soft cost 12, running
+# cost 5, Euler update and clamps 19, control clamp 5 per interval: 402 with
+# a costmap. A plan without a costmap has no cost-channel term (its
 # interpolation at the four wheels 12, its wheel sum 3 and its addition to
-# the running cost 1), and its kernels skip it: 414. Every workload here runs
-# without a costmap, so the algorithmic side of the ALU roofline counts 414.
-OPS_PER_STEP_COSTMAP = 430
+# the running cost 1), and its kernels skip it: 386. Every workload here runs
+# without a costmap, so the algorithmic side of the ALU roofline counts 386.
+OPS_PER_STEP_COSTMAP = 402
 OPS_PER_STEP = OPS_PER_STEP_COSTMAP - 16
 # MI355X vector ALU issue: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz, one
 # non-packed FP32 operation per lane per clock.
@@ -178,11 +179,12 @@ RK4_OPS_PER_STEP = 4 * (OPS_PER_STEP - 24) + 24 + 3 * 13 * 2 + 2 * 13
 # forward pass runs the Euler step (OPS_PER_STEP); the backward kernel
 # recomputes the step from its segment's checkpoint (OPS_PER_STEP) and
 # evaluates the step's vector-Jacobian product: its forward quantities
-# (attitude and chassis 45, CoM in grid units 2, four wheels of 111: gathers,
+# (attitude and chassis 45, CoM in grid units 2, the four wheels' contact
+# points, lookup coordinates and velocities 34, four wheels of 96: gathers,
 # slip, normal, suspension, tire) and the reverse sweep (chassis rows,
 # rotation, trigonometry 160; four wheels of 107, the cost channel's
-# cell-weight derivatives left out; wheel sums 63), 1 142 in all.
-ADJ_VJP_OPS_PER_STEP = 45 + 2 + 4 * 111 + 160 + 4 * 107 + 63
+# cell-weight derivatives left out; wheel sums 63), 1 116 in all.
+ADJ_VJP_OPS_PER_STEP = 45 + 2 + 34 + 4 * 96 + 160 + 4 * 107 + 63
 ADJ_BWD_OPS_PER_STEP = OPS_PER_STEP + ADJ_VJP_OPS_PER_STEP
 HBM_PEAK_GBS = 8000.0
 

@@ -311,8 +311,9 @@ __device__ __forceinline__ float srb_rhs(const RolloutArgs &a, const Arm (&arms)
     const float thd = fmaf(A.cph, wy, -(A.sph * wz));
     const float phd = fmaf(psid, A.sth, wx);
     const float gBx = a.g * A.sth;
-    const float gBy = (-a.g * A.cth) * A.sph;
-    const float gBz = (-a.g * A.cph) * A.cth;
+    // gravity (0, 0, -g) in the body frame: -g times the third row of R
+    const float gBy = -a.g * A.R32;
+    const float gBz = -a.g * A.R33;
     Motion m;
     m.vx = vx;
     m.vy = vy;
