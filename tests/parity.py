@@ -194,7 +194,12 @@ def assert_finite_agreement(gpu_J, gpu_fs, J64, J32, F32, label=""):
     """R1: the GPU and the oracle disagree on which candidates stay finite
     (cost and final state; cost alone when gpu_fs is None) for at most twice
     as many candidates as the oracle's float64 run disagrees with its own
-    float32-storage probe."""
+    float32-storage probe, plus three standard deviations of a Poisson count
+    of that mean: the candidates that change finiteness are the few whose
+    tumbling chassis (past the rollover limit) diverges, and a count of one
+    or two is a noisy estimate of how many a perturbation of the GPU's size
+    flips (the C5 stress plan: 1 in the probe, 2 or 3 on the GPU depending on
+    rounding; a wrong term changes hundreds)."""
     g = np.asarray(gpu_J, np.float64)
     fin = np.isfinite(J64)
     fin_g = np.isfinite(g)
@@ -207,8 +212,9 @@ def assert_finite_agreement(gpu_J, gpu_fs, J64, J32, F32, label=""):
     print(f"{label}: non-finite candidates: oracle {int((~fin).sum())}, gpu {int((~fin_g).sum())}, "
           f"probe {int((~fin_p).sum())}; finite on one side only: gpu {d_gpu}, probe {d_probe}",
           flush=True)
-    assert d_gpu <= 2 * d_probe, (f"{label}: {d_gpu} candidates finite on one side only "
-                                  f"(the oracle's probe: {d_probe})")
+    bound = 2 * d_probe + 3.0 * math.sqrt(2 * d_probe + 1)
+    assert d_gpu <= bound, (f"{label}: {d_gpu} candidates finite on one side only "
+                            f"(the oracle's probe: {d_probe}; bound {bound:.1f})")
     return {"nonfinite_oracle": int((~fin).sum()), "nonfinite_gpu": int((~fin_g).sum()),
             "finite_disagree": d_gpu, "probe_finite_disagree": d_probe,
             "fin": fin, "fin_g": fin_g, "fin_p": fin_p}
