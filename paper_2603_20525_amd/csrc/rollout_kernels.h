@@ -16,6 +16,20 @@
 namespace plan {
 namespace {
 
+// The kernels built with PLAN_REQUEST_AHEAD (the one-lane kernels for
+// launches of at most one wave per SIMD) have registers to spare: their
+// Euler kernels with one substep per interval request each node's terrain a
+// whole step ahead (euler_step_ahead), which holds two nodes' cell
+// coefficients in registers at once (190-260 VGPRs). The one-lane kernels
+// for three or four waves per SIMD (the paper's solver shape) need the
+// registers for occupancy; the two- and four-lane kernels measured no gain
+// (a wave there gathers one or two wheels' cells and waits mostly on its
+// own dependency chain).
+#ifdef PLAN_REQUEST_AHEAD
+constexpr bool REQUEST_AHEAD = true;
+#else
+constexpr bool REQUEST_AHEAD = false;
+#endif
 
 // One candidate k over control intervals [a.n0, a.n1), simulated by the
 // LANES lanes of its group (this lane is number sub). CHUNK: start from and
@@ -78,6 +92,52 @@ __device__ __forceinline__ float simulate(const RolloutArgs &a, int k, int sub, 
     };
     if constexpr (CKPT) write_ckpt(0);
 
+    // Euler with one substep per interval in a request-ahead build: the
+    // terrain of each node is requested a step ahead. The loop
+    // takes two intervals per trip so that the two nodes' requests alternate
+    // between two register sets (P, Q) instead of being copied from one to
+    // the other, which would wait for the loads in flight. A candidate at its
+    // goal skips the step and its requests; it stays frozen, so it never uses
+    // a set again.
+    constexpr bool AHEAD = REQUEST_AHEAD && !RK4 && !CKPT && S1;
+    if constexpr (AHEAD) {
+        auto interval = [&](int n, const NodeRequest<LANES, CM> &cur,
+                            NodeRequest<LANES, CM> &nxt) {
+            float u0, u1;
+            if constexpr (SAMPLED) {
+                if ((n >> 2) != blk_n) {
+                    blk_n = n >> 2;
+                    blk = sample_block(a.smp, k, blk_n);
+                }
+                draw_controls(a.smp, block_word(blk, n & 3), k, n, u0, u1);
+            } else {
+                u0 = nu0;
+                u1 = nu1;
+            }
+            const float dd = clampf_nan(u0, -a.drate_max, a.drate_max);
+            const float ax = a.accel_max * clampf_nan(u1, -1.0f, 1.0f);
+            const float gdx = st[0] - a.goal_x, gdy = st[1] - a.goal_y;
+            if (fmaf(gdx, gdx, gdy * gdy) > a.goal_r2) {
+                if constexpr (SAMPLED) {
+                    euler_step_ahead<LANES, CM>(a, arms, st, J, dd, ax, cur, nxt);
+                } else {
+                    euler_step_ahead<LANES, CM>(a, arms, st, J, dd, ax, cur, nxt, [&]() {
+                        nu0 = unext[0];
+                        nu1 = unext[K];
+                    });
+                }
+            }
+            if (n + 2 < a.n1) unext += 2 * K;
+        };
+        NodeRequest<LANES, CM> P, Q;
+        request_node<LANES, CM>(a, arms, st[0], st[1], st[2], st[3], st[4], st[5], P);
+        int n = a.n0;
+        for (; n + 1 < a.n1; n += 2) {
+            interval(n, P, Q);
+            interval(n + 1, Q, P);
+        }
+        if (n < a.n1) interval(n, P, Q);
+    } else {
     // uniform trip counts: a candidate that reaches the goal stays in the
     // loop frozen (its lanes skip the steps), so the loops carry no
     // per-lane exit or done-flag bookkeeping
@@ -131,6 +191,7 @@ __device__ __forceinline__ float simulate(const RolloutArgs &a, int k, int sub, 
                 write_ckpt(ckpt_done);
             }
         }
+    }
     }
     if constexpr (CKPT) {
         const int nseg = (a.N + a.ckpt_every - 1) / a.ckpt_every;

@@ -6,6 +6,7 @@
 // while with three or four one-lane waves per SIMD (the paper's 204 288
 // candidates) it is 2.6 % slower than the default schedule of rollout.hip.
 #define PLAN_ONE_WAVE_PER_SIMD 1
+#define PLAN_REQUEST_AHEAD 1
 #include "rollout_kernels.h"
 
 namespace plan {

@@ -272,46 +272,47 @@ struct NoHook {
     __device__ __forceinline__ void operator()() const {}
 };
 
-// Right-hand side of the model for one candidate (this lane's wheels, group
-// sums over the candidate's lanes): xd receives the state derivative and the
-// return value is the running cost rate L at the state. A hook other than
-// NoHook runs after the gathers are issued, behind a scheduling barrier so
-// that its loads stay after them.
-template <int LANES, bool CM = true, class Hook = NoHook>
-__device__ __forceinline__ float srb_rhs(const RolloutArgs &a, const Arm (&arms)[4 / LANES],
-                                         const float (&st)[13], float dd, float ax,
-                                         float (&xd)[13], const Hook &hook = Hook()) {
-    constexpr int WPL = 4 / LANES;  // wheels per lane
-    const float half_pi = 1.57079632679489662f;
-    float x = st[0], y = st[1], z = st[2];
-    float psi = st[3], th = st[4], ph = st[5];
-    float vx = st[6], vy = st[7], vz = st[8];
-    float wx = st[9], wy = st[10], wz = st[11];
-    float delta = st[12];
-    // attitude and this lane's terrain requests first, so the
-    // gathers overlap the chassis arithmetic below
-    const Attitude A = attitude(psi, th, ph);
-    const GridPos gp = grid_pos(a, x, y);
-    Gather G[WPL];
-#pragma unroll
-    for (int q = 0; q < WPL; ++q) G[q] = gather<CM>(a, A, gp, z, arms[q]);
-    if constexpr (!std::is_same<Hook, NoHook>::value) {
-        __builtin_amdgcn_sched_barrier(0);
-        hook();
-    }
+// Kinematic rows of the right-hand side: world velocity R v and the
+// Euler-angle rates of the 3-2-1 sequence. They need only the attitude and
+// the state, so the next node's position and angles (x + h of these, the
+// update's own fmaf) are known before the wheel forces are.
+struct Kin {
+    float vWx, vWy, vWz, psid, thd, phd;
+};
 
-    // kinematics: world velocity, Euler-angle rates, gravity in the
-    // body frame, rear longitudinal constraint force
-    const float vWx = fmaf(A.R11, vx, fmaf(A.R12, vy, A.R13 * vz));
-    const float vWy = fmaf(A.R21, vx, fmaf(A.R22, vy, A.R23 * vz));
-    const float vWz = fmaf(A.R31, vx, fmaf(A.R32, vy, A.R33 * vz));
+__device__ __forceinline__ Kin kinematics(const Attitude &A, const float (&st)[13]) {
+    const float vx = st[6], vy = st[7], vz = st[8];
+    const float wx = st[9], wy = st[10], wz = st[11];
+    Kin k;
+    k.vWx = fmaf(A.R11, vx, fmaf(A.R12, vy, A.R13 * vz));
+    k.vWy = fmaf(A.R21, vx, fmaf(A.R22, vy, A.R23 * vz));
+    k.vWz = fmaf(A.R31, vx, fmaf(A.R32, vy, A.R33 * vz));
     const float icth = frcp(A.cth);
     const float t1 = fmaf(A.sph, wy, A.cph * wz);
-    const float psid = t1 * icth;
-    const float thd = fmaf(A.cph, wy, -(A.sph * wz));
-    const float phd = fmaf(psid, A.sth, wx);
-    const float gBx = a.g * A.sth;
+    k.psid = t1 * icth;
+    k.thd = fmaf(A.cph, wy, -(A.sph * wz));
+    k.phd = fmaf(k.psid, A.sth, wx);
+    return k;
+}
+
+// The rest of the right-hand side once the attitude, this lane's terrain
+// requests G and the kinematic rows are there: gravity, the rear constraint
+// force, the running cost, the wheel forces (the first use of G) and the
+// Newton-Euler rows. xd receives the state derivative and the return value
+// is the running cost rate L at the state.
+template <int LANES, bool CM = true>
+__device__ __forceinline__ float srb_forces(const RolloutArgs &a, const Arm (&arms)[4 / LANES],
+                                            const float (&st)[13], float dd, float ax,
+                                            const Attitude &A, const Gather (&G)[4 / LANES],
+                                            const Kin &kn, float (&xd)[13]) {
+    constexpr int WPL = 4 / LANES;  // wheels per lane
+    const float half_pi = 1.57079632679489662f;
+    const float ph = st[5];
+    const float vx = st[6], vy = st[7], vz = st[8];
+    const float wx = st[9], wy = st[10], wz = st[11];
+    const float delta = st[12];
     // gravity (0, 0, -g) in the body frame: -g times the third row of R
+    const float gBx = a.g * A.sth;
     const float gBy = -a.g * A.R32;
     const float gBz = -a.g * A.R33;
     Motion m;
@@ -371,12 +372,12 @@ __device__ __forceinline__ float srb_rhs(const RolloutArgs &a, const Arm (&arms)
     const float wyd = fmaf(-a.dJxz * wx, wz, My) * a.invJyy;
     const float wzd = fmaf(a.dJxy * wx, wy, Mz) * a.invJzz;
 
-    xd[0] = vWx;
-    xd[1] = vWy;
-    xd[2] = vWz;
-    xd[3] = psid;
-    xd[4] = thd;
-    xd[5] = phd;
+    xd[0] = kn.vWx;
+    xd[1] = kn.vWy;
+    xd[2] = kn.vWz;
+    xd[3] = kn.psid;
+    xd[4] = kn.thd;
+    xd[5] = kn.phd;
     xd[6] = ax;
     xd[7] = vyd;
     xd[8] = vzd;
@@ -386,6 +387,31 @@ __device__ __forceinline__ float srb_rhs(const RolloutArgs &a, const Arm (&arms)
     xd[12] = dd;
     // without a costmap the cost channel adds nothing (L0 + 0 is L0)
     return CM ? L0 + csum : L0;
+}
+
+// Right-hand side of the model for one candidate (this lane's wheels, group
+// sums over the candidate's lanes): xd receives the state derivative and the
+// return value is the running cost rate L at the state. A hook other than
+// NoHook runs after the gathers are issued, behind a scheduling barrier so
+// that its loads stay after them.
+template <int LANES, bool CM = true, class Hook = NoHook>
+__device__ __forceinline__ float srb_rhs(const RolloutArgs &a, const Arm (&arms)[4 / LANES],
+                                         const float (&st)[13], float dd, float ax,
+                                         float (&xd)[13], const Hook &hook = Hook()) {
+    constexpr int WPL = 4 / LANES;  // wheels per lane
+    // attitude and this lane's terrain requests first, so the
+    // gathers overlap the chassis arithmetic
+    const Attitude A = attitude(st[3], st[4], st[5]);
+    const GridPos gp = grid_pos(a, st[0], st[1]);
+    Gather G[WPL];
+#pragma unroll
+    for (int q = 0; q < WPL; ++q) G[q] = gather<CM>(a, A, gp, st[2], arms[q]);
+    if constexpr (!std::is_same<Hook, NoHook>::value) {
+        __builtin_amdgcn_sched_barrier(0);
+        hook();
+    }
+    const Kin kn = kinematics(A, st);
+    return srb_forces<LANES, CM>(a, arms, st, dd, ax, A, G, kn, xd);
 }
 
 // Steering-angle limit and speed floor, applied to a completed step.
@@ -402,6 +428,56 @@ __device__ __forceinline__ void euler_step(const RolloutArgs &a, const Arm (&arm
                                            const Hook &hook = Hook()) {
     float xd[13];
     const float L = srb_rhs<LANES, CM>(a, arms, st, dd, ax, xd, hook);
+    J = fmaf(a.h, L, J);
+#pragma unroll
+    for (int q = 0; q < 13; ++q) st[q] = fmaf(a.h, xd[q], st[q]);
+    apply_limits(a, st);
+}
+
+// The terrain requests of one Euler node: its attitude and the cell
+// coefficients of this lane's wheels, whose loads stay in flight until the
+// step at that node uses them.
+template <int LANES, bool CM>
+struct NodeRequest {
+    Attitude A;
+    Gather G[4 / LANES];
+};
+
+template <int LANES, bool CM>
+__device__ __forceinline__ void request_node(const RolloutArgs &a, const Arm (&arms)[4 / LANES],
+                                             float x, float y, float z, float psi, float th,
+                                             float ph, NodeRequest<LANES, CM> &r) {
+    r.A = attitude(psi, th, ph);
+    const GridPos gp = grid_pos(a, x, y);
+#pragma unroll
+    for (int q = 0; q < 4 / LANES; ++q) r.G[q] = gather<CM>(a, r.A, gp, z, arms[q]);
+}
+
+// The same forward-Euler step with its node's terrain requested one step
+// earlier (cur) and the next node's requested here (nxt): the update moves
+// the position and angles by h times the kinematic rows, which the step has
+// before its wheel forces, so the next node's cells are loaded a whole step
+// ahead of their use. The arithmetic is that of euler_step, so the results
+// are the same bits. The hook (the next control pair) is issued before the
+// cell loads: loads complete in issue order, so waiting for the controls at
+// the next interval never waits for the cells.
+template <int LANES, bool CM = true, class Hook = NoHook>
+__device__ __forceinline__ void euler_step_ahead(const RolloutArgs &a,
+                                                 const Arm (&arms)[4 / LANES], float (&st)[13],
+                                                 float &J, float dd, float ax,
+                                                 const NodeRequest<LANES, CM> &cur,
+                                                 NodeRequest<LANES, CM> &nxt,
+                                                 const Hook &hook = Hook()) {
+    const Kin kn = kinematics(cur.A, st);
+    if constexpr (!std::is_same<Hook, NoHook>::value) {
+        hook();
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    request_node<LANES, CM>(a, arms, fmaf(a.h, kn.vWx, st[0]), fmaf(a.h, kn.vWy, st[1]),
+                            fmaf(a.h, kn.vWz, st[2]), fmaf(a.h, kn.psid, st[3]),
+                            fmaf(a.h, kn.thd, st[4]), fmaf(a.h, kn.phd, st[5]), nxt);
+    float xd[13];
+    const float L = srb_forces<LANES, CM>(a, arms, st, dd, ax, cur.A, cur.G, kn, xd);
     J = fmaf(a.h, L, J);
 #pragma unroll
     for (int q = 0; q < 13; ++q) st[q] = fmaf(a.h, xd[q], st[q]);
