@@ -60,12 +60,13 @@ ALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
 TRAFFIC_COUNTERS = {
     # fused kernel, one lane per candidate (c5) and four lanes (c2), 256-thread
     # workgroups, no costmap, cell-coefficient terrain; copy calibration
-    # 262144 KiB read as 131085.49 KiB (x1.99979) and written as 262144.0 KiB (x1.0)
-    "c5": (60253.00, 273.69, 262144.0 / 131085.49, 1.0, "d6c90994a734a5f0"),
-    "c2": (3313.82, 20.91, 262144.0 / 131085.49, 1.0, "d6c90994a734a5f0"),
+    # 262144 KiB read as 131084.55 KiB (x1.99981) and written as 262144.0 KiB (x1.0)
+    "c5": (60615.87, 273.69, 262144.0 / 131084.55, 1.0, "bc2e8365c8235408"),
+    "c2": (3313.82, 20.91, 262144.0 / 131084.55, 1.0, "bc2e8365c8235408"),
 }
 ROLLOUT_SOURCES = ("rollout_step.h", "rollout_kernels.h", "rollout.hip", "rollout_onelane_ilp.hip",
-                   "rollout_multilane.hip", "plan_internal.h", "select_common.h", "sample.h")
+                   "rollout_onelane_ahead.hip", "rollout_multilane.hip", "plan_internal.h",
+                   "select_common.h", "sample.h")
 
 
 def kernel_signature():

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libplan.so")
-SOURCES = ["rollout.hip", "rollout_onelane_ilp.hip", "rollout_multilane.hip", "est.hip",
+SOURCES = ["rollout.hip", "rollout_onelane_ilp.hip", "rollout_onelane_ahead.hip",
+           "rollout_multilane.hip", "est.hip",
            "select.hip", "plan_api.hip", "serve.hip", "adjoint.hip", "terrain_prep.hip",
            "order.hip"]
 

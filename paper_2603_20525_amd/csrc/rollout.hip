@@ -55,11 +55,16 @@ __global__ __launch_bounds__(256) void init_state(const RolloutArgs a) {
 
 }  // namespace
 
-// Public dispatch: one lane here (or, with ilp, in rollout_onelane_ilp.hip),
-// two and four lanes in rollout_multilane.hip.
+// Public dispatch: one lane here (or, with ilp, in rollout_onelane_ilp.hip,
+// and for forward Euler of one substep per interval with materialised
+// controls in rollout_onelane_ahead.hip), two and four lanes in
+// rollout_multilane.hip.
+static bool ahead(const RolloutArgs &a) { return a.method == 0 && a.S == 1; }
+
 hipError_t launch_rollout(const RolloutArgs &a, int lanes, int block, bool chunk,
                           hipStream_t s, bool ilp) {
     if (lanes != 1) return launch_rollout_multi(a, lanes, block, chunk, s);
+    if (ilp && ahead(a)) return launch_rollout_ahead1(a, block, chunk, false, s);
     return ilp ? launch_rollout_ilp1(a, block, chunk, s)
                : launch_rollout_lanes<1>(a, block, chunk, s);
 }
@@ -77,6 +82,7 @@ hipError_t launch_rollout_ckpt(const RolloutArgs &a, int lanes, int block, hipSt
 hipError_t launch_rollout_argmin(const RolloutArgs &a, int lanes, int block, bool sampled,
                                  hipStream_t s, bool ilp) {
     if (lanes != 1) return launch_argmin_multi(a, lanes, block, sampled, s);
+    if (ilp && !sampled && ahead(a)) return launch_rollout_ahead1(a, block, false, true, s);
     return ilp ? launch_argmin_ilp1(a, block, sampled, s)
                : launch_argmin_lanes<1>(a, block, sampled, s);
 }

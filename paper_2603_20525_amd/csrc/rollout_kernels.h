@@ -16,8 +16,8 @@
 namespace plan {
 namespace {
 
-// The kernels built with PLAN_REQUEST_AHEAD (the one-lane kernels for
-// launches of at most one wave per SIMD) have registers to spare: their
+// The kernels built with PLAN_REQUEST_AHEAD (rollout_onelane_ahead.hip: one
+// lane, launches of at most one wave per SIMD) have registers to spare: their
 // Euler kernels with one substep per interval request each node's terrain a
 // whole step ahead (euler_step_ahead), which holds two nodes' cell
 // coefficients in registers at once (190-260 VGPRs). The one-lane kernels
@@ -523,6 +523,12 @@ __forceinline__ hipError_t launch_slots_lanes(const RolloutArgs *slots, const Ti
 hipError_t launch_rollout_ilp1(const RolloutArgs &a, int block, bool chunk, hipStream_t s);
 hipError_t launch_sampled_ilp1(const RolloutArgs &a, int block, hipStream_t s);
 hipError_t launch_argmin_ilp1(const RolloutArgs &a, int block, bool sampled, hipStream_t s);
+
+// One-lane forward Euler of one substep per interval with materialised
+// controls (plain, chunked or fused with the argmin), requesting each node's
+// terrain a step ahead; defined in rollout_onelane_ahead.hip.
+hipError_t launch_rollout_ahead1(const RolloutArgs &a, int block, bool chunk, bool fused,
+                                 hipStream_t s);
 
 // Two- and four-lane dispatch, defined in rollout_multilane.hip.
 hipError_t launch_rollout_multi(const RolloutArgs &a, int lanes, int block, bool chunk,

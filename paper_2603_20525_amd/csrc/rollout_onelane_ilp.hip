@@ -5,8 +5,9 @@
 // (2.6-4 % on the stress workload's 65 536 candidates, one wave per SIMD),
 // while with three or four one-lane waves per SIMD (the paper's 204 288
 // candidates) it is 2.6 % slower than the default schedule of rollout.hip.
+// The forward-Euler kernels of one substep per interval with materialised
+// controls run from rollout_onelane_ahead.hip instead.
 #define PLAN_ONE_WAVE_PER_SIMD 1
-#define PLAN_REQUEST_AHEAD 1
 #include "rollout_kernels.h"
 
 namespace plan {
