@@ -168,7 +168,7 @@ __device__ void step_vjp(const RolloutArgs &a, const Arm (&arms)[4 / LANES],
         const float dl = r.front ? delta : 0.0f;
         guard[i] = (vix[i] == 0.0f && viy[i] == 0.0f);
         rr[i] = guard[i] ? 0.0f : viy[i] * frcp(vix[i]);
-        alpha[i] = guard[i] ? -dl : atanf(rr[i]) - dl;
+        alpha[i] = guard[i] ? -dl : atan_mm(rr[i]) - dl;
         Ca[i] = a.C * alpha[i];
         qq[i] = frsq(fmaf(Ca[i], Ca[i], a.mu2));
         Fyv[i] = (Fz[i] * (-Ca[i] * a.mu)) * qq[i];

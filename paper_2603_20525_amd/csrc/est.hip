@@ -73,8 +73,8 @@ __device__ __forceinline__ void est_step(const RolloutArgs &a, float (&st)[7], f
     const float Fzr = fmaf(-a.Kzzr, gBz, a.Kzx * axb);
     // virtual-tire slip angles (v_x >= vx_min > 0) and sigmoid tire
     const float ivx = frcp(vx);
-    const float af = atanf(fmaf(wz, a.Lf, vy) * ivx) - delta;
-    const float ar = atanf(fmaf(-wz, a.Lr, vy) * ivx);
+    const float af = atan_mm(fmaf(wz, a.Lf, vy) * ivx) - delta;
+    const float ar = atan_mm(fmaf(-wz, a.Lr, vy) * ivx);
     const float Caf = a.C * af, Car = a.C * ar;
     const float Fyf = (Fzf * (-Caf * a.mu)) * frsq(fmaf(Caf, Caf, a.mu2));
     const float Fyr = (Fzr * (-Car * a.mu)) * frsq(fmaf(Car, Car, a.mu2));
