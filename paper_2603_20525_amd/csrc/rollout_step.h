@@ -37,9 +37,12 @@ __device__ __forceinline__ float group_sum(float v) {
 // the sign of x. Largest absolute error in float32 evaluation 4.3e-7 on
 // [-1, 1] and below 6e-7 beyond, where the reciprocal and the subtraction
 // round as well (the library's sine and cosine are of order 1e-6);
-// atan(+-inf) = +-pi/2, NaN in gives NaN.
+// atan(+-inf) = +-pi/2. NAN_TO_ZERO: a NaN argument gives 0 (|x| is taken
+// as the IEEE maximum of |x| and 0, which returns 0 for a NaN), the slip
+// ratio's 0/0 convention at no extra instruction; otherwise NaN gives NaN.
+template <bool NAN_TO_ZERO = false>
 __device__ __forceinline__ float atan_mm(float x) {
-    const float ax = fabsf(x);
+    const float ax = NAN_TO_ZERO ? fmaxf(fabsf(x), 0.0f) : fabsf(x);
     const bool big = ax > 1.0f;
     const float r = big ? frcp(ax) : ax;
     const float t = r * r;
@@ -234,12 +237,10 @@ __device__ __forceinline__ WheelPre wheel_pre(const RolloutArgs &a, const Motion
     // slip angle (literal atan of the velocity ratio; 0/0 gives -delta_i),
     // evaluated without a branch so the step stays one basic block. For
     // finite velocities the ratio is NaN only at 0/0 (v_rcp(0) is infinite),
-    // which maps to ratio 0, atan 0 = 0; a NaN velocity means a non-finite
+    // whose arctangent is taken as 0; a NaN velocity means a non-finite
     // state, which scores +inf at the end whatever the slip angle.
     const float dl = r.front ? m.delta : 0.0f;
-    float ratio = p.viy * frcp(p.vix);
-    ratio = (ratio == ratio) ? ratio : 0.0f;
-    const float alpha = atan_mm(ratio) - dl;
+    const float alpha = atan_mm<true>(p.viy * frcp(p.vix)) - dl;
     const float Ca = a.C * alpha;
     p.tire = -Ca * a.mu;
     p.q = frsq(fmaf(Ca, Ca, a.mu2));

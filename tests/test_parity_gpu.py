@@ -86,6 +86,22 @@ def test_c1_full_parity_every_launch_shape(c1, lanes, block):
     print(f"c1 lanes={lanes} block={block}: max cost err {ce:.3g}, state err {se:.3g} (x tol)")
 
 
+@pytest.mark.parametrize("lanes,block", SHAPES)
+def test_start_at_rest_takes_the_zero_over_zero_slip_convention(c1, lanes, block):
+    """From rest every wheel's contact-point velocity is 0/0 at the first
+    node: the slip angle is then -delta_i (the convention of the oracle), not
+    a NaN that would score the candidate +inf. Two intervals, every launch
+    shape, against the oracle."""
+    s0 = np.array(c1.w.state0, dtype=np.float32).copy()
+    s0[6:12] = 0.0
+    u = np.ascontiguousarray(c1.w.controls[:2])
+    J, fs, _ = c1.gpu(controls=u, state0=s0, lanes=lanes, block=block)
+    assert np.isfinite(J).all() and np.isfinite(fs).all()
+    Jo, fso, _ = c1.oracle(controls=u, state0=s0)
+    ce, se = assert_rollout_parity(J, fs, Jo, fso, f"c1 at rest lanes={lanes} block={block}")
+    print(f"c1 from rest lanes={lanes} block={block}: max cost err {ce:.3g}, state err {se:.3g}")
+
+
 def _horizon(case, idx=None, lanes=0, block=0, label="", min_cost=0.9, min_state=0.5,
              controls=None, **kw):
     """Whole-horizon parity of every candidate (or of the candidates idx)
