@@ -8,21 +8,17 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libplan.so")
-SOURCES = ["rollout.hip", "rollout_onelane_ilp.hip", "rollout_onelane_ahead.hip",
-           "rollout_multilane.hip", "est.hip",
+SOURCES = ["rollout.hip", "rollout_onelane_1wave.hip", "rollout_multilane.hip", "est.hip",
            "select.hip", "plan_api.hip", "serve.hip", "adjoint.hip", "terrain_prep.hip",
            "order.hip"]
 
-# Per-source flags. The two- and four-lane rollout kernels, and the one-lane
-# kernels used for launches of at most one wave per SIMD, are scheduled for
-# instruction-level parallelism: each SIMD then holds at most one or two
-# waves, so the per-step latency of a single wave is what counts (measured
-# 3-4 % faster; the one-lane kernels of rollout.hip, which serve launches of
-# three or four waves per SIMD, are 2.6 % faster with the default schedule).
-SOURCE_FLAGS = {
-    "rollout_multilane.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
-    "rollout_onelane_ilp.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
-}
+# Per-source flags (none at present). Every unit uses the default instruction
+# scheduler: the max-ILP scheduler, once 3-4 % faster for the kernels of one
+# wave per SIMD, measured slower on the current step (one-lane stress plan
+# 196.7 against 193.4 us; one-lane sampled paper-shape plans at 49 152 and
+# 65 536 candidates 0.89-0.90 against 0.83-0.85 ms; two lanes at 32 768
+# candidates 71.0 against 69.5 us) and equal at four lanes.
+SOURCE_FLAGS = {}
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

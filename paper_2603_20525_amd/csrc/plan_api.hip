@@ -481,8 +481,8 @@ static plan_status_t launch(plan_ctx *c, RolloutArgs &a, Kind kind) {
     c->last_lanes = lanes;
     c->last_block = block;
     // one lane per candidate with at most one wave per SIMD: the kernels
-    // scheduled for instruction-level parallelism
-    const bool ilp = lanes == 1 && ((long long)a.K + 63) / 64 <= c->simds;
+    // built for a wave that has its SIMD to itself
+    const bool one_wave = lanes == 1 && ((long long)a.K + 63) / 64 <= c->simds;
     // automatic one-lane launches of the paper's shape (several substeps per
     // interval, no costmap, forward Euler) whose last round of waves would be
     // a small remainder: that remainder runs four lanes per candidate
@@ -509,15 +509,15 @@ static plan_status_t launch(plan_ctx *c, RolloutArgs &a, Kind kind) {
     switch (kind) {
     case Kind::plain:
     case Kind::chunk:
-        HIP_TRY(c, plan::launch_rollout(a, lanes, block, kind == Kind::chunk, c->stream, ilp));
+        HIP_TRY(c, plan::launch_rollout(a, lanes, block, kind == Kind::chunk, c->stream, one_wave));
         break;
     case Kind::sampled:
-        HIP_TRY(c, plan::launch_rollout_sampled(a, lanes, block, c->stream, ilp));
+        HIP_TRY(c, plan::launch_rollout_sampled(a, lanes, block, c->stream, one_wave));
         break;
     case Kind::fused:
     case Kind::fused_sampled:
         HIP_TRY(c, plan::launch_rollout_argmin(a, lanes, block, kind == Kind::fused_sampled,
-                                               c->stream, ilp));
+                                               c->stream, one_wave));
         break;
     }
     if (c->timing) {

@@ -238,11 +238,12 @@ struct TickTable {
 
 // chunk = false: candidates start from s0 with zero cost. chunk = true:
 // they continue from a.state / a.cost. Both run the same step code.
-// ilp (one lane per candidate only): use the kernels scheduled for
-// instruction-level parallelism, for launches of at most one wave per SIMD;
-// the arithmetic, and so every result, is the same either way.
+// one_wave (one lane per candidate only): use the kernels built for launches
+// of at most one wave per SIMD (no four-wave register bound; forward Euler of
+// one substep per interval requests each node's terrain a step ahead); the
+// arithmetic, and so every result, is the same either way.
 hipError_t launch_rollout(const RolloutArgs &a, int lanes, int block, bool chunk, hipStream_t s,
-                          bool ilp = false);
+                          bool one_wave = false);
 
 // Full-horizon rollout that also stores every candidate's state at each
 // checkpoint (a.ckpt, a.ckpt_every): the adjoint's forward pass in one launch.
@@ -251,12 +252,12 @@ hipError_t launch_rollout_ckpt(const RolloutArgs &a, int lanes, int block, hipSt
 // Full-horizon rollout whose last workgroup to finish also selects the argmin
 // (a.sel_* and a.plan), with controls read (sampled = false) or drawn.
 hipError_t launch_rollout_argmin(const RolloutArgs &a, int lanes, int block, bool sampled,
-                                 hipStream_t s, bool ilp = false);
+                                 hipStream_t s, bool one_wave = false);
 
 // As launch_rollout (full horizon from a.s0) with the controls drawn in the
 // kernel from a.smp instead of read from a.controls.
 hipError_t launch_rollout_sampled(const RolloutArgs &a, int lanes, int block, hipStream_t s,
-                                  bool ilp = false);
+                                  bool one_wave = false);
 
 // One-lane full-horizon launches of several Euler substeps per interval
 // without a costmap, whose K is R whole rounds of one wave per SIMD (R = 1..3)

@@ -55,24 +55,19 @@ __global__ __launch_bounds__(256) void init_state(const RolloutArgs a) {
 
 }  // namespace
 
-// Public dispatch: one lane here (or, with ilp, in rollout_onelane_ilp.hip,
-// and for forward Euler of one substep per interval with materialised
-// controls in rollout_onelane_ahead.hip), two and four lanes in
-// rollout_multilane.hip.
-static bool ahead(const RolloutArgs &a) { return a.method == 0 && a.S == 1; }
-
+// Public dispatch: one lane here (or, with one_wave, in
+// rollout_onelane_1wave.hip), two and four lanes in rollout_multilane.hip.
 hipError_t launch_rollout(const RolloutArgs &a, int lanes, int block, bool chunk,
-                          hipStream_t s, bool ilp) {
+                          hipStream_t s, bool one_wave) {
     if (lanes != 1) return launch_rollout_multi(a, lanes, block, chunk, s);
-    if (ilp && ahead(a)) return launch_rollout_ahead1(a, block, chunk, false, s);
-    return ilp ? launch_rollout_ilp1(a, block, chunk, s)
-               : launch_rollout_lanes<1>(a, block, chunk, s);
+    return one_wave ? launch_rollout_1wave(a, block, chunk, s)
+                    : launch_rollout_lanes<1>(a, block, chunk, s);
 }
 
 hipError_t launch_rollout_sampled(const RolloutArgs &a, int lanes, int block, hipStream_t s,
-                                  bool ilp) {
+                                  bool one_wave) {
     if (lanes != 1) return launch_sampled_multi(a, lanes, block, s);
-    return ilp ? launch_sampled_ilp1(a, block, s) : launch_sampled_lanes<1>(a, block, s);
+    return one_wave ? launch_sampled_1wave(a, block, s) : launch_sampled_lanes<1>(a, block, s);
 }
 
 hipError_t launch_rollout_ckpt(const RolloutArgs &a, int lanes, int block, hipStream_t s) {
@@ -80,11 +75,10 @@ hipError_t launch_rollout_ckpt(const RolloutArgs &a, int lanes, int block, hipSt
 }
 
 hipError_t launch_rollout_argmin(const RolloutArgs &a, int lanes, int block, bool sampled,
-                                 hipStream_t s, bool ilp) {
+                                 hipStream_t s, bool one_wave) {
     if (lanes != 1) return launch_argmin_multi(a, lanes, block, sampled, s);
-    if (ilp && !sampled && ahead(a)) return launch_rollout_ahead1(a, block, false, true, s);
-    return ilp ? launch_argmin_ilp1(a, block, sampled, s)
-               : launch_argmin_lanes<1>(a, block, sampled, s);
+    return one_wave ? launch_argmin_1wave(a, block, sampled, s)
+                    : launch_argmin_lanes<1>(a, block, sampled, s);
 }
 
 int balanced_split(long long K, int simds) {

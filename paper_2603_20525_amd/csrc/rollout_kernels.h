@@ -1,12 +1,9 @@
 // Rollout kernel templates (SRB model, stage cost, ESM constraint) and, per
 // lane count, their launch dispatch. Three translation units instantiate
-// them: rollout.hip (one lane per candidate), rollout_onelane_ilp.hip (one
+// them: rollout.hip (one lane per candidate), rollout_onelane_1wave.hip (one
 // lane per candidate for launches of at most one wave per SIMD) and
-// rollout_multilane.hip (two and four lanes per candidate); the last two are
-// compiled with the max-ILP instruction scheduler, which shortens the
-// per-step latency of a wave that has its SIMD to itself and lengthens the
-// step where three or four one-lane waves share a SIMD. The arithmetic is the
-// same in all, so results are identical for every launch shape.
+// rollout_multilane.hip (two and four lanes per candidate). The arithmetic is
+// the same in all, so results are identical for every launch shape.
 #pragma once
 
 #include "plan_internal.h"
@@ -16,7 +13,7 @@
 namespace plan {
 namespace {
 
-// The kernels built with PLAN_REQUEST_AHEAD (rollout_onelane_ahead.hip: one
+// The kernels built with PLAN_REQUEST_AHEAD (rollout_onelane_1wave.hip: one
 // lane, launches of at most one wave per SIMD) have registers to spare: their
 // Euler kernels with one substep per interval request each node's terrain a
 // whole step ahead (euler_step_ahead), which holds two nodes' cell
@@ -518,17 +515,11 @@ __forceinline__ hipError_t launch_slots_lanes(const RolloutArgs *slots, const Ti
 
 }  // namespace
 
-// One-lane dispatch on the kernels built with the max-ILP scheduler, defined
-// in rollout_onelane_ilp.hip.
-hipError_t launch_rollout_ilp1(const RolloutArgs &a, int block, bool chunk, hipStream_t s);
-hipError_t launch_sampled_ilp1(const RolloutArgs &a, int block, hipStream_t s);
-hipError_t launch_argmin_ilp1(const RolloutArgs &a, int block, bool sampled, hipStream_t s);
-
-// One-lane forward Euler of one substep per interval with materialised
-// controls (plain, chunked or fused with the argmin), requesting each node's
-// terrain a step ahead; defined in rollout_onelane_ahead.hip.
-hipError_t launch_rollout_ahead1(const RolloutArgs &a, int block, bool chunk, bool fused,
-                                 hipStream_t s);
+// One-lane dispatch for launches of at most one wave per SIMD, defined in
+// rollout_onelane_1wave.hip.
+hipError_t launch_rollout_1wave(const RolloutArgs &a, int block, bool chunk, hipStream_t s);
+hipError_t launch_sampled_1wave(const RolloutArgs &a, int block, hipStream_t s);
+hipError_t launch_argmin_1wave(const RolloutArgs &a, int block, bool sampled, hipStream_t s);
 
 // Two- and four-lane dispatch, defined in rollout_multilane.hip.
 hipError_t launch_rollout_multi(const RolloutArgs &a, int lanes, int block, bool chunk,

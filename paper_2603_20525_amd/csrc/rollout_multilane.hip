@@ -1,5 +1,5 @@
 // Two- and four-lane instantiations of the rollout kernels (see
-// rollout_kernels.h). Built with the max-ILP instruction scheduler.
+// rollout_kernels.h).
 #include "rollout_kernels.h"
 
 namespace plan {
