@@ -60,9 +60,9 @@ ALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
 TRAFFIC_COUNTERS = {
     # fused kernel, one lane per candidate (c5) and four lanes (c2), 256-thread
     # workgroups, no costmap, cell-coefficient terrain; copy calibration
-    # 262144 KiB read as 131084.62 KiB (x1.99981) and written as 262144.0 KiB (x1.0)
-    "c5": (60620.29, 273.69, 262144.0 / 131084.62, 1.0, "3e97f0ca672e0117"),
-    "c2": (3313.32, 20.91, 262144.0 / 131084.62, 1.0, "3e97f0ca672e0117"),
+    # 262144 KiB read as 131084.54 KiB (x1.99981) and written as 262144.0 KiB (x1.0)
+    "c5": (60620.54, 273.69, 262144.0 / 131084.54, 1.0, "69ddd8a1d74f33cd"),
+    "c2": (3312.91, 20.91, 262144.0 / 131084.54, 1.0, "69ddd8a1d74f33cd"),
 }
 ROLLOUT_SOURCES = ("rollout_step.h", "rollout_kernels.h", "rollout.hip", "rollout_onelane_1wave.hip",
                    "rollout_multilane.hip", "plan_internal.h", "select_common.h", "sample.h")

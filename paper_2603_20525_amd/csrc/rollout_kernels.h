@@ -113,8 +113,10 @@ __device__ __forceinline__ float simulate(const RolloutArgs &a, int k, int sub, 
             }
             const float dd = clampf_nan(u0, -a.drate_max, a.drate_max);
             const float ax = a.accel_max * clampf_nan(u1, -1.0f, 1.0f);
+            // goal test at the node, written as in the other loop so that a
+            // NaN position (never at the goal) keeps stepping there as here
             const float gdx = st[0] - a.goal_x, gdy = st[1] - a.goal_y;
-            if (fmaf(gdx, gdx, gdy * gdy) > a.goal_r2) {
+            if (!(fmaf(gdx, gdx, gdy * gdy) <= a.goal_r2)) {
                 if constexpr (SAMPLED) {
                     euler_step_ahead<LANES, CM>(a, arms, st, J, dd, ax, cur, nxt);
                 } else {

@@ -363,6 +363,24 @@ def test_non_finite_candidates_score_infinity(c1):
     assert_rollout_parity(J, fs, Jo, fso, "non-finite")
 
 
+def test_non_finite_candidates_agree_bitwise_over_launch_shapes(c1):
+    """A candidate whose state turns NaN keeps stepping in every kernel form
+    (its position is never at the goal), so its final state, NaN entries
+    included, and its +inf cost are the same bits at every launch shape."""
+    u = c1.w.controls.copy()
+    u[10, 0, 3] = np.nan
+    u[4, 1, 40] = np.nan
+    ref = c1.gpu(controls=u, lanes=1, block=64)
+    assert math.isinf(ref[0][3]) and math.isinf(ref[0][40])
+    assert np.isnan(ref[1][:, 3]).any()
+    for lanes, block in SHAPES[1:]:
+        J, fs, _ = c1.gpu(controls=u, lanes=lanes, block=block)
+        np.testing.assert_array_equal(J, ref[0], err_msg=f"lanes={lanes} block={block}")
+        np.testing.assert_array_equal(fs, ref[1], err_msg=f"lanes={lanes} block={block}")
+    c1.planner.set_launch(0, 0)
+    print(f"non-finite candidates: {len(SHAPES)} launch shapes bitwise equal")
+
+
 # ----------------------------------------------------------------- select
 
 def _select_case(K, N=20, seed=0):
