@@ -274,6 +274,37 @@ def test_costmap_obstacles_parity():
     _horizon(case, label="costmap", min_cost=0.99, min_state=0.95)
 
 
+def test_costmap_launch_shapes_agree_bitwise():
+    """With a costmap that obstacles actually hit, every launch shape (the
+    one-lane request-ahead kernels with their cost channel included) gives
+    the same bits as the one-lane launch, for the plain and one-launch paths."""
+    w = inputs.c1(K=512, N=30)
+    T = w.terrain
+    cm = oracle.costmap_polygons(inputs.obstacle_polygons(T, seed=77, count=8), T.W, T.H, T.x0,
+                                 T.y0, T.res, 1.0e6, 0.25).astype(np.float32)
+    case = Case(w, costmap=cm)
+    ud = dev(w.controls)
+    out = {}
+    for lanes, block in SHAPES:
+        J, fs, _ = case.gpu(lanes=lanes, block=block)
+        J1 = torch.empty(w.K, device="cuda")
+        plan = torch.empty(w.N, 2, device="cuda")
+        k, jb = case.planner.rollout_argmin(w.state0, ud, J1, plan)
+        torch.cuda.synchronize()
+        out[(lanes, block)] = (J, fs, J1.cpu().numpy(), plan.cpu().numpy(), k, jb)
+    case.planner.set_launch(0, 0)
+    ref = out[SHAPES[0]]
+    assert (ref[0] > 1e3).sum() > 10  # obstacles are actually hit
+    for shape, got in out.items():
+        for i, (a, b) in enumerate(zip(got, ref)):
+            if isinstance(a, np.ndarray):
+                np.testing.assert_array_equal(a, b, err_msg=f"{shape} output {i}")
+            else:
+                assert a == b, (shape, i, a, b)
+    print(f"costmap: {len(SHAPES)} launch shapes bitwise equal, "
+          f"{int((ref[0] > 1e3).sum())} of {w.K} candidates with a cost above 1e3")
+
+
 def test_goal_exit_parity():
     w = inputs.c1(K=512)
     w.cost["goal_x"], w.cost["goal_y"] = 12.0, 12.8
