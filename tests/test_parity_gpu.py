@@ -261,7 +261,11 @@ def test_paper_step_map_at_5ms():
     print(f"paper 5 ms step map (400 steps): state {ws:.3g}, cost {wc:.3g}")
 
 
-def test_costmap_obstacles_parity():
+@pytest.mark.parametrize("lanes,block", [(0, 0), (1, 256)])
+def test_costmap_obstacles_parity(lanes, block):
+    """Obstacles and a path boundary as a costmap, against the oracle: the
+    step map and the whole horizon, at the automatic launch (four lanes) and
+    at one lane (the request-ahead kernels with their cost channel)."""
     w = inputs.c1(K=512)
     T = w.terrain
     cm = oracle.costmap_polygons(inputs.obstacle_polygons(T, seed=77, count=8), T.W, T.H, T.x0,
@@ -269,9 +273,12 @@ def test_costmap_obstacles_parity():
     case = Case(w, costmap=cm)
     Jo, _, _ = case.oracle()
     assert (Jo > 1e3).sum() > 10  # obstacles are actually hit
+    case.planner.set_launch(lanes, block)
     assert_step_map_parity(case.planner, case.o, w.controls, dev(w.controls), w.state0, 1,
-                           label="costmap step map")
-    _horizon(case, label="costmap", min_cost=0.99, min_state=0.95)
+                           label=f"costmap step map lanes={lanes}")
+    _horizon(case, lanes=lanes, block=block, label=f"costmap lanes={lanes}", min_cost=0.99,
+             min_state=0.95)
+    case.planner.set_launch(0, 0)
 
 
 def test_costmap_launch_shapes_agree_bitwise():
