@@ -312,11 +312,16 @@ def test_costmap_launch_shapes_agree_bitwise():
           f"{int((ref[0] > 1e3).sum())} of {w.K} candidates with a cost above 1e3")
 
 
-def test_goal_exit_parity():
+@pytest.mark.parametrize("lanes,block", [(0, 0), (1, 256)])
+def test_goal_exit_parity(lanes, block):
+    """Candidates that reach the goal freeze there, against the oracle, at
+    the automatic launch and at one lane (the request-ahead kernel skips a
+    frozen candidate's steps and requests)."""
     w = inputs.c1(K=512)
     w.cost["goal_x"], w.cost["goal_y"] = 12.0, 12.8
     case = Case(w)
-    J, fs, _ = case.gpu()
+    J, fs, _ = case.gpu(lanes=lanes, block=block)
+    case.planner.set_launch(0, 0)
     Jo, fso, ex = case.oracle()
     assert (ex >= 0).mean() > 0.5
     # a candidate may cross the goal circle within FP32 rounding of a node:
@@ -327,7 +332,9 @@ def test_goal_exit_parity():
     marginal = (np.abs(d_g - rg) < 1e-3) | (np.abs(d_o - rg) < 1e-3)
     ok = ~marginal
     assert marginal.mean() < 0.05
-    assert_rollout_parity(J[ok], fs[:, ok], Jo[ok], fso[:, ok], "goal exit")
+    assert_rollout_parity(J[ok], fs[:, ok], Jo[ok], fso[:, ok], f"goal exit lanes={lanes}")
+    print(f"goal exit lanes={lanes}: {int((ex >= 0).sum())} of {w.K} candidates reach the goal, "
+          f"{int(marginal.sum())} marginal")
 
 
 def test_nonsquare_terrain_and_leaving_the_map():
