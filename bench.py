@@ -64,8 +64,9 @@ TRAFFIC_COUNTERS = {
     "c5": (60620.54, 273.69, 262144.0 / 131084.54, 1.0, "69ddd8a1d74f33cd"),
     "c2": (3312.91, 20.91, 262144.0 / 131084.54, 1.0, "69ddd8a1d74f33cd"),
 }
-ROLLOUT_SOURCES = ("rollout_step.h", "rollout_kernels.h", "rollout.hip", "rollout_onelane_1wave.hip",
-                   "rollout_multilane.hip", "plan_internal.h", "select_common.h", "sample.h")
+ROLLOUT_SOURCES = ("rollout_step.h", "rollout_kernels.h", "rollout.hip",
+                   "rollout_onelane_1wave.hip", "rollout_multilane.hip", "plan_internal.h",
+                   "select_common.h", "sample.h")
 
 
 def kernel_signature():
